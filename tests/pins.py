@@ -1,0 +1,457 @@
+"""Pins of the FP64 oracle to facts fixed by the paper and by mathematics.
+
+Each ``pin_*`` function takes a loaded oracle library (``oracle.load(path)``)
+and raises AssertionError when the oracle disagrees with:
+
+* closed forms: the pinhole projection a pinhole ray image must reproduce,
+  the angle to the nearest border ray, the analytic derivative of pinhole
+  rays, the pinhole projection Jacobian (Supp. A, projection Jacobian);
+* special cases: identity pairs, planted descriptors, exact-threshold gates;
+* invariants: depth independence of rays for a central camera (Sec. 3.1),
+  orthogonality of the backward to the radial direction (Supp. A, Eq. norm_jac);
+* brute force: exhaustive scans of the ray error on tiny generic cameras;
+* the paper's convergence statement (Sec. 3.2: almost all valid pixels within
+  10 iterations);
+* finite differences of the loss through the forward, and autograd through an
+  independent unrolled statement of the solver.
+
+``test_oracle_pins.py`` runs them on the oracle; ``test_oracle_mutants.py``
+runs them on deliberately broken copies of the oracle to show each plausible
+mistake is caught.
+"""
+from __future__ import annotations
+
+import functools
+import math
+
+import numpy as np
+
+import oracle
+import synth
+
+
+def fwd(lib, Xii, Xji, Dii=None, Dji=None, Qii=None, Qji=None, p_init=None, **kw):
+    H, W = Xii.shape[:2]
+    if Dii is None:
+        Dii = np.ones((H, W, 1))
+        Dji = np.ones((H, W, 1))
+    args = dict(oracle.DEFAULTS)
+    args.update(kw)
+    args.setdefault("nthreads", 1)
+    return oracle.match_fwd(Xii, Xji, Dii, Dji, Qii, Qji, p_init, lib=lib, **args)
+
+
+def pinhole_rays(H, W, f=None):
+    f0, cx, cy = synth.camera(H, W)
+    f = f0 if f is None else f
+    xs, ys = synth.pixel_grid(H, W)
+    return np.stack([(xs - cx) / f, (ys - cy) / f, np.ones_like(xs)], -1), f, cx, cy
+
+
+@functools.lru_cache(maxsize=None)
+def _pair(H, W, seed, conf=True):
+    return synth.make_pair(H, W, seed, conf=conf)
+
+
+# ---------------------------------------------------------------- forward pins
+
+def pin_identity(lib):
+    """X^j_i = X^i_i, D^j_i = D^i_i: every pixel returns to itself (identity init)."""
+    for (H, W) in [(48, 64), (7, 13)]:
+        p = synth.identity_pair(H, W, seed=11)
+        o = fwd(lib, p.Xii, p.Xji, p.Dii, p.Dji)
+        xs, ys = synth.pixel_grid(H, W)
+        assert np.abs(o["p"][..., 0] - xs).max() <= 1e-12, "identity: p_x"
+        assert np.abs(o["p"][..., 1] - ys).max() <= 1e-12, "identity: p_y"
+        assert o["theta"].max() <= 1e-7, "identity: theta"
+        assert (o["idx"] == np.arange(H * W).reshape(H, W)).all(), "identity: idx"
+        assert o["valid"].all(), "identity: valid"
+        # xhat is X^i_i sampled at p* = the pixel itself.
+        assert np.abs(o["xhat"] - p.Xii).max() <= 1e-12, "identity: xhat"
+
+
+def _interior_true_match(pair, margin):
+    pr = pair.proj
+    return ((pr[..., 0] >= margin) & (pr[..., 0] <= pair.W - 1 - margin)
+            & (pr[..., 1] >= margin) & (pr[..., 1] <= pair.H - 1 - margin))
+
+
+def pin_pinhole(lib):
+    """A pinhole ray image: the converged match is the pinhole projection of the query.
+
+    The oracle differs from the projection only by the bilinear interpolation
+    of the ray image, which shrinks with resolution (1e-2 px at 64x48 and
+    2e-3 px at 160x120 bound it); queries whose projection is within 1 px of
+    the border are left out because they can converge onto the clamped edge.
+    """
+    for (H, W, tol, seed) in [(48, 64, 1e-2, 1001), (120, 160, 2e-3, 77)]:
+        pair = _pair(H, W, seed, False)
+        o = fwd(lib, pair.Xii, pair.Xji)
+        m = _interior_true_match(pair, 1.0)
+        assert m.mean() > 0.5
+        err = np.abs(o["p"] - pair.proj)[m]
+        assert err.max() <= tol, "pinhole: max |p* - pi(x)| = %g" % err.max()
+        assert o["valid"][m].all(), "pinhole: interior matches must be valid"
+        assert o["theta"][m].max() <= 1e-12, "pinhole: zero residual"
+
+
+def pin_brute_force(lib):
+    """Tiny generic central cameras with radial distortion: for queries inside the
+    field of view, LM reaches the global minimiser of the ray error found by an
+    exhaustive scan (1/8 px, then 1/128 px around the best cell).  Queries whose
+    rays lie outside the field of view have no zero-residual match and must be
+    invalid."""
+    for (H, W, seed) in [(9, 12, 5), (12, 16, 6)]:
+        Xii = synth.distorted_camera_pointmap(H, W, seed)
+        rng = np.random.Generator(np.random.PCG64(seed))
+        n_in, n_out = 14, 4
+        # In-FOV query rays: the camera's rays through random fractional pixels.
+        fx = rng.uniform(0.5, W - 1.5, n_in)
+        fy = rng.uniform(0.5, H - 1.5, n_in)
+        rays_in = synth.distorted_camera_rays(H, W, fx, fy)
+        # Out-of-FOV rays: beyond a random border by 1.5 - 3 px.
+        side = rng.integers(0, 4, n_out)
+        ox = np.where(side == 0, -rng.uniform(1.5, 3, n_out), np.where(side == 1, W - 1 + rng.uniform(1.5, 3, n_out), rng.uniform(0, W - 1, n_out)))
+        oy = np.where(side == 2, -rng.uniform(1.5, 3, n_out), np.where(side == 3, H - 1 + rng.uniform(1.5, 3, n_out), rng.uniform(0, H - 1, n_out)))
+        rays_out = synth.distorted_camera_rays(H, W, ox, oy)
+        pts = np.concatenate([rays_in, rays_out]) * rng.uniform(0.5, 3.0, n_in + n_out)[:, None]
+        n_q = n_in + n_out
+        flat = rng.choice(H * W, size=n_q, replace=False)
+        qy, qx = flat // W, flat % W
+        Xji = np.tile(np.array([0.0, 0.0, 1.0]), (H, W, 1))
+        Xji[qy, qx] = pts
+        o = fwd(lib, Xii, Xji)
+        gx = np.arange(0, (W - 1) * 8 + 1) / 8.0
+        gy = np.arange(0, (H - 1) * 8 + 1) / 8.0
+        GX, GY = np.meshgrid(gx, gy)
+        for k in range(n_q):
+            lm_p = o["p"][qy[k], qx[k]]
+            if k >= n_in:
+                assert not o["valid"][qy[k], qx[k]], "brute force: out-of-FOV query must be invalid"
+                continue
+            c = oracle.cost_grid(Xii, pts[k], GX, GY, lib=lib)
+            j = np.unravel_index(np.argmin(c), c.shape)
+            bx, by = GX[j], GY[j]
+            fxs = np.clip(bx + np.arange(-32, 33) / 128.0, 0, W - 1)
+            fys = np.clip(by + np.arange(-32, 33) / 128.0, 0, H - 1)
+            FX, FY = np.meshgrid(fxs, fys)
+            cf = oracle.cost_grid(Xii, pts[k], FX, FY, lib=lib)
+            jf = np.unravel_index(np.argmin(cf), cf.shape)
+            best = cf[jf]
+            lm_c = oracle.cost_grid(Xii, pts[k], lm_p[:1], lm_p[1:], lib=lib)[0]
+            assert lm_c <= best + 1e-12, "brute force: LM cost %g above scan %g" % (lm_c, best)
+            assert np.abs(lm_p - [FX[jf], FY[jf]]).max() <= 2.0 / 128, "brute force: location"
+            assert o["valid"][qy[k], qx[k]], "brute force: in-FOV query must be valid"
+
+
+def pin_depth_invariance(lib):
+    """Rays do not depend on depth (Sec. 3.1): scaling any point by 2^k changes nothing."""
+    pair = _pair(48, 64, 1001)
+    rng = np.random.Generator(np.random.PCG64(3))
+    si = 2.0 ** rng.integers(-3, 4, size=(pair.H, pair.W, 1))
+    sj = 2.0 ** rng.integers(-3, 4, size=(pair.H, pair.W, 1))
+    a = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji)
+    b = fwd(lib, pair.Xii * si, pair.Xji * sj, pair.Dii, pair.Dji, pair.Qii, pair.Qji)
+    for k in ("p", "idx", "valid", "theta"):
+        assert np.array_equal(a[k], b[k]), "depth invariance: %s" % k
+
+
+def pin_border_angle(lib):
+    """Queries outside the FOV converge to the nearest border ray; the residual angle
+    equals the closed-form angle between the query ray and that border ray (Eq. 3)."""
+    for (H, W, axis) in [(31, 40, 0), (40, 31, 1)]:
+        R, f, cx, cy = pinhole_rays(H, W)
+        Xii = R * 2.0
+        angles = [1e-3, 3e-2, 0.3, 0.7]
+        Xji = np.tile(np.array([0.0, 0.0, 1.0]), (H, W, 1))
+        ub = ((W - 1) - cx) / f if axis == 0 else ((H - 1) - cy) / f
+        queries = []
+        for k, ang in enumerate(angles):
+            uq = math.tan(math.atan(ub) + ang)
+            vec = np.array([uq, 0.0, 1.0]) if axis == 0 else np.array([0.0, uq, 1.0])
+            qy, qx = 2 + k, 3
+            Xji[qy, qx] = vec * 1.7
+            queries.append((qy, qx, ang))
+        # Far outside the FOV the clamped iterations creep along the border, so
+        # this pin (about the angle, not the speed) gives them 100 iterations.
+        o = fwd(lib, Xii, Xji, K=100)
+        for qy, qx, ang in queries:
+            th = o["theta"][qy, qx]
+            assert abs(th - ang) <= 1e-9 * max(1.0, ang), "border angle: %g vs %g" % (th, ang)
+            # Eq. 3: |psi1 - psi2|^2 = 2 (1 - cos theta) with the border ray.
+            pb = o["p"][qy, qx]
+            expect_edge = (W - 1) if axis == 0 else (H - 1)
+            assert abs(pb[axis] - expect_edge) <= 1e-12, "border angle: match not on the border"
+
+
+def pin_gradient_images(lib):
+    """Central-difference gradient images of a pinhole ray image match the analytic
+    derivative of the pinhole ray (Sec. 3.1 rays) up to O(1/f^2) truncation."""
+    H, W = 30, 44
+    R, f, cx, cy = pinhole_rays(H, W)
+    Rn, Gx, Gy = oracle.ray_images(R * 3.0, lib=lib)
+    n = np.linalg.norm(R, axis=-1, keepdims=True)
+    psi = R / n
+    ex = np.array([1.0 / f, 0, 0])
+    ey = np.array([0, 1.0 / f, 0])
+    ax = (ex - psi * (psi @ ex)[..., None]) / n
+    ay = (ey - psi * (psi @ ey)[..., None]) / n
+    sl = (slice(1, H - 1), slice(1, W - 1))
+    assert np.abs(Rn - psi).max() <= 1e-15, "ray image"
+    scale = np.abs(ax[sl]).max()
+    assert np.abs(Gx[sl] - ax[sl]).max() <= 2.0 / f ** 2 * scale, "Gx"
+    assert np.abs(Gy[sl] - ay[sl]).max() <= 2.0 / f ** 2 * scale, "Gy"
+    # One-sided at the border: forward difference of the first two columns/rows.
+    assert np.allclose(Gx[:, 0], Rn[:, 1] - Rn[:, 0], rtol=0, atol=1e-15), "Gx border"
+    assert np.allclose(Gy[-1], Rn[-1] - Rn[-2], rtol=0, atol=1e-15), "Gy border"
+
+
+def pin_convergence(lib):
+    """Sec. 3.2: LM converges for almost all valid pixels within 10 iterations.
+    The 10th step moves at most 1e-6 px for >= 99.9 % of valid pixels at 512x384."""
+    pair = _pair(384, 512, 2000)
+    a = fwd(lib, pair.Xii, pair.Xji, K=9, nthreads=0)
+    b = fwd(lib, pair.Xii, pair.Xji, K=10, nthreads=0)
+    m = b["valid"] & _interior_true_match(pair, 1.0)
+    step = np.abs(b["p"] - a["p"]).max(-1)[m]
+    assert (step <= 1e-6).mean() >= 0.999, "convergence: %g" % (step <= 1e-6).mean()
+    assert m.mean() > 0.5
+
+
+def pin_refine_planted(lib):
+    """Feature refine (Sec. 3.2): a query descriptor planted equal to the descriptor of
+    a pixel inside the window selects that pixel, including at the window's corners
+    and where the window is clipped by the image border."""
+    pair = _pair(48, 64, 1001, False)
+    base = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji)
+    r = 3
+    Dji = pair.Dji.astype(np.float64).copy()
+    rng = np.random.Generator(np.random.PCG64(9))
+    H, W = pair.H, pair.W
+    m0 = np.floor(base["p"] + 0.5).astype(int)
+    want = {}
+    offsets = [(-r, -r), (r, r), (-r, r), (r, -r), (0, 0), (1, -2)]
+    ys, xs = np.nonzero(base["valid"])
+    pick = rng.choice(len(ys), size=60, replace=False)
+    for k, j in enumerate(pick):
+        y, x = ys[j], xs[j]
+        dx, dy = offsets[k % len(offsets)]
+        mx, my = m0[y, x, 0] + dx, m0[y, x, 1] + dy
+        if not (0 <= mx < W and 0 <= my < H):
+            continue
+        Dji[y, x] = pair.Dii[my, mx]
+        want[(y, x)] = my * W + mx
+    o = fwd(lib, pair.Xii, pair.Xji, pair.Dii, Dji, r=r)
+    assert len(want) > 20
+    for (y, x), m in want.items():
+        assert o["idx"][y, x] == m, "planted refine at (%d,%d): %d vs %d" % (y, x, o["idx"][y, x], m)
+    # r = 0: the refined match is p* rounded half up.
+    o0 = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji, r=0)
+    assert (o0["idx"] == m0[..., 1] * W + m0[..., 0]).all(), "r = 0"
+
+
+def pin_refine_ties(lib):
+    """Equal scores: the first maximum in row-major window order wins."""
+    pair = _pair(48, 64, 1001, False)
+    H, W = pair.H, pair.W
+    Dc = np.ones((H, W, 4)) / 2.0
+    o = fwd(lib, pair.Xii, pair.Xji, Dc, Dc, r=2)
+    m0 = np.floor(o["p"] + 0.5).astype(int)
+    fx = np.maximum(m0[..., 0] - 2, 0)
+    fy = np.maximum(m0[..., 1] - 2, 0)
+    assert (o["idx"] == fy * W + fx).all(), "ties: first in row-major order"
+    assert (o["gap"] == 0).all(), "ties: zero gap"
+
+
+def pin_conf_gate(lib):
+    """Match confidence q = sqrt(Q^i_i[m] Q^j_i[n]) (Sec. 3.3) gated at q >= q_min,
+    with m the refined match (not the query pixel): exact-threshold cases on a
+    warped pair, where m and n differ."""
+    pair = _pair(48, 64, 1001, False)
+    H, W = pair.H, pair.W
+    base = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji)
+    rng = np.random.Generator(np.random.PCG64(5))
+    Qi = rng.choice([0.5, 1.0, 2.0, 4.0], size=(H, W))
+    idx = np.where(base["idx"] >= 0, base["idx"], 0)
+    assert (idx != np.arange(H * W).reshape(H, W))[base["valid"]].mean() > 0.5
+    # Q^j_i chosen so that q is exactly 1.5 (passes) or just below (fails).
+    below = rng.uniform(size=(H, W)) < 0.5
+    target = np.where(below, 2.25 * (1 - 1e-9), 2.25)
+    Qj = target / Qi.reshape(-1)[idx]
+    o = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji, Qi, Qj, conf_min=1.5)
+    assert np.array_equal(o["idx"], base["idx"]), "the gate must not change the match"
+    assert np.array_equal(o["valid"], base["valid"] & ~below), "confidence gate"
+
+
+def pin_dist_gate(lib):
+    """3D distance gate (Sec. 3.2): same rays at 1.5x depth match pixel-to-pixel with
+    distance 0.5 |X^i_i|; the gate keeps exactly those within max_dist."""
+    p = synth.identity_pair(24, 32, seed=4)
+    Xj = p.Xii.astype(np.float64) * 1.5
+    dist = 0.5 * np.linalg.norm(p.Xii.astype(np.float64), axis=-1)
+    thr = float(np.median(dist))
+    o = fwd(lib, p.Xii, Xj, p.Dii, p.Dji, max_dist=thr)
+    assert np.array_equal(o["valid"], dist <= thr), "distance gate"
+    o = fwd(lib, p.Xii, Xj, p.Dii, p.Dji)
+    assert o["valid"].all(), "distance gate off by default"
+
+
+def pin_theta_gate(lib):
+    """Residual-angle gate: matches with theta above max_theta are invalid."""
+    pair = _pair(48, 64, 1001, False)
+    o = fwd(lib, pair.Xii, pair.Xji, max_theta=math.inf)
+    o2 = fwd(lib, pair.Xii, pair.Xji, max_theta=1e-4)
+    assert o["valid"].all()
+    assert np.array_equal(o2["valid"], o["theta"] <= 1e-4)
+    outside = ~_interior_true_match(pair, -0.5)
+    assert not o2["valid"][outside].any(), "queries beyond the FOV must be invalid"
+
+
+def pin_bad_inputs(lib):
+    """Non-finite or zero query points and non-finite initial pixels give invalid
+    matches; bad reference pixels do not poison matches elsewhere."""
+    pair = _pair(24, 32, 42, False)
+    Xj = pair.Xji.astype(np.float64).copy()
+    Xj[0, 0] = [np.nan, 0, 1]
+    Xj[1, 1] = [0, 0, 0]
+    Xj[2, 2] = [np.inf, 1, 1]
+    Xi = pair.Xii.astype(np.float64).copy()
+    Xi[20, 30] = [np.nan, np.nan, np.nan]
+    pinit = np.stack(synth.pixel_grid(24, 32), -1).astype(np.float64)
+    pinit[3, 3] = [np.nan, 1.0]
+    o = fwd(lib, Xi, Xj, p_init=pinit)
+    for (y, x) in [(0, 0), (1, 1), (2, 2), (3, 3)]:
+        assert o["idx"][y, x] == -1 and not o["valid"][y, x] and o["theta"][y, x] == np.inf
+    ref = fwd(lib, pair.Xii, pair.Xji)
+    far = np.ones((24, 32), bool)
+    far[14:, 22:] = False
+    far[:4, :4] = False
+    assert np.array_equal(o["p"][far], ref["p"][far]), "bad reference pixel leaked"
+    assert np.isfinite(o["p"]).all()
+
+
+def pin_p_init(lib):
+    """Initialisation from given pixels (Sec. 3.2, tracking): starting at the pinhole
+    projection, or a few pixels away from it, converges to the same match."""
+    pair = _pair(48, 64, 1001, False)
+    ref = fwd(lib, pair.Xii, pair.Xji)
+    m = ref["valid"] & _interior_true_match(pair, 1.0)
+    o1 = fwd(lib, pair.Xii, pair.Xji, p_init=pair.proj)
+    o2 = fwd(lib, pair.Xii, pair.Xji, p_init=pair.proj + 2.5)
+    assert np.abs(o1["p"] - ref["p"])[m].max() <= 1e-9
+    assert np.abs(o2["p"] - ref["p"])[m].max() <= 1e-9
+
+
+# --------------------------------------------------------------- backward pins
+
+def _fd_setup(lib, K=20):
+    pair = _pair(24, 32, 5000)
+    o = fwd(lib, pair.Xii, pair.Xji, K=K)
+    frac = o["p"] - np.floor(o["p"])
+    near_edge = ((frac < 1e-5) | (frac > 1 - 1e-5)).any(-1)
+    mask = o["valid"] & ~near_edge
+    return pair, o, mask
+
+
+def _loss(lib, Xii, Xji, mask, K=20):
+    o = fwd(lib, Xii, Xji, K=K)
+    d = o["xhat"] - Xji
+    return float((d * d).sum(-1)[mask].sum())
+
+
+def _adjoint_total(lib, pair, o, mask):
+    Xi = pair.Xii.astype(np.float64)
+    Xj = pair.Xji.astype(np.float64)
+    gx = 2.0 * (o["xhat"] - Xj) * mask[..., None]
+    dXi, dXj = oracle.match_bwd(Xi, Xj, o["p"], mask, None, gx, lib=lib)
+    return dXi, dXj - gx
+
+
+def pin_bwd_fd(lib):
+    """Implicit adjoint vs central finite differences (eps 1e-6, fp64, mask frozen,
+    queries within 1e-5 px of a bilinear cell edge left out) on a 32x24 pair."""
+    pair, o, mask = _fd_setup(lib)
+    gi, gj = _adjoint_total(lib, pair, o, mask)
+    Xi = pair.Xii.astype(np.float64)
+    Xj = pair.Xji.astype(np.float64)
+    rng = np.random.Generator(np.random.PCG64(8))
+    eps = 1e-6
+    for name, X, G in (("Xii", Xi, gi), ("Xji", Xj, gj)):
+        flat = rng.choice(X.size, size=120, replace=False)
+        # Always include the largest-gradient elements.
+        flat = np.unique(np.concatenate([flat, np.argsort(-np.abs(G).reshape(-1))[:30]]))
+        scale = np.abs(G).max()
+        for e in flat:
+            Xp = X.copy(); Xp.reshape(-1)[e] += eps
+            Xm = X.copy(); Xm.reshape(-1)[e] -= eps
+            if name == "Xii":
+                fd = (_loss(lib, Xp, Xj, mask) - _loss(lib, Xm, Xj, mask)) / (2 * eps)
+            else:
+                fd = (_loss(lib, Xi, Xp, mask) - _loss(lib, Xi, Xm, mask)) / (2 * eps)
+            g = G.reshape(-1)[e]
+            assert abs(fd - g) <= 1e-5 * max(abs(fd), 1e-2 * scale), \
+                "FD %s[%d]: fd %.10g adjoint %.10g" % (name, e, fd, g)
+
+
+def pin_bwd_unrolled(lib):
+    """Implicit adjoint vs torch fp64 autograd through the unrolled iterations of an
+    independent statement of the solver (20 iterations, converged)."""
+    import torch
+    from oracle import unrolled
+    pair, o, mask = _fd_setup(lib)
+    Xi = torch.tensor(pair.Xii, dtype=torch.float64, requires_grad=True)
+    Xj = torch.tensor(pair.Xji, dtype=torch.float64, requires_grad=True)
+    p, th, xh = unrolled.lm_project(Xi, Xj, K=20)
+    assert np.abs(p.detach().numpy().reshape(o["p"].shape) - o["p"]).max() <= 1e-9, "unrolled p*"
+    m = torch.tensor(mask.reshape(-1))
+    L = ((xh - Xj.reshape(-1, 3)) ** 2).sum(-1)[m].sum()
+    L.backward()
+    gi, gj = _adjoint_total(lib, pair, o, mask)
+    assert np.abs(gi - Xi.grad.numpy()).max() <= 1e-8 * np.abs(gi).max(), "unrolled dXii"
+    assert np.abs(gj - Xj.grad.numpy()).max() <= 1e-8 * np.abs(gj).max(), "unrolled dXji"
+
+
+def pin_bwd_orthogonal(lib):
+    """Through the ray map only (no xhat gradient) the adjoint is orthogonal to the
+    radial direction: N(X) = (I - u u^T)/|X| annihilates X (Supp. A, Eq. norm_jac)."""
+    pair, o, mask = _fd_setup(lib)
+    rng = np.random.Generator(np.random.PCG64(1))
+    gp = rng.normal(size=o["p"].shape)
+    Xi = pair.Xii.astype(np.float64)
+    Xj = pair.Xji.astype(np.float64)
+    dXi, dXj = oracle.match_bwd(Xi, Xj, o["p"], mask, gp, None, lib=lib)
+    rad_i = (dXi * Xi).sum(-1) / np.linalg.norm(Xi, axis=-1)
+    rad_j = (dXj * Xj).sum(-1) / np.linalg.norm(Xj, axis=-1)
+    assert np.abs(rad_i).max() <= 1e-12 * np.abs(dXi).max()
+    assert np.abs(rad_j).max() <= 1e-12 * np.abs(dXj).max()
+    assert (dXj[~mask] == 0).all(), "invalid queries contribute nothing"
+    assert np.abs(dXj[mask]).max() > 0
+
+
+def pin_bwd_projection_jacobian(lib):
+    """For a pinhole ray image, dp*/dx is the pinhole projection Jacobian
+    (f/z) [[1, 0, -x/z], [0, 1, -y/z]] (Supp. A, projection Jacobian), up to the
+    interpolation error of the ray image."""
+    pair = _pair(120, 160, 77, False)
+    o = fwd(lib, pair.Xii, pair.Xji)
+    m = o["valid"] & _interior_true_match(pair, 1.0)
+    f, cx, cy = synth.camera(pair.H, pair.W)
+    X = pair.Xji.astype(np.float64)
+    x, y, z = X[..., 0], X[..., 1], X[..., 2]
+    for comp in (0, 1):
+        gp = np.zeros(o["p"].shape)
+        gp[..., comp] = 1.0
+        _, dXj = oracle.match_bwd(pair.Xii, X, o["p"], m, gp, None, lib=lib)
+        want = np.zeros_like(X)
+        want[..., comp] = f / z
+        want[..., 2] = -f * (x if comp == 0 else y) / z ** 2
+        err = np.linalg.norm(dXj - want, axis=-1)[m] / np.linalg.norm(want, axis=-1)[m]
+        assert err.max() <= 5e-2, "projection Jacobian row %d: %g" % (comp, err.max())
+
+
+ALL_PINS = [
+    pin_identity, pin_pinhole, pin_brute_force, pin_depth_invariance, pin_border_angle,
+    pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
+    pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init,
+    pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian,
+]

@@ -1,0 +1,94 @@
+"""Planted mistakes in the oracle must fail at least one pin.
+
+Each mutant is a textual edit of ``oracle/m3s_oracle.c`` (a dropped term, a
+wrong sign or index, a transposed operand, a wrong tie-break...).  The edited
+copy is compiled to a temporary library on the CPU and the pin battery of
+``pins.py`` runs against it in a child process (so a mutant that crashes also
+counts as caught).  A mutant that survives every pin means the pins would not
+notice that mistake in the oracle.
+"""
+import concurrent.futures as cf
+import os
+import subprocess
+import sys
+
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "gradient_not_divided": [("/ (double)(xp - xm);", ";")],
+    "gy_uses_x_neighbours": [("(R[3 * ((long)yp * W + x) + c] - R[3 * ((long)ym * W + x) + c])",
+                              "(R[3 * ((long)y * W + xp) + c] - R[3 * ((long)y * W + xm) + c])")],
+    "step_sign": [("double dx = -(a11 * g0 - a01 * g1) / det;", "double dx = (a11 * g0 - a01 * g1) / det;")],
+    "no_renormalisation": [("double psi[3] = {r[0] / n, r[1] / n, r[2] / n};", "double psi[3] = {r[0], r[1], r[2]};")],
+    "lambda_grows_on_accept": [("lambda /= 10.0;", "lambda *= 10.0;")],
+    "accept_uphill": [("if (nxt.c < cur.c) {", "if (nxt.c > cur.c) {")],
+    "theta_is_chord": [("double th = 2.0 * asin(fmin(1.0, sqrt(cur.c) / 2.0));", "double th = sqrt(cur.c);")],
+    "window_short": [("for (int dy = -C->r; dy <= C->r; ++dy) {", "for (int dy = -C->r; dy < C->r; ++dy) {")],
+    "tie_takes_last": [("if (s > best) { second = best; best = s; best_m = m; }",
+                        "if (s >= best) { second = best; best = s; best_m = m; }")],
+    "refine_rounds_down": [("int mx0 = (int)floor(px + 0.5), my0 = (int)floor(py + 0.5);",
+                            "int mx0 = (int)floor(px), my0 = (int)floor(py);")],
+    "conf_gate_strict": [("sqrt(C->Qii[best_m] * C->Qji[n]) >= C->conf_min", "sqrt(C->Qii[best_m] * C->Qji[n]) > C->conf_min")],
+    "conf_gate_wrong_pixel": [("sqrt(C->Qii[best_m] * C->Qji[n])", "sqrt(C->Qii[n] * C->Qji[n])")],
+    "xhat_from_rays": [("bilerp3(C->Xii, &cl, C->xhat + 3 * n);", "bilerp3(C->rm.R, &cl, C->xhat + 3 * n);")],
+    "ray_image_not_normalised": [("R[3 * m + 0] = x[0] / n;", "R[3 * m + 0] = x[0];"),
+                                 ("R[3 * m + 1] = x[1] / n;", "R[3 * m + 1] = x[1];"),
+                                 ("R[3 * m + 2] = x[2] / n;", "R[3 * m + 2] = x[2];")],
+    "target_not_normalised": [("/* Target ray psi(x) (Sec. 3.1). */\n    double t[3] = {x[0] / xn, x[1] / xn, x[2] / xn};",
+                               "/* Target ray psi(x) (Sec. 3.1). */\n    double t[3] = {x[0], x[1], x[2]};")],
+    "identity_init_transposed": [("px0 = (double)(n % W);\n        py0 = (double)(n / W);",
+                                  "px0 = (double)(n / W);\n        py0 = (double)(n % W);")],
+    "bilinear_weights_swapped": [("w10 = c->a * (1 - c->b);", "w10 = (1 - c->a) * c->b;"),
+                                 ("double w01 = (1 - c->a) * c->b,", "double w01 = c->a * (1 - c->b),")],
+    "bwd_drops_direct_xhat_term": [("dXii[3 * cm[c] + k] += w[c] * gx[k];", "dXii[3 * cm[c] + k] += 0.0 * gx[k];")],
+    "bwd_query_sign": [("for (int k = 0; k < 3; ++k) dXji[3 * n + k] = out[k];",
+                        "for (int k = 0; k < 3; ++k) dXji[3 * n + k] = -out[k];")],
+    "bwd_one_row_derivative": [("drx[k] = (1 - b) * (R10[k] - R00[k]) + b * (R11[k] - R01[k]);",
+                                "drx[k] = (R10[k] - R00[k]);")],
+    "bwd_drops_ray_norm": [("dXii[3 * cm[c] + k] -= (w[c] / rn) * out[k];", "dXii[3 * cm[c] + k] -= w[c] * out[k];")],
+    "bwd_corner_weights_swapped": [("double w[4] = {(1 - a) * (1 - b), a * (1 - b), (1 - a) * b, a * b};",
+                                    "double w[4] = {(1 - a) * (1 - b), (1 - a) * b, a * (1 - b), a * b};")],
+    "bwd_xhat_derivative_transposed": [("gp0 += dxx * gx[k];\n                gp1 += dxy * gx[k];",
+                                        "gp0 += dxy * gx[k];\n                gp1 += dxx * gx[k];")],
+}
+
+_BATTERY = r"""
+import sys
+sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
+import oracle, pins
+lib = oracle.load(%(lib)r)
+for pin in pins.ALL_PINS:
+    try:
+        pin(lib)
+    except AssertionError as e:
+        print("CAUGHT by", pin.__name__, "-", str(e)[:120]); sys.exit(0)
+print("SURVIVED"); sys.exit(3)
+"""
+
+
+def _build_and_run(name, edits, tmpdir):
+    src = open(oracle._SRC).read()
+    for old, new in edits:
+        assert src.count(old) == 1, "mutant %s: snippet not found exactly once: %r" % (name, old)
+        src = src.replace(old, new)
+    cpath = os.path.join(tmpdir, name + ".c")
+    with open(cpath, "w") as f:
+        f.write(src)
+    lib = oracle.compile_oracle(cpath, os.path.join(tmpdir, "lib_" + name + ".so"))
+    code = _BATTERY % dict(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=lib)
+    env = dict(os.environ, OMP_NUM_THREADS="2")
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600, env=env)
+    return name, r.returncode, (r.stdout + r.stderr).strip()[-400:]
+
+
+def test_every_mutant_is_caught(tmp_path):
+    with cf.ThreadPoolExecutor(max_workers=4) as ex:
+        results = list(ex.map(lambda kv: _build_and_run(kv[0], kv[1], str(tmp_path)), MUTANTS.items()))
+    survived = [(n, out) for n, rc, out in results if rc == 3]
+    for n, rc, out in results:
+        print("%-32s rc=%d %s" % (n, rc, out.splitlines()[-1] if out else ""))
+    assert not survived, "mutants not caught by any pin: %s" % survived
