@@ -27,7 +27,9 @@
  * Readings where the paper is silent (they are listed with reasons in the
  * design notes of the repository):
  *   pixel (x, y) = (column, row), pixel centres at integers, domain
- *     [0, W-1] x [0, H-1]; every iterate is clamped to it;
+ *     [0, W-1] x [0, H-1]; every iterate is clamped to it, and a coordinate
+ *     sitting on its bound whose step points outward is held while the other
+ *     coordinate takes its own 1-D damped step;
  *   the ray image is sampled bilinearly (cell origin x0 = min(floor(x), W-2))
  *     and the sample renormalised to unit length;
  *   the LM Jacobian uses bilinear samples of central-difference gradient
@@ -231,6 +233,13 @@ static void match_one(const fwd_ctx *C, long n)
         double dx = -(a11 * g0 - a01 * g1) / det;
         double dy = -(a00 * g1 - a01 * g0) / det;
         if (!isfinite(dx) || !isfinite(dy)) { lambda *= 10.0; continue; }
+        /* Bounds: a coordinate on its bound whose step points out of the image
+           is held; the other coordinate takes its own 1-D damped step. */
+        int hold_x = (px <= 0.0 && dx < 0.0) || (px >= W - 1.0 && dx > 0.0);
+        int hold_y = (py <= 0.0 && dy < 0.0) || (py >= H - 1.0 && dy > 0.0);
+        if (hold_x && hold_y) { dx = 0.0; dy = 0.0; }
+        else if (hold_x) { dx = 0.0; dy = -g1 / a11; }
+        else if (hold_y) { dy = 0.0; dx = -g0 / a00; }
         double qx = clampd(px + dx, 0.0, W - 1.0), qy = clampd(py + dy, 0.0, H - 1.0);
         sample_ray_error(&C->rm, qx, qy, t, &nxt);
         if (nxt.c < cur.c) {

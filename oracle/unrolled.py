@@ -15,7 +15,8 @@ It follows the same readings as the C oracle: pixel centres at integers,
 bilinear sampling of the normalised ray image with renormalisation, the
 Jacobian from bilinear samples of central-difference gradient images, fixed K,
 Levenberg damping x10 / /10 with acceptance on strictly lower cost, clamping
-to the image domain.  Accept/reject decisions are taken on values and enter
+to the image domain with a coordinate held on its bound when its step points
+outward.  Accept/reject decisions are taken on values and enter
 autograd through ``torch.where``; floor() of the cell origin is piecewise
 constant.  Inputs are assumed finite with non-zero points.
 """
@@ -96,7 +97,16 @@ def lm_project(Xii: torch.Tensor, Xji: torch.Tensor, K: int = 10, lambda0: float
         g0 = (Jx * e).sum(-1)
         g1 = (Jy * e).sum(-1)
         det = a00 * a11 - a01 * a01
-        d = torch.stack([-(a11 * g0 - a01 * g1) / det, -(a00 * g1 - a01 * g0) / det], -1)
+        dx = -(a11 * g0 - a01 * g1) / det
+        dy = -(a00 * g1 - a01 * g0) / det
+        # Bounds: hold a coordinate on its bound whose step points outward; the
+        # other then takes its 1-D damped step.
+        hx = (((p[:, 0] <= 0) & (dx < 0)) | ((p[:, 0] >= W - 1) & (dx > 0))).detach()
+        hy = (((p[:, 1] <= 0) & (dy < 0)) | ((p[:, 1] >= H - 1) & (dy > 0))).detach()
+        zero = torch.zeros_like(dx)
+        dx, dy = (torch.where(hx, zero, torch.where(hy, -g0 / a00, dx)),
+                  torch.where(hy, zero, torch.where(hx, -g1 / a11, dy)))
+        d = torch.stack([dx, dy], -1)
         q = torch.minimum(torch.maximum(p + d, lo), hi)
         cq, eq, Jxq, Jyq = _sample(R, Gx, Gy, q, t)
         acc = (cq < c).detach()

@@ -172,9 +172,9 @@ def pin_border_angle(lib):
             qy, qx = 2 + k, 3
             Xji[qy, qx] = vec * 1.7
             queries.append((qy, qx, ang))
-        # Far outside the FOV the clamped iterations creep along the border, so
-        # this pin (about the angle, not the speed) gives them 100 iterations.
-        o = fwd(lib, Xii, Xji, K=100)
+        # The method's own 10 iterations: with the coordinate on the border held,
+        # the other one converges along the border.
+        o = fwd(lib, Xii, Xji, K=10)
         for qy, qx, ang in queries:
             th = o["theta"][qy, qx]
             assert abs(th - ang) <= 1e-9 * max(1.0, ang), "border angle: %g vs %g" % (th, ang)
@@ -402,7 +402,8 @@ def pin_bwd_unrolled(lib):
     Xi = torch.tensor(pair.Xii, dtype=torch.float64, requires_grad=True)
     Xj = torch.tensor(pair.Xji, dtype=torch.float64, requires_grad=True)
     p, th, xh = unrolled.lm_project(Xi, Xj, K=20)
-    assert np.abs(p.detach().numpy().reshape(o["p"].shape) - o["p"]).max() <= 1e-9, "unrolled p*"
+    dp = np.abs(p.detach().numpy().reshape(o["p"].shape) - o["p"]).max(-1)
+    assert dp[o["valid"]].max() <= 1e-9, "unrolled p*"
     m = torch.tensor(mask.reshape(-1))
     L = ((xh - Xj.reshape(-1, 3)) ** 2).sum(-1)[m].sum()
     L.backward()

@@ -26,6 +26,10 @@ MUTANTS = {
     "no_renormalisation": [("double psi[3] = {r[0] / n, r[1] / n, r[2] / n};", "double psi[3] = {r[0], r[1], r[2]};")],
     "lambda_grows_on_accept": [("lambda /= 10.0;", "lambda *= 10.0;")],
     "accept_uphill": [("if (nxt.c < cur.c) {", "if (nxt.c > cur.c) {")],
+    "bound_not_held": [("int hold_x = (px <= 0.0 && dx < 0.0) || (px >= W - 1.0 && dx > 0.0);", "int hold_x = 0;"),
+                       ("int hold_y = (py <= 0.0 && dy < 0.0) || (py >= H - 1.0 && dy > 0.0);", "int hold_y = 0;")],
+    "held_step_wrong_diagonal": [("else if (hold_x) { dx = 0.0; dy = -g1 / a11; }", "else if (hold_x) { dx = 0.0; dy = -g1 / a00; }"),
+                                 ("else if (hold_y) { dy = 0.0; dx = -g0 / a00; }", "else if (hold_y) { dy = 0.0; dx = -g0 / a11; }")],
     "theta_is_chord": [("double th = 2.0 * asin(fmin(1.0, sqrt(cur.c) / 2.0));", "double th = sqrt(cur.c);")],
     "window_short": [("for (int dy = -C->r; dy <= C->r; ++dy) {", "for (int dy = -C->r; dy < C->r; ++dy) {")],
     "tie_takes_last": [("if (s > best) { second = best; best = s; best_m = m; }",
