@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Benchmark of the gfx950 projective pointmap matcher (MASt3R-SLAM, Sec. 3.2).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+
+A step matches one 512x384 pair (196,608 query pixels, D = 24 descriptors,
+10 LM iterations, refine radius 3, confidences gated at 1.5) with
+m3s_match_fwd: ray-image prep plus the fused LM / refine / gate kernel.  Steps
+cycle through a pool of 8 distinct pairs (~380 MB of inputs, more than the
+256 MB Infinity Cache) so that inputs stream from HBM.  `value` is forward
+pixel matches per second over K timed steps (inputs resident in HBM).
+
+Further legs, reported in the same JSON line:
+  fwd_bwd        forward (with xhat) then the implicit-adjoint backward per pair;
+  batched        64 edges at 512x384 in one persistent hipGraph launch
+                 (autotuned) vs a loop of per-pair launches on the same GPU;
+  batched_uneven 96 edges of mixed resolution (512x384, 384x512, 512x288),
+                 K in 5..15 and r in 2..4 per edge, same comparison;
+  roofline       the forward kernel's algorithmic bytes over its average
+                 duration, timed live with hipEvents around each launch;
+  cpu_baseline   the FP64 oracle on the host cores, on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import synth  # noqa: E402
+
+METRIC = "pixel matches/sec (512x384 pair, 10 LM iters, r=3 refine); fwd+bwd matches/sec"
+HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per query of the forward path (D = 24, confidences on):
+# X^i_i 12 + X^j_i 12 + D^i_i 96 + D^j_i 96 + Q 8 + outputs p 8, idx 4, valid 1, theta 4.
+FWD_BYTES_PER_QUERY = 12 + 12 + 8 * 24 + 8 + 8 + 4 + 1 + 4
+# Backward per query: grad_p 8 + grad_xhat 12 + p 8 + valid 1 + X^j_i 12 + X^i_i 12
+# + dX^j_i 12 + dX^i_i 12 + its zero fill 12; forward with xhat adds 12.
+BWD_BYTES_PER_QUERY = 8 + 12 + 8 + 1 + 12 + 12 + 12 + 12 + 12
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+class PreparedPair:
+    """Device tensors and pre-built ctypes argument blocks of one pair."""
+
+    def __init__(self, m3s, lib, pair, device, want_xhat=False, K=None, r=None):
+        import torch
+        from paper_2412_12392_amd import _lib, match as M
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
+        self.H, self.W = pair.H, pair.W
+        self.t = dict(Xii=t(pair.Xii), Xji=t(pair.Xji), Dii=t(pair.Dii), Dji=t(pair.Dji), Qii=t(pair.Qii),
+                      Qji=t(pair.Qji))
+        self.res = M._alloc_outputs(pair.H, pair.W, device, True, want_xhat)
+        self.pair_c = M._pair(self.t["Xii"], self.t["Xji"], self.t["Dii"], self.t["Dji"],
+                                          self.t["Qii"], self.t["Qji"], None)
+        self.out_c = M._outputs(self.res)
+        self.prm = _lib.default_params(lib, max_iter=K if K is not None else pair.K,
+                                       refine_radius=r if r is not None else pair.r)
+        self.K, self.r = self.prm.max_iter, self.prm.refine_radius
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--pool", type=int, default=8, help="distinct 512x384 pairs cycled through")
+    ap.add_argument("--only-main", action="store_true", help="time only the single-pair forward leg")
+    ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain device copy of known size (for HBM counter scaling)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the edges of a keyframe graph "
+              "would shard across GPUs with no exchange in the forward); run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2412_12392_amd as m3s
+    from paper_2412_12392_amd import _lib
+    lib = m3s.load_library()
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    props = torch.cuda.get_device_properties(dev)
+    stream = torch.cuda.current_stream()
+    sp = stream.cuda_stream
+
+    # ------------------------------------------------------------ single pair
+    t0 = time.time()
+    pool_pairs = [synth.make_pair(384, 512, 2000 + k, K=10, r=3, conf=True) for k in range(args.pool)]
+    log("generated %d pairs in %.1fs" % (len(pool_pairs), time.time() - t0))
+    pool = [PreparedPair(m3s, lib, p, dev) for p in pool_pairs]
+    N = pool[0].H * pool[0].W
+    ws = torch.empty(lib.m3s_workspace_bytes(ctypes.byref(pool[0].pair_c), ctypes.byref(pool[0].prm)),
+                     dtype=torch.uint8, device=dev)
+    wsp, wsn = ws.data_ptr(), ws.numel()
+
+    def fwd_step(k):
+        P = pool[k % len(pool)]
+        st = lib.m3s_match_fwd(ctypes.byref(P.pair_c), ctypes.byref(P.prm), ctypes.byref(P.out_c), wsp, wsn, sp)
+        if st:
+            _lib.check(lib, "m3s_match_fwd", st)
+
+    for k in range(args.warmup):
+        fwd_step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        fwd_step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    value = N * args.steps / el
+    ms_per_step = el / args.steps * 1e3
+    log("fwd: %.3f ms/step, %.3e matches/s" % (ms_per_step, value))
+
+    # Same steps with hipEvents around each kernel: the forward kernel's own duration.
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    for k in range(args.steps):
+        fwd_step(k)
+    torch.cuda.synchronize()
+    lib.m3s_timing_enable(0)
+    kt = {}
+    for name in ("prep", "fwd"):
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        _lib.check(lib, "m3s_timing_read", lib.m3s_timing_read(name.encode(), ctypes.byref(tot), ctypes.byref(cnt)))
+        kt[name] = tot.value / max(cnt.value, 1)
+    alg_bytes = FWD_BYTES_PER_QUERY * N
+    achieved = alg_bytes / (kt["fwd"] * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "kernel": "fwd_kernel<32,8,24>", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "algorithmic_bytes_per_launch": alg_bytes,
+                "kernel_avg_us": round(kt["fwd"] * 1e3, 2), "prep_avg_us": round(kt["prep"] * 1e3, 2),
+                "path_achieved_GBs": round(alg_bytes / ((kt["fwd"] + kt["prep"]) * 1e-3) / 1e9, 1)}
+    log("kernel timing: fwd %.2f us, prep %.2f us" % (kt["fwd"] * 1e3, kt["prep"] * 1e3))
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "single pair 512x384 (W x H), D=24, K=10 LM iterations, r=3 refine, "
+                                  "confidences gated at 1.5, identity init",
+                      "queries_per_step": N, "pool_pairs": len(pool), "device": props.name,
+                      "gcn_arch": getattr(props, "gcnArchName", "")},
+           "roofline": roofline}
+
+    if not args.only_main:
+        out["fwd_bwd"] = fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
+        out["batched"] = batched_leg(m3s, lib, _lib, synth.batched_uniform, dev, args, "64 edges 512x384, K=10, r=3")
+        out["batched_uneven"] = batched_leg(m3s, lib, _lib, synth.batched_uneven, dev, args,
+                                            "96 edges: 40x 512x384, 32x 384x512, 24x 512x288; K 5..15, r 2..4")
+    if args.copy_calibration:
+        out["copy_calibration"] = copy_calibration(torch, dev)
+    if not args.skip_cpu:
+        out["cpu_baseline"] = cpu_baseline(pool_pairs[0], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
+    import torch
+    pool = [PreparedPair(m3s, lib, p, dev, want_xhat=True) for p in pool_pairs]
+    N = pool[0].H * pool[0].W
+    ws = torch.empty(lib.m3s_workspace_bytes(ctypes.byref(pool[0].pair_c), ctypes.byref(pool[0].prm)),
+                     dtype=torch.uint8, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(0)
+    grad_p = torch.randn((pool[0].H, pool[0].W, 2), generator=g).to(dev)
+    grad_x = torch.randn((pool[0].H, pool[0].W, 3), generator=g).to(dev)
+    gXi = torch.empty((pool[0].H, pool[0].W, 3), device=dev)
+    gXj = torch.empty_like(gXi)
+    bwd_pairs = [_lib.Pair(P.H, P.W, 0, P.t["Xii"].data_ptr(), P.t["Xji"].data_ptr(), 0, 0, 0, 0, 0) for P in pool]
+
+    def step(k):
+        P = pool[k % len(pool)]
+        st = lib.m3s_match_fwd(ctypes.byref(P.pair_c), ctypes.byref(P.prm), ctypes.byref(P.out_c), ws.data_ptr(),
+                               ws.numel(), sp)
+        _lib.check(lib, "m3s_match_fwd", st)
+        st = lib.m3s_match_bwd(ctypes.byref(bwd_pairs[k % len(pool)]), ctypes.byref(P.out_c), grad_p.data_ptr(),
+                               grad_x.data_ptr(), gXi.data_ptr(), gXj.data_ptr(), sp)
+        _lib.check(lib, "m3s_match_bwd", st)
+
+    for k in range(args.warmup):
+        step(k)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(k)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    for k in range(min(args.steps, 20)):
+        step(k)
+    torch.cuda.synchronize()
+    lib.m3s_timing_enable(0)
+    kt = {}
+    for name in ("prep", "fwd", "fill", "bwd"):
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        lib.m3s_timing_read(name.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+        kt[name + "_avg_us"] = round(tot.value / max(cnt.value, 1) * 1e3, 2)
+    bwd_us = kt["bwd_avg_us"] + kt["fill_avg_us"]
+    res = {"workload": "512x384 pair: forward with xhat, then backward (grad_p, grad_xhat)",
+           "matches_per_s": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5),
+           "kernels": kt,
+           "bwd_achieved_GBs": round(BWD_BYTES_PER_QUERY * N / (bwd_us * 1e-6) / 1e9, 1)}
+    log("fwd+bwd:", res)
+    return res
+
+
+def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
+    import torch
+    t0 = time.time()
+    pairs = make_pairs()
+    log("batched leg %s: %d edges generated in %.1fs" % (label, len(pairs), time.time() - t0))
+    edges = []
+    for p in pairs:
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        edges.append(m3s.EdgeInput(t(p.Xii), t(p.Xji), t(p.Dii), t(p.Dji), t(p.Qii), t(p.Qji), None, p.K, p.r))
+    queries = sum(p.H * p.W for p in pairs)
+    prm = m3s.params()
+    table, outs = m3s.make_edges(edges)
+    n = len(edges)
+    nbytes = lib.m3s_batched_workspace_bytes(table, n, ctypes.byref(prm))
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    flags = _lib.M3S_BATCH_GRAPH | _lib.M3S_BATCH_AUTOTUNE
+
+    def call():
+        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), flags, ws.data_ptr(), ws.numel(), s.cuda_stream)
+        _lib.check(lib, "m3s_match_batched", st)
+
+    steps = max(3, args.steps // 10)
+    with torch.cuda.stream(s):
+        for _ in range(max(2, args.warmup // 5)):
+            call()
+    s.synchronize()
+    grid, tile = m3s.last_batched_config()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            call()
+    s.synchronize()
+    el_b = (time.perf_counter() - t0) / steps
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    with torch.cuda.stream(s):
+        call()
+    s.synchronize()
+    lib.m3s_timing_enable(0)
+    tot, cnt = ctypes.c_double(), ctypes.c_int64()
+    lib.m3s_timing_read(b"batched_graph", ctypes.byref(tot), ctypes.byref(cnt))
+    graph_ms = tot.value / max(cnt.value, 1)
+
+    # Per-pair loop over the same edges on the same stream.
+    pw = torch.empty(max(lib.m3s_workspace_bytes(ctypes.byref(table[k].in_), ctypes.byref(prm)) for k in range(n)),
+                     dtype=torch.uint8, device=dev)
+    prms = [_lib.default_params(lib, max_iter=e.max_iter, refine_radius=e.refine_radius) for e in edges]
+
+    def loop():
+        for k in range(n):
+            st = lib.m3s_match_fwd(ctypes.byref(table[k].in_), ctypes.byref(prms[k]), ctypes.byref(table[k].out),
+                                   pw.data_ptr(), pw.numel(), s.cuda_stream)
+            _lib.check(lib, "m3s_match_fwd", st)
+
+    with torch.cuda.stream(s):
+        loop()
+    s.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            loop()
+    s.synchronize()
+    el_p = (time.perf_counter() - t0) / steps
+    res = {"workload": label, "edges": n, "queries": queries,
+           "batched_matches_per_s": round(queries / el_b, 1), "batched_ms": round(el_b * 1e3, 4),
+           "graph_launch_ms_events": round(graph_ms, 4),
+           "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
+           "speedup_vs_per_pair": round(el_p / el_b, 3), "launch": {"grid": grid, "tile_config": tile},
+           "algorithmic_GBs": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9, 1)}
+    log("batched:", res)
+    del ws, pw, outs, edges
+    torch.cuda.empty_cache()
+    return res
+
+
+def copy_calibration(torch, dev):
+    """A plain device copy of known size, for scaling HBM byte counters."""
+    n = 256 << 20
+    a = torch.empty(n // 4, dtype=torch.float32, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    return {"bytes_read": n, "bytes_written": n, "launches": 3}
+
+
+def cpu_baseline(pair, seconds):
+    """The FP64 oracle (OpenMP over queries) on the host cores, repeated on one
+    512x384 pair for about `seconds` seconds of wall time."""
+    import oracle
+    lib = oracle.load()
+    args = dict(oracle.DEFAULTS, K=pair.K, r=pair.r)
+    oracle.match_pair(pair)  # warm-up (thread pool)
+    calls = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.match_pair(pair)
+        calls += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    N = pair.H * pair.W
+    return {"value": round(N * calls / el, 1), "unit": "matches/s", "cores": oracle.max_threads(lib),
+            "kind": "oracle", "sample": "%d repeated forward passes over one 512x384 pair (%d queries each), "
+                                        "%.1f s, fp64 C with OpenMP over queries" % (calls, N, el),
+            "host_cpus": os.cpu_count()}
+
+
+if __name__ == "__main__":
+    main()

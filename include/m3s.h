@@ -1,0 +1,216 @@
+/*
+ * m3s.h -- C ABI of the MI355X (gfx950) projective pointmap matcher.
+ *
+ * The library implements the pointmap matching of MASt3R-SLAM (Murai,
+ * Dexheimer, Davison, CVPR 2025, arXiv 2412.12392), Sec. 3.2:
+ *
+ *   m_{i,j} = M(X^i_i, X^j_i, D^i_i, D^j_i)
+ *
+ * For every pixel n of the query pointmap X^j_i (both pointmaps are expressed
+ * in camera i, Sec. 3.1), it finds the pixel p of frame i whose normalised ray
+ * psi(X^i_i(p)) best aligns with psi(x_n) by minimising the ray error of Eq. 2,
+ * |psi([X^i_i]_p) - psi(x_n)|^2, with Levenberg-Marquardt (Sec. 3.2), reports
+ * the residual angle of Eq. 3, refines the integer match to the best
+ * descriptor dot product in a small window (Sec. 3.2, feature refinement), and
+ * gates it by residual angle, match confidence sqrt(Q^i_i[m] Q^j_i[n])
+ * (Sec. 3.3) and 3D distance (Sec. 3.2, occlusion and outlier handling).
+ * A backward pass gives the implicit adjoint of the converged match, and a
+ * batched entry point matches many edges of a keyframe graph in one launch.
+ *
+ * Conventions shared by every entry point:
+ *   - All array arguments are caller-owned DEVICE memory (HBM of the current
+ *     HIP device), fp32 unless stated, row-major, pixel m = y * W + x.
+ *     Pointmaps are H*W*3 (x, y, z interleaved); descriptors H*W*D;
+ *     confidences H*W; pixel positions H*W*2 as (x = column, y = row).
+ *   - Pixel centres are at integer coordinates; the match domain is
+ *     [0, W-1] x [0, H-1].  H and W must be at least 2.
+ *   - The library never keeps, frees or reallocates caller memory.  The
+ *     workspace is caller-provided device memory of the size the matching
+ *     *_workspace_bytes function reports; its contents need not be preserved
+ *     between calls (except as stated for m3s_match_batched).
+ *   - Work is enqueued asynchronously on `stream` (a hipStream_t; NULL is the
+ *     null stream).  Arguments are validated on the host first: on any error
+ *     nothing is enqueued and a status code is returned; m3s_last_error()
+ *     then describes the problem (per calling thread).  Faults inside kernels
+ *     surface when the caller synchronises the stream.
+ *   - The library never aborts, exits or prints.
+ */
+#ifndef M3S_H
+#define M3S_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define M3S_VERSION 1
+#define M3S_MAX_RADIUS 8      /* largest refine radius r */
+#define M3S_MAX_ITER 1000     /* largest LM iteration count K */
+#define M3S_MAX_DESC 64       /* largest descriptor dimension D */
+
+typedef enum {
+    M3S_OK = 0,
+    M3S_ERR_NULL = 1,         /* a required pointer is NULL */
+    M3S_ERR_SHAPE = 2,        /* H, W < 2, D out of [1, M3S_MAX_DESC], size overflow */
+    M3S_ERR_PARAM = 3,        /* a parameter out of its documented range */
+    M3S_ERR_WORKSPACE = 4,    /* workspace NULL, misaligned (256 B) or too small */
+    M3S_ERR_HIP = 5,          /* a HIP runtime call failed */
+    M3S_ERR_UNSUPPORTED = 6   /* device is not gfx950, or an unsupported flag */
+} m3s_status;
+
+/*
+ * Matching parameters (Sec. 3.2 and 3.3).  m3s_default_params fills the
+ * values of the paper's setting: K = 10 iterations ("within 10 iterations"),
+ * lambda 1e-8, refine radius 3, confidence gate 1.5, residual-angle gate
+ * 1e-4 rad and no 3D-distance gate.
+ */
+typedef struct {
+    int32_t max_iter;       /* K in [0, M3S_MAX_ITER]: LM iterations, run exactly (no early exit) */
+    float   lambda_init;    /* initial Levenberg damping, finite and > 0 */
+    int32_t refine_radius;  /* r in [0, M3S_MAX_RADIUS]: window (2r+1)^2; 0 = round(p*) */
+    float   conf_min;       /* q_min: valid needs sqrt(Qii[idx] * Qji[n]) >= conf_min (if Q given); finite */
+    float   max_theta;      /* valid needs residual angle <= max_theta (rad); >= 0, may be +inf */
+    float   max_dist;       /* valid needs |Xii[idx] - Xji[n]| <= max_dist; > 0, +inf disables the gate */
+} m3s_params;
+
+/* One matching problem: reference frame i and query pointmap X^j_i, same H x W. */
+typedef struct {
+    int32_t H, W, D;
+    const float *Xii;       /* [H*W*3] reference pointmap X^i_i (required) */
+    const float *Xji;       /* [H*W*3] query pointmap X^j_i in camera i (required) */
+    const float *Dii;       /* [H*W*D] reference descriptors D^i_i (required) */
+    const float *Dji;       /* [H*W*D] query descriptors D^j_i (required) */
+    const float *Qii;       /* [H*W] descriptor confidence Q^i_i, or NULL */
+    const float *Qji;       /* [H*W] descriptor confidence Q^j_i, or NULL (both or neither) */
+    const float *p_init;    /* [H*W*2] initial pixel per query, or NULL for the identity mapping */
+} m3s_pair;
+
+/*
+ * Per-query outputs.  p, idx and valid are required; theta and xhat may be
+ * NULL.  A query with a non-finite or zero point, or a non-finite initial
+ * pixel, gets idx = -1, valid = 0, theta = +inf and p = its clamped initial
+ * pixel (0 if that is non-finite).
+ */
+typedef struct {
+    float   *p;             /* [H*W*2] continuous match p* before refinement, (x, y) */
+    int32_t *idx;           /* [H*W]   refined match, linear pixel index in frame i, or -1 */
+    uint8_t *valid;         /* [H*W]   1 if the match passes every gate, else 0 */
+    float   *theta;         /* [H*W]   residual angle at p* in radians (Eq. 3), or NULL */
+    float   *xhat;          /* [H*W*3] X^i_i sampled bilinearly at p*, or NULL */
+} m3s_outputs;
+
+/* One edge of a batch: its pair, its outputs, and optional per-edge K and r (< 0: use the common ones). */
+typedef struct {
+    m3s_pair    in;
+    m3s_outputs out;
+    int32_t     max_iter;
+    int32_t     refine_radius;
+} m3s_edge;
+
+/* Fills *params with the defaults listed above.  NULL is ignored. */
+void m3s_default_params(m3s_params *params);
+
+/*
+ * Workspace bytes m3s_match_fwd needs for this pair (0 on invalid shapes).
+ * The workspace holds the ray image of X^i_i and its gradient images.
+ */
+size_t m3s_workspace_bytes(const m3s_pair *pair, const m3s_params *params);
+
+/*
+ * m3s_match_fwd -- match every pixel of pair->Xji (Sec. 3.2, Eq. 2 and 3;
+ * gates of Sec. 3.2 and 3.3).  Steps, all on the GPU:
+ *   ray image R = X^i_i / |X^i_i| and its central-difference gradient images;
+ *   per query: target ray t = x / |x|, start at p_init or the query's own
+ *   pixel, K Levenberg-Marquardt iterations on |psi_hat(p) - t|^2 with the
+ *   bilinearly sampled, renormalised ray psi_hat, damping lambda I (x10 on a
+ *   rejected step, /10 on an accepted one), every iterate clamped to the
+ *   image; residual angle 2 asin(|e| / 2); refine to the first maximum of the
+ *   raw descriptor dot product over the (2r+1)^2 window around round(p*);
+ *   gates.
+ * ws must be 256-byte aligned device memory of >= m3s_workspace_bytes().
+ */
+m3s_status m3s_match_fwd(const m3s_pair *pair, const m3s_params *params, const m3s_outputs *out,
+                         void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * m3s_match_bwd -- implicit adjoint of the converged match (no counterpart in
+ * the paper).  Given the forward's p and valid, and upstream gradients
+ * grad_p [H*W*2] (required) and grad_xhat [H*W*3] (or NULL), writes
+ * grad_Xii and grad_Xji [H*W*3] each (overwritten) for the dependence of p*
+ * and xhat on the two pointmaps.  At p* the ray residual vanishes, so with
+ * Je = d psi_hat / d p (exact derivative of the bilinear ray sample) the
+ * adjoint solves (Je^T Je) mu = g, v = Je mu, and scatters
+ * grad_Xji[n] = N(x_n) v and grad_Xii[c] -= w_c N(X^i_i[c]) v / |r|, with
+ * N(X) = (I - X X^T/|X|^2)/|X| (Supp. A, Eq. norm_jac), plus the bilinear
+ * weights of grad_xhat into the four corners of p*.  Invalid queries
+ * contribute nothing.  grad_Xii is accumulated with fp32 atomics, so its
+ * rounding may differ between runs.  No workspace is needed.
+ */
+m3s_status m3s_match_bwd(const m3s_pair *pair, const m3s_outputs *fwd,
+                         const float *grad_p, const float *grad_xhat,
+                         float *grad_Xii, float *grad_Xji, void *stream);
+
+/* Flags of m3s_match_batched. */
+#define M3S_BATCH_GRAPH    0x1u  /* capture the launch sequence in a hipGraph and replay it */
+#define M3S_BATCH_AUTOTUNE 0x2u  /* time candidate launch shapes once per shape signature */
+
+/*
+ * Workspace bytes m3s_match_batched needs for these edges (0 on invalid input):
+ * the ray images of every edge, a device copy of the edge table and the
+ * work-queue counter.
+ */
+size_t m3s_batched_workspace_bytes(const m3s_edge *edges, int32_t n_edges, const m3s_params *common);
+
+/*
+ * m3s_match_batched -- m3s_match_fwd over n_edges edges (the edges of a
+ * keyframe graph, Sec. 3.4; matching every new edge is the per-keyframe
+ * cost of Sec. 3.2) in one persistent launch.  Edges may differ in H, W, K
+ * and r (D may differ too).  `edges` is a HOST array; it is copied into the
+ * workspace on `stream` before the launch, so the caller may reuse it as
+ * soon as the call returns.  Results equal those of m3s_match_fwd on each
+ * edge bit for bit.  With M3S_BATCH_GRAPH the launch sequence is captured
+ * into a hipGraph keyed by (device, workspace address, edge shapes) and
+ * replayed on later calls with the same key; the edge table lives in the
+ * workspace, so new pointers need no re-capture.  With M3S_BATCH_AUTOTUNE
+ * the first call for a shape signature times candidate launch shapes
+ * (synchronising the stream) and caches the fastest.  Calls that share a
+ * workspace must not overlap.
+ */
+m3s_status m3s_match_batched(const m3s_edge *edges, int32_t n_edges, const m3s_params *common,
+                             uint32_t flags, void *ws, size_t ws_bytes, void *stream);
+
+/* Launch shape the batched path used for its last call on this thread: workgroups, tile id. */
+void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
+
+/*
+ * Kernel timing (off by default).  When enabled, the library records a pair of
+ * hipEvents around every kernel it launches eagerly (and around each hipGraph
+ * launch, as "batched_graph").  m3s_timing_read synchronises on the recorded
+ * events and returns, for the kernel `name` ("prep", "fwd", "fill", "bwd",
+ * "batched_counter", "batched_prep", "batched_fwd", "batched_graph"), the
+ * summed duration in milliseconds and the number of launches since the last
+ * reset.  Meant for benchmarks: the events cost a little time per launch.
+ */
+void m3s_timing_enable(int32_t on);
+m3s_status m3s_timing_read(const char *name, double *total_ms, int64_t *launches);
+void m3s_timing_reset(void);
+
+/* Drops every cached hipGraph and autotuning result. */
+void m3s_clear_caches(void);
+
+/* Static description of a status code. */
+const char *m3s_status_string(m3s_status status);
+
+/* Details of the last error on the calling thread ("" if none). */
+const char *m3s_last_error(void);
+
+/* M3S_VERSION of the library. */
+int32_t m3s_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* M3S_H */

@@ -1,0 +1,552 @@
+// C ABI of libm3s (declared in include/m3s.h): host-side validation, workspace
+// layout, dispatch, hipGraph capture/replay and the batched-launch autotuner.
+// Host code only; the kernels live in m3s_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "m3s.h"
+#include "m3s_internal.h"
+
+using m3s::EdgeArgs;
+
+namespace {
+
+thread_local std::string g_last_error;
+thread_local int32_t g_last_grid = 0, g_last_tile = 0;
+
+m3s_status fail(m3s_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+m3s_status hip_fail(hipError_t e, const char* what) {
+    return fail(M3S_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// ---------------------------------------------------------------- device info
+
+struct DeviceInfo {
+    bool checked = false;
+    bool supported = false;
+    int cus = 0;
+    std::string arch;
+};
+std::mutex g_dev_mu;
+std::map<int, DeviceInfo> g_devices;
+
+m3s_status current_device(int* dev, DeviceInfo* info) {
+    hipError_t e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    DeviceInfo& d = g_devices[*dev];
+    if (!d.checked) {
+        hipDeviceProp_t prop;
+        e = hipGetDeviceProperties(&prop, *dev);
+        if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+        d.arch = prop.gcnArchName;
+        d.supported = d.arch.compare(0, 6, "gfx950") == 0;
+        d.cus = prop.multiProcessorCount;
+        d.checked = true;
+    }
+    *info = d;
+    if (!d.supported) return fail(M3S_ERR_UNSUPPORTED, "device %d is %s; libm3s is built for gfx950 only", *dev, d.arch.c_str());
+    return M3S_OK;
+}
+
+// ---------------------------------------------------------------- validation
+
+m3s_status check_params(const m3s_params* P) {
+    if (P->max_iter < 0 || P->max_iter > M3S_MAX_ITER) return fail(M3S_ERR_PARAM, "max_iter %d outside [0, %d]", P->max_iter, M3S_MAX_ITER);
+    if (!(std::isfinite(P->lambda_init) && P->lambda_init > 0.f)) return fail(M3S_ERR_PARAM, "lambda_init must be finite and > 0");
+    if (P->refine_radius < 0 || P->refine_radius > M3S_MAX_RADIUS)
+        return fail(M3S_ERR_PARAM, "refine_radius %d outside [0, %d]", P->refine_radius, M3S_MAX_RADIUS);
+    if (!std::isfinite(P->conf_min)) return fail(M3S_ERR_PARAM, "conf_min must be finite");
+    if (std::isnan(P->max_theta) || P->max_theta < 0.f) return fail(M3S_ERR_PARAM, "max_theta must be >= 0");
+    if (std::isnan(P->max_dist) || !(P->max_dist > 0.f)) return fail(M3S_ERR_PARAM, "max_dist must be > 0 (inf disables)");
+    return M3S_OK;
+}
+
+m3s_status check_shape(int32_t H, int32_t W) {
+    if (H < 2 || W < 2) return fail(M3S_ERR_SHAPE, "H and W must be >= 2 (got %d x %d)", H, W);
+    if ((int64_t)H * W > (int64_t)INT32_MAX / 4) return fail(M3S_ERR_SHAPE, "H * W too large (%lld)", (long long)H * W);
+    return M3S_OK;
+}
+
+m3s_status check_pair(const m3s_pair* A, bool need_desc) {
+    if (!A) return fail(M3S_ERR_NULL, "pair is NULL");
+    m3s_status s = check_shape(A->H, A->W);
+    if (s != M3S_OK) return s;
+    if (!A->Xii || !A->Xji) return fail(M3S_ERR_NULL, "Xii and Xji are required");
+    if (!aligned(A->Xii, 4) || !aligned(A->Xji, 4)) return fail(M3S_ERR_PARAM, "pointmaps must be 4-byte aligned");
+    if (need_desc) {
+        if (A->D < 1 || A->D > M3S_MAX_DESC) return fail(M3S_ERR_SHAPE, "D %d outside [1, %d]", A->D, M3S_MAX_DESC);
+        if (!A->Dii || !A->Dji) return fail(M3S_ERR_NULL, "Dii and Dji are required");
+        if (!aligned(A->Dii, 4) || !aligned(A->Dji, 4)) return fail(M3S_ERR_PARAM, "descriptors must be 4-byte aligned");
+        if ((A->Qii == nullptr) != (A->Qji == nullptr)) return fail(M3S_ERR_NULL, "Qii and Qji must both be given or both be NULL");
+        if (A->p_init && !aligned(A->p_init, 4)) return fail(M3S_ERR_PARAM, "p_init must be 4-byte aligned");
+    }
+    return M3S_OK;
+}
+
+m3s_status check_outputs(const m3s_outputs* O) {
+    if (!O) return fail(M3S_ERR_NULL, "outputs is NULL");
+    if (!O->p || !O->idx || !O->valid) return fail(M3S_ERR_NULL, "outputs p, idx and valid are required");
+    if (!aligned(O->p, 8)) return fail(M3S_ERR_PARAM, "p must be 8-byte aligned");
+    if (!aligned(O->idx, 4) || (O->theta && !aligned(O->theta, 4)) || (O->xhat && !aligned(O->xhat, 4)))
+        return fail(M3S_ERR_PARAM, "outputs must be 4-byte aligned");
+    return M3S_OK;
+}
+
+size_t ray_bytes(int32_t H, int32_t W) { return align_up((size_t)H * W * m3s::kRecF4 * sizeof(float4)); }
+
+// Descriptors go to registers with 16-byte loads when D == 24 and both arrays are 16-byte aligned.
+bool desc_in_regs(const m3s_pair* A) {
+    return A->D == 24 && aligned(A->Dii, 16) && aligned(A->Dji, 16);
+}
+
+EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P, int K, int r, const float4* rays) {
+    EdgeArgs E;
+    std::memset(&E, 0, sizeof E);
+    E.H = A->H; E.W = A->W; E.D = A->D; E.K = K; E.r = r;
+    E.lambda0 = P->lambda_init; E.conf_min = P->conf_min; E.max_theta = P->max_theta; E.max_dist = P->max_dist;
+    E.Xii = A->Xii; E.Xji = A->Xji; E.Dii = A->Dii; E.Dji = A->Dji;
+    E.Qii = A->Qii; E.Qji = A->Qji; E.p_init = A->p_init; E.rays = rays;
+    E.p = O->p; E.idx = O->idx; E.valid = O->valid; E.theta = O->theta; E.xhat = O->xhat;
+    return E;
+}
+
+int env_tile_config() {
+    const char* s = std::getenv("M3S_TILE_CONFIG");
+    if (!s) return 0;
+    int v = std::atoi(s);
+    return (v >= 0 && v < m3s::kNumTileConfigs) ? v : 0;
+}
+
+// ---------------------------------------------------------------- batched state
+
+struct Plan {
+    std::vector<EdgeArgs> table;     // in launch (tile) order
+    std::vector<int32_t> prep_begin;
+    int total_tiles = 0, total_prep = 0;
+    size_t off_table = 0, off_prep = 0, off_rays = 0, total_bytes = 0;
+    bool desc_regs = true;
+    std::string signature;
+};
+
+struct TuneResult { int tile = 0; int grid = 0; };
+std::mutex g_cache_mu;
+std::map<std::string, TuneResult> g_tune;           // signature -> best launch shape
+std::map<std::string, hipGraphExec_t> g_graphs;     // signature + ws + launch shape -> graph
+
+m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, int tile_config, Plan* plan) {
+    if (!edges) return fail(M3S_ERR_NULL, "edges is NULL");
+    if (n < 1 || n > (1 << 20)) return fail(M3S_ERR_SHAPE, "n_edges %d outside [1, 2^20]", n);
+    m3s_status s = check_params(P);
+    if (s != M3S_OK) return s;
+    // Heaviest edges first (queries x (iterations + window)), so the work queue
+    // ends on small tiles.
+    std::vector<int> order(n);
+    std::vector<double> cost(n);
+    for (int e = 0; e < n; ++e) {
+        const m3s_edge& E = edges[e];
+        s = check_pair(&E.in, true);
+        if (s != M3S_OK) return fail(s, "edge %d: %s", e, g_last_error.c_str());
+        s = check_outputs(&E.out);
+        if (s != M3S_OK) return fail(s, "edge %d: %s", e, g_last_error.c_str());
+        int K = E.max_iter >= 0 ? E.max_iter : P->max_iter;
+        int r = E.refine_radius >= 0 ? E.refine_radius : P->refine_radius;
+        if (K > M3S_MAX_ITER) return fail(M3S_ERR_PARAM, "edge %d: max_iter %d > %d", e, K, M3S_MAX_ITER);
+        if (r > M3S_MAX_RADIUS) return fail(M3S_ERR_PARAM, "edge %d: refine_radius %d > %d", e, r, M3S_MAX_RADIUS);
+        order[e] = e;
+        cost[e] = (double)E.in.H * E.in.W * (20.0 * (K + 1) + (double)E.in.D * (2 * r + 1) * (2 * r + 1));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+    int tx, ty;
+    m3s::tile_shape(tile_config, &tx, &ty);
+    plan->table.clear();
+    plan->prep_begin.clear();
+    plan->desc_regs = true;
+    size_t off = align_up(sizeof(int32_t));
+    plan->off_table = off;
+    off += align_up(sizeof(EdgeArgs) * (size_t)n);
+    plan->off_prep = off;
+    off += align_up(sizeof(int32_t) * (size_t)n);
+    plan->off_rays = off;
+    int64_t tiles = 0, prep = 0;
+    std::string sig;
+    char buf[96];
+    for (int k = 0; k < n; ++k) {
+        const m3s_edge& E = edges[order[k]];
+        int K = E.max_iter >= 0 ? E.max_iter : P->max_iter;
+        int r = E.refine_radius >= 0 ? E.refine_radius : P->refine_radius;
+        EdgeArgs A = make_edge(&E.in, &E.out, P, K, r, nullptr);
+        A.rays = reinterpret_cast<const float4*>(off);  // offset; rebased onto ws by the caller
+        off += ray_bytes(E.in.H, E.in.W);
+        A.tiles_x = (E.in.W + tx - 1) / tx;
+        A.tiles_y = (E.in.H + ty - 1) / ty;
+        A.tile_begin = (int32_t)tiles;
+        tiles += (int64_t)A.tiles_x * A.tiles_y;
+        plan->prep_begin.push_back((int32_t)prep);
+        prep += ((int64_t)E.in.H * E.in.W + 255) / 256;
+        if (tiles > INT32_MAX / 2 || prep > INT32_MAX / 2) return fail(M3S_ERR_SHAPE, "batch too large");
+        if (!desc_in_regs(&E.in)) plan->desc_regs = false;
+        plan->table.push_back(A);
+        snprintf(buf, sizeof buf, "%d,%d,%d,%d,%d,%d,%d;", order[k], E.in.H, E.in.W, E.in.D, K, r,
+                 (E.in.Qii ? 1 : 0) | (E.in.p_init ? 2 : 0) | (E.out.theta ? 4 : 0) | (E.out.xhat ? 8 : 0));
+        sig += buf;
+    }
+    plan->total_tiles = (int)tiles;
+    plan->total_prep = (int)prep;
+    plan->total_bytes = off;
+    plan->signature = sig + (plan->desc_regs ? "R" : "G");
+    return M3S_OK;
+}
+
+// Rebase the table onto the workspace and copy it (and prep_begin) to the device.
+m3s_status upload_plan(Plan& plan, char* ws, hipStream_t s) {
+    for (EdgeArgs& A : plan.table) A.rays = reinterpret_cast<const float4*>(ws + reinterpret_cast<uintptr_t>(A.rays));
+    hipError_t e = hipMemcpyAsync(ws + plan.off_table, plan.table.data(), sizeof(EdgeArgs) * plan.table.size(),
+                                  hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(edge table)");
+    e = hipMemcpyAsync(ws + plan.off_prep, plan.prep_begin.data(), sizeof(int32_t) * plan.prep_begin.size(),
+                       hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(prep table)");
+    return M3S_OK;
+}
+
+hipError_t run_batched(const Plan& plan, char* ws, int tile, int grid, hipStream_t s) {
+    return m3s::launch_batched(reinterpret_cast<const EdgeArgs*>(ws + plan.off_table),
+                               reinterpret_cast<const int32_t*>(ws + plan.off_prep), (int)plan.table.size(),
+                               plan.total_prep, plan.total_tiles, reinterpret_cast<int32_t*>(ws), tile, grid,
+                               plan.desc_regs, s);
+}
+
+// ---------------------------------------------------------------- kernel timing
+
+struct TimedLaunch { std::string name; hipEvent_t e0, e1; };
+std::mutex g_timer_mu;
+bool g_timer_on = false;
+std::vector<TimedLaunch> g_timed;          // recorded, not yet read
+std::vector<hipEvent_t> g_event_pool;
+std::map<std::string, std::pair<double, int64_t>> g_timer_totals;
+thread_local std::string g_timer_name;
+thread_local hipEvent_t g_timer_e0 = nullptr;
+
+hipEvent_t pooled_event() {
+    if (!g_event_pool.empty()) {
+        hipEvent_t e = g_event_pool.back();
+        g_event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
+    return st != hipStreamCaptureStatusNone;
+}
+
+}  // namespace
+
+namespace m3s {
+
+void timer_begin(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    g_timer_e0 = nullptr;
+    if (!g_timer_on || capturing(s)) return;
+    hipEvent_t e0 = pooled_event();
+    if (!e0) return;
+    if (hipEventRecord(e0, s) != hipSuccess) { g_event_pool.push_back(e0); return; }
+    g_timer_e0 = e0;
+    g_timer_name = name;
+}
+
+void timer_end(hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    if (!g_timer_e0) return;
+    hipEvent_t e1 = pooled_event();
+    if (e1 && hipEventRecord(e1, s) == hipSuccess) {
+        g_timed.push_back({g_timer_name, g_timer_e0, e1});
+    } else {
+        g_event_pool.push_back(g_timer_e0);
+        if (e1) g_event_pool.push_back(e1);
+    }
+    g_timer_e0 = nullptr;
+}
+
+}  // namespace m3s
+
+namespace {
+
+m3s_status drain_timings() {
+    for (TimedLaunch& t : g_timed) {
+        hipError_t e = hipEventSynchronize(t.e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, t.e0, t.e1);
+        if (e != hipSuccess) return hip_fail(e, "timing events");
+        auto& tot = g_timer_totals[t.name];
+        tot.first += ms;
+        tot.second += 1;
+        g_event_pool.push_back(t.e0);
+        g_event_pool.push_back(t.e1);
+    }
+    g_timed.clear();
+    return M3S_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void m3s_timing_enable(int32_t on) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    g_timer_on = on != 0;
+}
+
+m3s_status m3s_timing_read(const char* name, double* total_ms, int64_t* launches) {
+    if (!name || !total_ms || !launches) return fail(M3S_ERR_NULL, "name, total_ms and launches are required");
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    m3s_status s = drain_timings();
+    if (s != M3S_OK) return s;
+    auto it = g_timer_totals.find(name);
+    *total_ms = it == g_timer_totals.end() ? 0.0 : it->second.first;
+    *launches = it == g_timer_totals.end() ? 0 : it->second.second;
+    return M3S_OK;
+}
+
+void m3s_timing_reset(void) {
+    std::lock_guard<std::mutex> lk(g_timer_mu);
+    drain_timings();
+    g_timer_totals.clear();
+}
+
+
+void m3s_default_params(m3s_params* P) {
+    if (!P) return;
+    P->max_iter = 10;
+    P->lambda_init = 1e-8f;
+    P->refine_radius = 3;
+    P->conf_min = 1.5f;
+    P->max_theta = 1e-4f;
+    P->max_dist = INFINITY;
+}
+
+size_t m3s_workspace_bytes(const m3s_pair* pair, const m3s_params*) {
+    if (!pair || pair->H < 2 || pair->W < 2 || (int64_t)pair->H * pair->W > (int64_t)INT32_MAX / 4) return 0;
+    return ray_bytes(pair->H, pair->W);
+}
+
+m3s_status m3s_match_fwd(const m3s_pair* pair, const m3s_params* params, const m3s_outputs* out, void* ws,
+                         size_t ws_bytes, void* stream) {
+    m3s_params defaults;
+    m3s_default_params(&defaults);
+    const m3s_params* P = params ? params : &defaults;
+    m3s_status s = check_params(P);
+    if (s != M3S_OK) return s;
+    if ((s = check_pair(pair, true)) != M3S_OK) return s;
+    if ((s = check_outputs(out)) != M3S_OK) return s;
+    size_t need = ray_bytes(pair->H, pair->W);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need, ws_bytes);
+    int dev;
+    DeviceInfo info;
+    if ((s = current_device(&dev, &info)) != M3S_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    float4* rays = reinterpret_cast<float4*>(ws);
+    EdgeArgs A = make_edge(pair, out, P, P->max_iter, P->refine_radius, rays);
+    hipError_t e = m3s::launch_prep(pair->Xii, rays, pair->H, pair->W, st);
+    if (e != hipSuccess) return hip_fail(e, "prep launch");
+    e = m3s::launch_fwd(A, env_tile_config(), desc_in_regs(pair), st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+m3s_status m3s_match_bwd(const m3s_pair* pair, const m3s_outputs* fwd, const float* grad_p, const float* grad_xhat,
+                         float* grad_Xii, float* grad_Xji, void* stream) {
+    m3s_status s = check_pair(pair, false);
+    if (s != M3S_OK) return s;
+    if (!fwd || !fwd->p || !fwd->valid) return fail(M3S_ERR_NULL, "forward outputs p and valid are required");
+    if (!grad_p || !grad_Xii || !grad_Xji) return fail(M3S_ERR_NULL, "grad_p, grad_Xii and grad_Xji are required");
+    if (!aligned(fwd->p, 4) || !aligned(grad_p, 4) || !aligned(grad_Xii, 4) || !aligned(grad_Xji, 4) ||
+        (grad_xhat && !aligned(grad_xhat, 4)))
+        return fail(M3S_ERR_PARAM, "gradients must be 4-byte aligned");
+    int dev;
+    DeviceInfo info;
+    if ((s = current_device(&dev, &info)) != M3S_OK) return s;
+    hipError_t e = m3s::launch_bwd(pair->H, pair->W, pair->Xii, pair->Xji, fwd->p, fwd->valid, grad_p, grad_xhat,
+                                   grad_Xii, grad_Xji, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "backward launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+size_t m3s_batched_workspace_bytes(const m3s_edge* edges, int32_t n_edges, const m3s_params* common) {
+    m3s_params defaults;
+    m3s_default_params(&defaults);
+    Plan plan;
+    std::string saved = g_last_error;
+    m3s_status s = plan_batched(edges, n_edges, common ? common : &defaults, 0, &plan);
+    g_last_error = saved;
+    return s == M3S_OK ? plan.total_bytes : 0;
+}
+
+m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_params* common, uint32_t flags,
+                             void* ws, size_t ws_bytes, void* stream) {
+    m3s_params defaults;
+    m3s_default_params(&defaults);
+    const m3s_params* P = common ? common : &defaults;
+    if (flags & ~(uint32_t)(M3S_BATCH_GRAPH | M3S_BATCH_AUTOTUNE))
+        return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
+    int tile = env_tile_config();
+    Plan plan;
+    m3s_status s = plan_batched(edges, n_edges, P, tile, &plan);
+    if (s != M3S_OK) return s;
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < plan.total_bytes)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", plan.total_bytes,
+                    ws_bytes);
+    int dev;
+    DeviceInfo info;
+    if ((s = current_device(&dev, &info)) != M3S_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    char* W = reinterpret_cast<char*>(ws);
+    std::string tune_key = std::to_string(dev) + "|" + plan.signature;
+
+    int grid = info.cus * 4;
+    if (flags & M3S_BATCH_AUTOTUNE) {
+        TuneResult tr;
+        bool have = false;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_tune.find(tune_key);
+            if (it != g_tune.end()) { tr = it->second; have = true; }
+        }
+        if (!have) {
+            hipEvent_t e0, e1;
+            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+                return fail(M3S_ERR_HIP, "hipEventCreate failed");
+            float best = INFINITY;
+            const int mults[] = {1, 2, 4, 8};
+            for (int tc = 0; tc < m3s::kNumTileConfigs; ++tc) {
+                Plan p2;
+                if ((s = plan_batched(edges, n_edges, P, tc, &p2)) != M3S_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
+                if ((s = upload_plan(p2, W, st)) != M3S_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
+                for (int mult : mults) {
+                    int g = info.cus * mult;
+                    hipError_t e = run_batched(p2, W, tc, g, st);  // warm-up
+                    float ms_sum = 0.f;
+                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+                        hipEventRecord(e0, st);
+                        e = run_batched(p2, W, tc, g, st);
+                        hipEventRecord(e1, st);
+                        hipEventSynchronize(e1);
+                        float ms = 0.f;
+                        hipEventElapsedTime(&ms, e0, e1);
+                        ms_sum += ms;
+                    }
+                    if (e != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return hip_fail(e, "autotune launch"); }
+                    if (ms_sum < best) { best = ms_sum; tr.tile = tc; tr.grid = g; }
+                }
+            }
+            hipEventDestroy(e0);
+            hipEventDestroy(e1);
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_tune[tune_key] = tr;
+        }
+        if (tr.tile != tile) {
+            tile = tr.tile;
+            if ((s = plan_batched(edges, n_edges, P, tile, &plan)) != M3S_OK) return s;
+        }
+        grid = tr.grid;
+    }
+    grid = std::max(1, std::min(grid, plan.total_tiles));
+    if ((s = upload_plan(plan, W, st)) != M3S_OK) return s;
+    g_last_grid = grid;
+    g_last_tile = tile;
+
+    if ((flags & M3S_BATCH_GRAPH) && st != nullptr) {
+        std::string gkey = tune_key + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) + "|" +
+                           std::to_string(tile) + "|" + std::to_string(grid);
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_graphs.find(gkey);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = run_batched(plan, W, tile, grid, st);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "captured launch"); }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_graphs[gkey] = exec;
+        }
+        m3s::timer_begin("batched_graph", st);
+        hipError_t e = hipGraphLaunch(exec, st);
+        m3s::timer_end(st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        hipError_t e = run_batched(plan, W, tile, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+void m3s_batched_last_config(int32_t* grid, int32_t* tile_config) {
+    if (grid) *grid = g_last_grid;
+    if (tile_config) *tile_config = g_last_tile;
+}
+
+void m3s_clear_caches(void) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    for (auto& kv : g_graphs) hipGraphExecDestroy(kv.second);
+    g_graphs.clear();
+    g_tune.clear();
+}
+
+const char* m3s_status_string(m3s_status s) {
+    switch (s) {
+        case M3S_OK: return "ok";
+        case M3S_ERR_NULL: return "required pointer is NULL";
+        case M3S_ERR_SHAPE: return "invalid shape";
+        case M3S_ERR_PARAM: return "invalid parameter";
+        case M3S_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
+        case M3S_ERR_HIP: return "HIP runtime error";
+        case M3S_ERR_UNSUPPORTED: return "unsupported device or flag";
+    }
+    return "unknown status";
+}
+
+const char* m3s_last_error(void) { return g_last_error.c_str(); }
+
+int32_t m3s_version(void) { return M3S_VERSION; }
+
+}  // extern "C"

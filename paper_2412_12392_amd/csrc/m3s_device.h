@@ -1,0 +1,153 @@
+// Device-side building blocks of the gfx950 matcher: the per-edge argument
+// block, the ray-record layout of the workspace, the bilinear ray sampler and
+// the per-query Levenberg-Marquardt projection (MASt3R-SLAM, Sec. 3.2, Eq. 2).
+// Shared by the single-pair and the batched kernels so both produce the same
+// bits for the same edge.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace m3s {
+
+// Everything one edge needs on the device.  Lives in kernel arguments for the
+// single-pair launch and in the workspace edge table for the batched launch.
+struct EdgeArgs {
+    int32_t H, W, D, K, r;
+    int32_t tiles_x, tiles_y;      // query tiles of this edge (batched path)
+    int32_t tile_begin;            // first global tile id of this edge (batched path)
+    float lambda0, conf_min, max_theta, max_dist;
+    const float* Xii;
+    const float* Xji;
+    const float* Dii;
+    const float* Dji;
+    const float* Qii;              // nullptr: no confidence gate
+    const float* Qji;
+    const float* p_init;           // nullptr: identity initialisation
+    const float4* rays;            // workspace: 3 float4 per reference pixel
+    float* p;
+    int32_t* idx;
+    uint8_t* valid;
+    float* theta;                  // may be nullptr
+    float* xhat;                   // may be nullptr
+};
+
+// Ray record of reference pixel m: {R.x, R.y, R.z, Gx.x}, {Gx.y, Gx.z, Gy.x, Gy.y},
+// {Gy.z, 0, 0, 0}: the unit ray R = X/|X| (zero for a non-finite or zero point)
+// and its central-difference gradients along x and y (one-sided at the border).
+constexpr int kRecF4 = 3;
+
+__device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
+
+// Hardware reciprocal and reciprocal square root (v_rcp_f32 / v_rsq_f32, about
+// 1 ulp).  The matcher's tolerances are orders of magnitude looser.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+
+__device__ __forceinline__ float3 load_point(const float* __restrict__ X, long m) {
+    return f3(X[3 * m + 0], X[3 * m + 1], X[3 * m + 2]);
+}
+
+__device__ __forceinline__ bool finite3(float3 v) {
+    return isfinite(v.x) && isfinite(v.y) && isfinite(v.z);
+}
+
+// Unit ray of a point, zero for a non-finite or zero point.
+__device__ __forceinline__ float3 unit_ray(float3 x) {
+    float n2 = x.x * x.x + x.y * x.y + x.z * x.z;
+    if (!(finite3(x) && n2 > 0.0f && isfinite(n2))) return f3(0.f, 0.f, 0.f);
+    float inv = rsq(n2);
+    return f3(x.x * inv, x.y * inv, x.z * inv);
+}
+
+struct Sample {
+    float c;          // ray error |e|^2 (inf for a degenerate sample)
+    float e0, e1, e2; // e = psi_hat - t
+    float jx0, jx1, jx2, jy0, jy1, jy2;  // d psi_hat / d p (gradient-image Jacobian)
+};
+
+// Ray error of Eq. 2 at pixel (px, py) (inside the domain) for target ray t.
+__device__ __forceinline__ void sample_ray_error(const float4* __restrict__ rec, int H, int W,
+                                                 float px, float py, float3 t, Sample& s) {
+    int x0 = min((int)floorf(px), W - 2);
+    int y0 = min((int)floorf(py), H - 2);
+    float a = px - (float)x0, b = py - (float)y0;
+    long m00 = (long)y0 * W + x0;
+    const float4* r00 = rec + kRecF4 * m00;
+    const float4* r10 = r00 + kRecF4;
+    const float4* r01 = r00 + (long)kRecF4 * W;
+    const float4* r11 = r01 + kRecF4;
+    float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
+    float4 A0 = r00[0], A1 = r00[1], A2 = r00[2];
+    float4 B0 = r10[0], B1 = r10[1], B2 = r10[2];
+    float4 C0 = r01[0], C1 = r01[1], C2 = r01[2];
+    float4 D0 = r11[0], D1 = r11[1], D2 = r11[2];
+#define M3S_BL(i, c) (w00 * A##i.c + w10 * B##i.c + w01 * C##i.c + w11 * D##i.c)
+    float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
+    float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
+    float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = M3S_BL(2, x);
+#undef M3S_BL
+    float n2 = rx * rx + ry * ry + rz * rz;
+    if (!(n2 > 0.0f) || !isfinite(n2)) {
+        s.c = INFINITY;
+        s.e0 = s.e1 = s.e2 = 0.f;
+        s.jx0 = s.jx1 = s.jx2 = s.jy0 = s.jy1 = s.jy2 = 0.f;
+        return;
+    }
+    float inv = rsq(n2);
+    float p0 = rx * inv, p1 = ry * inv, p2 = rz * inv;
+    float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
+    float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
+    s.jx0 = (gxx - p0 * pgx) * inv;
+    s.jx1 = (gxy - p1 * pgx) * inv;
+    s.jx2 = (gxz - p2 * pgx) * inv;
+    s.jy0 = (gyx - p0 * pgy) * inv;
+    s.jy1 = (gyy - p1 * pgy) * inv;
+    s.jy2 = (gyz - p2 * pgy) * inv;
+    s.e0 = p0 - t.x;
+    s.e1 = p1 - t.y;
+    s.e2 = p2 - t.z;
+    s.c = s.e0 * s.e0 + s.e1 * s.e1 + s.e2 * s.e2;
+}
+
+__device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
+
+// K Levenberg-Marquardt iterations from (px, py); returns the final cost.
+__device__ __forceinline__ float lm_project(const float4* __restrict__ rec, int H, int W, int K, float lambda0,
+                                            float3 t, float& px, float& py) {
+    Sample cur, nxt;
+    sample_ray_error(rec, H, W, px, py, t, cur);
+    float lambda = lambda0;
+    const float xmax = (float)(W - 1), ymax = (float)(H - 1);
+    for (int it = 0; it < K; ++it) {
+        float a00 = cur.jx0 * cur.jx0 + cur.jx1 * cur.jx1 + cur.jx2 * cur.jx2 + lambda;
+        float a01 = cur.jx0 * cur.jy0 + cur.jx1 * cur.jy1 + cur.jx2 * cur.jy2;
+        float a11 = cur.jy0 * cur.jy0 + cur.jy1 * cur.jy1 + cur.jy2 * cur.jy2 + lambda;
+        float g0 = cur.jx0 * cur.e0 + cur.jx1 * cur.e1 + cur.jx2 * cur.e2;
+        float g1 = cur.jy0 * cur.e0 + cur.jy1 * cur.e1 + cur.jy2 * cur.e2;
+        float idet = rcp(a00 * a11 - a01 * a01);
+        float dx = -(a11 * g0 - a01 * g1) * idet;
+        float dy = -(a00 * g1 - a01 * g0) * idet;
+        if (!isfinite(dx) || !isfinite(dy)) { lambda *= 10.f; continue; }
+        // A coordinate on its bound whose step points out of the image is
+        // held; the other coordinate then takes its own 1-D damped step.
+        bool hold_x = (px <= 0.f && dx < 0.f) || (px >= xmax && dx > 0.f);
+        bool hold_y = (py <= 0.f && dy < 0.f) || (py >= ymax && dy > 0.f);
+        if (hold_x | hold_y) {
+            float fx = -g0 * rcp(a00), fy = -g1 * rcp(a11);
+            dx = hold_x ? 0.f : fx;
+            dy = hold_y ? 0.f : fy;
+        }
+        float qx = clampf(px + dx, 0.f, xmax), qy = clampf(py + dy, 0.f, ymax);
+        sample_ray_error(rec, H, W, qx, qy, t, nxt);
+        if (nxt.c < cur.c) {
+            px = qx; py = qy; cur = nxt;
+            lambda *= 0.1f;
+        } else {
+            lambda *= 10.f;
+        }
+    }
+    return cur.c;
+}
+
+}  // namespace m3s

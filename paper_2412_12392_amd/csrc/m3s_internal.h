@@ -1,0 +1,28 @@
+// Host-side launchers of the gfx950 kernels (internal to libm3s).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "m3s_device.h"
+
+namespace m3s {
+
+// Tile configurations of the forward kernels (query tile TX x TY, 256 lanes).
+constexpr int kNumTileConfigs = 3;
+void tile_shape(int tile_config, int* tx, int* ty);
+
+// Optional per-kernel event timing (implemented in m3s_capi.hip).  Both calls
+// are no-ops unless timing is enabled and the stream is not being captured.
+void timer_begin(const char* name, hipStream_t s);
+void timer_end(hipStream_t s);
+
+hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s);
+hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s);
+hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
+                          int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs,
+                          hipStream_t s);
+hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
+                      const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s);
+
+}  // namespace m3s

@@ -1,0 +1,413 @@
+// gfx950 kernels of the projective pointmap matcher (MASt3R-SLAM, Sec. 3.2).
+//
+//   prep      ray image R = X^i_i / |X^i_i| and its central-difference
+//             gradient images, packed as 3 float4 per reference pixel
+//             (Sec. 3.1: each pointmap defines its own central camera through
+//             its rays; Fig. 2: the reference pointmap is normalised first).
+//   fwd       one lane per query pixel: LM on the ray error (Eq. 2), residual
+//             angle (Eq. 3), bilinear xhat, window refine by descriptor dot
+//             product (feature refinement paragraph), gates (Sec. 3.2, 3.3).
+//   bwd       implicit adjoint at p* with fp32 atomics into dL/dX^i_i.
+//   batched   persistent work-queue version of prep + fwd over an edge table.
+//
+// Every launch is checked on the host against the shapes its grid assumes;
+// kernels bound-check every pixel they touch against H and W.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "m3s_device.h"
+#include "m3s_internal.h"
+
+namespace m3s {
+
+// ---------------------------------------------------------------- prep
+
+__device__ __forceinline__ void prep_pixel(const float* __restrict__ X, float4* __restrict__ rec,
+                                           int H, int W, int x, int y) {
+    int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+    int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+    long row = (long)y * W;
+    float3 r = unit_ray(load_point(X, row + x));
+    float3 rxm = unit_ray(load_point(X, row + xm));
+    float3 rxp = unit_ray(load_point(X, row + xp));
+    float3 rym = unit_ray(load_point(X, (long)ym * W + x));
+    float3 ryp = unit_ray(load_point(X, (long)yp * W + x));
+    float sx = 1.0f / (float)(xp - xm), sy = 1.0f / (float)(yp - ym);
+    float3 gx = f3((rxp.x - rxm.x) * sx, (rxp.y - rxm.y) * sx, (rxp.z - rxm.z) * sx);
+    float3 gy = f3((ryp.x - rym.x) * sy, (ryp.y - rym.y) * sy, (ryp.z - rym.z) * sy);
+    float4* o = rec + kRecF4 * (row + x);
+    o[0] = make_float4(r.x, r.y, r.z, gx.x);
+    o[1] = make_float4(gx.y, gx.z, gy.x, gy.y);
+    o[2] = make_float4(gy.z, 0.f, 0.f, 0.f);
+}
+
+__global__ void __launch_bounds__(256) prep_kernel(const float* __restrict__ X, float4* __restrict__ rec, int H, int W) {
+    long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= (long)H * W) return;
+    prep_pixel(X, rec, H, W, (int)(m % W), (int)(m / W));
+}
+
+// ---------------------------------------------------------------- forward
+
+// Descriptor dot product of the query (in registers for a compile-time D)
+// with reference pixel m; the products are accumulated in index order.
+template <int DT>
+struct QueryDesc {
+    float q[DT];
+    __device__ __forceinline__ void load(const float* __restrict__ Dj, long n, int) {
+        const float4* s = reinterpret_cast<const float4*>(Dj + (long)DT * n);
+#pragma unroll
+        for (int k = 0; k < DT / 4; ++k) {
+            float4 v = s[k];
+            q[4 * k] = v.x; q[4 * k + 1] = v.y; q[4 * k + 2] = v.z; q[4 * k + 3] = v.w;
+        }
+    }
+    __device__ __forceinline__ float dot(const float* __restrict__ Di, long m, int) const {
+        const float4* s = reinterpret_cast<const float4*>(Di + (long)DT * m);
+        float acc = 0.f;
+#pragma unroll
+        for (int k = 0; k < DT / 4; ++k) {
+            float4 v = s[k];
+            acc = fmaf(q[4 * k], v.x, acc);
+            acc = fmaf(q[4 * k + 1], v.y, acc);
+            acc = fmaf(q[4 * k + 2], v.z, acc);
+            acc = fmaf(q[4 * k + 3], v.w, acc);
+        }
+        return acc;
+    }
+};
+
+// Any D (or unaligned descriptors): both operands read from memory.
+template <>
+struct QueryDesc<0> {
+    const float* q;
+    __device__ __forceinline__ void load(const float* __restrict__ Dj, long n, int D) { q = Dj + (long)D * n; }
+    __device__ __forceinline__ float dot(const float* __restrict__ Di, long m, int D) const {
+        const float* d = Di + (long)D * m;
+        float acc = 0.f;
+        for (int k = 0; k < D; ++k) acc = fmaf(q[k], d[k], acc);
+        return acc;
+    }
+};
+
+// Match query pixel (x, y) of edge A and write its outputs.
+template <int DT>
+__device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
+    const int H = A.H, W = A.W;
+    const long n = (long)y * W + x;
+    float3 xq = load_point(A.Xji, n);
+    float px0, py0;
+    bool bad = false;
+    if (A.p_init) {
+        px0 = A.p_init[2 * n];
+        py0 = A.p_init[2 * n + 1];
+        if (!isfinite(px0) || !isfinite(py0)) { bad = true; px0 = py0 = 0.f; }
+    } else {
+        px0 = (float)x;
+        py0 = (float)y;
+    }
+    float px = clampf(px0, 0.f, (float)(W - 1)), py = clampf(py0, 0.f, (float)(H - 1));
+    float n2 = xq.x * xq.x + xq.y * xq.y + xq.z * xq.z;
+    if (!finite3(xq) || !(n2 > 0.f) || !isfinite(n2)) bad = true;
+    if (bad) {
+        reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
+        A.idx[n] = -1;
+        A.valid[n] = 0;
+        if (A.theta) A.theta[n] = INFINITY;
+        if (A.xhat) { A.xhat[3 * n] = NAN; A.xhat[3 * n + 1] = NAN; A.xhat[3 * n + 2] = NAN; }
+        return;
+    }
+    float inv = rsq(n2);
+    float3 t = f3(xq.x * inv, xq.y * inv, xq.z * inv);
+
+    // Levenberg-Marquardt on Eq. 2.
+    float c = lm_project(A.rays, H, W, A.K, A.lambda0, t, px, py);
+    reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
+
+    // Residual angle, Eq. 3 solved for theta.
+    float th = 2.0f * asinf(fminf(1.0f, sqrtf(c) * 0.5f));
+    if (A.theta) A.theta[n] = th;
+
+    if (A.xhat) {
+        int x0 = min((int)floorf(px), W - 2), y0 = min((int)floorf(py), H - 2);
+        float a = px - (float)x0, b = py - (float)y0;
+        long m00 = (long)y0 * W + x0;
+        float3 X00 = load_point(A.Xii, m00), X10 = load_point(A.Xii, m00 + 1);
+        float3 X01 = load_point(A.Xii, m00 + W), X11 = load_point(A.Xii, m00 + W + 1);
+        float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
+        A.xhat[3 * n + 0] = w00 * X00.x + w10 * X10.x + w01 * X01.x + w11 * X11.x;
+        A.xhat[3 * n + 1] = w00 * X00.y + w10 * X10.y + w01 * X01.y + w11 * X11.y;
+        A.xhat[3 * n + 2] = w00 * X00.z + w10 * X10.z + w01 * X01.z + w11 * X11.z;
+    }
+
+    // Feature refine: first maximum of the raw dot product over the window,
+    // row-major, around p* rounded half up.
+    const int r = A.r;
+    int mx0 = (int)floorf(px + 0.5f), my0 = (int)floorf(py + 0.5f);
+    QueryDesc<DT> qd;
+    qd.load(A.Dji, n, A.D);
+    float best = -INFINITY;
+    long bi = -1;
+    for (int dy = -r; dy <= r; ++dy) {
+        int my = my0 + dy;
+        if (my < 0 || my >= H) continue;
+        for (int dx = -r; dx <= r; ++dx) {
+            int mx = mx0 + dx;
+            if (mx < 0 || mx >= W) continue;
+            long m = (long)my * W + mx;
+            float s = qd.dot(A.Dii, m, A.D);
+            if (s > best) { best = s; bi = m; }
+        }
+    }
+
+    // Gates: residual angle, match confidence (Sec. 3.3), 3D distance (Sec. 3.2).
+    bool ok = bi >= 0 && th <= A.max_theta;
+    if (ok && A.Qii) ok = sqrtf(A.Qii[bi] * A.Qji[n]) >= A.conf_min;
+    if (ok && A.max_dist < INFINITY) {
+        float3 xr = load_point(A.Xii, bi);
+        float d0 = xr.x - xq.x, d1 = xr.y - xq.y, d2 = xr.z - xq.z;
+        ok = sqrtf(d0 * d0 + d1 * d1 + d2 * d2) <= A.max_dist;
+    }
+    A.idx[n] = (int32_t)bi;
+    A.valid[n] = ok ? 1 : 0;
+}
+
+template <int TX, int TY, int DT>
+__global__ void __launch_bounds__(TX * TY) fwd_kernel(EdgeArgs A) {
+    int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
+    int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+    if (x >= A.W || y >= A.H) return;
+    match_query<DT>(A, x, y);
+}
+
+// ---------------------------------------------------------------- batched
+
+// Edge of a global tile id: the last edge whose tile_begin <= tile.
+__device__ __forceinline__ int find_edge(const EdgeArgs* __restrict__ E, int n_edges, int tile) {
+    int lo = 0, hi = n_edges - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (E[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// One block of 256 pixels per prep tile; prep tiles of edge e start at
+// prep_begin[e] (stored in EdgeArgs::tiles_x of the prep table copy).
+__global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __restrict__ E, const int32_t* __restrict__ prep_begin,
+                                                           int n_edges) {
+    int blk = blockIdx.x;
+    int lo = 0, hi = n_edges - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (prep_begin[mid] <= blk) lo = mid; else hi = mid - 1;
+    }
+    const EdgeArgs& A = E[lo];
+    long m = (long)(blk - prep_begin[lo]) * 256 + threadIdx.x;
+    if (m >= (long)A.H * A.W) return;
+    prep_pixel(A.Xii, const_cast<float4*>(A.rays), A.H, A.W, (int)(m % A.W), (int)(m / A.W));
+}
+
+template <int TX, int TY, int DT>
+__global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
+                                                               int32_t* __restrict__ counter) {
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();
+        int tile = s_tile;
+        __syncthreads();
+        if (tile >= total_tiles) return;
+        int e = find_edge(E, n_edges, tile);
+        EdgeArgs A = E[e];
+        int local = tile - A.tile_begin;
+        int ty = local / A.tiles_x, tx = local - ty * A.tiles_x;
+        int x = tx * TX + (int)(threadIdx.x % TX);
+        int y = ty * TY + (int)(threadIdx.x / TX);
+        if (x < A.W && y < A.H) {
+            if (DT != 0 && A.D != DT) {
+                match_query<0>(A, x, y);
+            } else {
+                match_query<DT>(A, x, y);
+            }
+        }
+    }
+}
+
+__global__ void __launch_bounds__(64) set_counter_kernel(int32_t* counter) {
+    if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// ---------------------------------------------------------------- backward
+
+__global__ void __launch_bounds__(256) fill_zero_kernel(float* __restrict__ a, long count) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long stride = (long)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) a[i] = 0.f;
+}
+
+// v -> N(X) v = (v - u (u.v)) / |X| with u = X/|X| (Supp. A, Eq. norm_jac).
+__device__ __forceinline__ float3 norm_jac_apply(float3 X, float3 v) {
+    float inv = rsq(X.x * X.x + X.y * X.y + X.z * X.z);
+    float3 u = f3(X.x * inv, X.y * inv, X.z * inv);
+    float uv = u.x * v.x + u.y * v.y + u.z * v.z;
+    return f3((v.x - u.x * uv) * inv, (v.y - u.y * uv) * inv, (v.z - u.z * uv) * inv);
+}
+
+__global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __restrict__ Xii, const float* __restrict__ Xji,
+                                                  const float* __restrict__ p, const uint8_t* __restrict__ valid,
+                                                  const float* __restrict__ grad_p, const float* __restrict__ grad_xhat,
+                                                  float* __restrict__ dXii, float* __restrict__ dXji) {
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= (long)H * W) return;
+    if (!valid[n]) {
+        dXji[3 * n] = 0.f; dXji[3 * n + 1] = 0.f; dXji[3 * n + 2] = 0.f;
+        return;
+    }
+    float px = p[2 * n], py = p[2 * n + 1];
+    int x0 = min(max((int)floorf(px), 0), W - 2), y0 = min(max((int)floorf(py), 0), H - 2);
+    float a = px - (float)x0, b = py - (float)y0;
+    long cm[4] = {(long)y0 * W + x0, (long)y0 * W + x0 + 1, (long)(y0 + 1) * W + x0, (long)(y0 + 1) * W + x0 + 1};
+    float w[4] = {(1.f - a) * (1.f - b), a * (1.f - b), (1.f - a) * b, a * b};
+    float3 X[4], R[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        X[c] = load_point(Xii, cm[c]);
+        R[c] = unit_ray(X[c]);
+    }
+    float3 r = f3(w[0] * R[0].x + w[1] * R[1].x + w[2] * R[2].x + w[3] * R[3].x,
+                  w[0] * R[0].y + w[1] * R[1].y + w[2] * R[2].y + w[3] * R[3].y,
+                  w[0] * R[0].z + w[1] * R[1].z + w[2] * R[2].z + w[3] * R[3].z);
+    // Exact derivatives of the bilinear ray sample.
+    float3 drx = f3((1.f - b) * (R[1].x - R[0].x) + b * (R[3].x - R[2].x),
+                    (1.f - b) * (R[1].y - R[0].y) + b * (R[3].y - R[2].y),
+                    (1.f - b) * (R[1].z - R[0].z) + b * (R[3].z - R[2].z));
+    float3 dry = f3((1.f - a) * (R[2].x - R[0].x) + a * (R[3].x - R[1].x),
+                    (1.f - a) * (R[2].y - R[0].y) + a * (R[3].y - R[1].y),
+                    (1.f - a) * (R[2].z - R[0].z) + a * (R[3].z - R[1].z));
+    float3 j0 = norm_jac_apply(r, drx), j1 = norm_jac_apply(r, dry);
+
+    float gp0 = grad_p[2 * n], gp1 = grad_p[2 * n + 1];
+    float3 gx = f3(0.f, 0.f, 0.f);
+    if (grad_xhat) {
+        gx = load_point(grad_xhat, n);
+        float3 dxx = f3((1.f - b) * (X[1].x - X[0].x) + b * (X[3].x - X[2].x),
+                        (1.f - b) * (X[1].y - X[0].y) + b * (X[3].y - X[2].y),
+                        (1.f - b) * (X[1].z - X[0].z) + b * (X[3].z - X[2].z));
+        float3 dxy = f3((1.f - a) * (X[2].x - X[0].x) + a * (X[3].x - X[1].x),
+                        (1.f - a) * (X[2].y - X[0].y) + a * (X[3].y - X[1].y),
+                        (1.f - a) * (X[2].z - X[0].z) + a * (X[3].z - X[1].z));
+        gp0 += dxx.x * gx.x + dxx.y * gx.y + dxx.z * gx.z;
+        gp1 += dxy.x * gx.x + dxy.y * gx.y + dxy.z * gx.z;
+    }
+    float a00 = j0.x * j0.x + j0.y * j0.y + j0.z * j0.z;
+    float a01 = j0.x * j1.x + j0.y * j1.y + j0.z * j1.z;
+    float a11 = j1.x * j1.x + j1.y * j1.y + j1.z * j1.z;
+    float det = a00 * a11 - a01 * a01;
+    bool solve = det > 0.f && isfinite(det);
+    float idet = solve ? rcp(det) : 0.f;
+    float mu0 = (a11 * gp0 - a01 * gp1) * idet;
+    float mu1 = (a00 * gp1 - a01 * gp0) * idet;
+    float3 v = f3(j0.x * mu0 + j1.x * mu1, j0.y * mu0 + j1.y * mu1, j0.z * mu0 + j1.z * mu1);
+    float3 dq = solve ? norm_jac_apply(load_point(Xji, n), v) : f3(0.f, 0.f, 0.f);
+    dXji[3 * n] = dq.x; dXji[3 * n + 1] = dq.y; dXji[3 * n + 2] = dq.z;
+    float irn = rsq(r.x * r.x + r.y * r.y + r.z * r.z);
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        if (w[c] == 0.f) continue;
+        float3 g = f3(w[c] * gx.x, w[c] * gx.y, w[c] * gx.z);
+        bool has_ray = R[c].x != 0.f || R[c].y != 0.f || R[c].z != 0.f;
+        if (solve && has_ray) {
+            float3 nv = norm_jac_apply(X[c], v);
+            float s = w[c] * irn;
+            g.x -= s * nv.x; g.y -= s * nv.y; g.z -= s * nv.z;
+        }
+        unsafeAtomicAdd(dXii + 3 * cm[c] + 0, g.x);
+        unsafeAtomicAdd(dXii + 3 * cm[c] + 1, g.y);
+        unsafeAtomicAdd(dXii + 3 * cm[c] + 2, g.z);
+    }
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline unsigned blocks_for(long count, int per) { return (unsigned)((count + per - 1) / per); }
+
+hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s) {
+    long N = (long)H * W;
+    timer_begin("prep", s);
+    prep_kernel<<<blocks_for(N, 256), 256, 0, s>>>(Xii, rays, H, W);
+    timer_end(s);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+static hipError_t launch_fwd_tile(const EdgeArgs& A, bool desc_regs, hipStream_t s) {
+    dim3 grid((A.W + TX - 1) / TX, (A.H + TY - 1) / TY);
+    if (desc_regs && A.D == 24)
+        fwd_kernel<TX, TY, 24><<<grid, TX * TY, 0, s>>>(A);
+    else
+        fwd_kernel<TX, TY, 0><<<grid, TX * TY, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s) {
+    hipError_t e;
+    timer_begin("fwd", s);
+    switch (tile_config) {
+        case 1: e = launch_fwd_tile<16, 16>(A, desc_regs, s); break;
+        case 2: e = launch_fwd_tile<64, 4>(A, desc_regs, s); break;
+        default: e = launch_fwd_tile<32, 8>(A, desc_regs, s); break;
+    }
+    timer_end(s);
+    return e;
+}
+
+void tile_shape(int tile_config, int* tx, int* ty) {
+    switch (tile_config) {
+        case 1: *tx = 16; *ty = 16; return;
+        case 2: *tx = 64; *ty = 4; return;
+        default: *tx = 32; *ty = 8; return;
+    }
+}
+
+hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
+                          int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs, hipStream_t s) {
+    timer_begin("batched_counter", s);
+    set_counter_kernel<<<1, 64, 0, s>>>(counter);
+    timer_end(s);
+    timer_begin("batched_prep", s);
+    batched_prep_kernel<<<total_prep_blocks, 256, 0, s>>>(table, prep_begin, n_edges);
+    timer_end(s);
+    timer_begin("batched_fwd", s);
+    switch (tile_config) {
+        case 1:
+            if (desc_regs) batched_fwd_kernel<16, 16, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            else batched_fwd_kernel<16, 16, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            break;
+        case 2:
+            if (desc_regs) batched_fwd_kernel<64, 4, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            else batched_fwd_kernel<64, 4, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            break;
+        default:
+            if (desc_regs) batched_fwd_kernel<32, 8, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            else batched_fwd_kernel<32, 8, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+            break;
+    }
+    timer_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
+                      const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s) {
+    long N = (long)H * W;
+    timer_begin("fill", s);
+    fill_zero_kernel<<<min(blocks_for(3 * N, 256), 4096u), 256, 0, s>>>(dXii, 3 * N);
+    timer_end(s);
+    timer_begin("bwd", s);
+    bwd_kernel<<<blocks_for(N, 256), 256, 0, s>>>(H, W, Xii, Xji, p, valid, grad_p, grad_xhat, dXii, dXji);
+    timer_end(s);
+    return hipGetLastError();
+}
+
+}  // namespace m3s

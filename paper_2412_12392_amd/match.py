@@ -1,0 +1,204 @@
+"""Python binding of libm3s over torch device tensors.
+
+Marshals torch tensors (device memory) and the current HIP stream into the C
+ABI of include/m3s.h.  Every step of the matcher runs inside libm3s's HIP
+kernels; nothing here computes.  There is no CPU fallback: a missing library
+or a CPU tensor raises.
+
+    res = match(Xii, Xji, Dii, Dji, Qii, Qji)        # MASt3R-SLAM Sec. 3.2
+    gXii, gXji = match_backward(Xii, Xji, res.p, res.valid, grad_p, grad_xhat)
+    outs = match_batched([EdgeInput(...), ...], graph=True)
+    p, xhat, idx, valid, theta = MatchFunction.apply(Xii, Xji, Dii, Dji, Qii, Qji, None, params)
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+
+
+@dataclass
+class MatchResult:
+    p: torch.Tensor                  # (H, W, 2) float32, continuous match p*
+    idx: torch.Tensor                # (H, W) int32, refined linear index or -1
+    valid: torch.Tensor              # (H, W) uint8
+    theta: Optional[torch.Tensor]    # (H, W) float32 residual angle, or None
+    xhat: Optional[torch.Tensor]     # (H, W, 3) float32 X^i_i at p*, or None
+
+
+@dataclass
+class EdgeInput:
+    Xii: torch.Tensor
+    Xji: torch.Tensor
+    Dii: torch.Tensor
+    Dji: torch.Tensor
+    Qii: Optional[torch.Tensor] = None
+    Qji: Optional[torch.Tensor] = None
+    p_init: Optional[torch.Tensor] = None
+    max_iter: int = -1               # < 0: the common value
+    refine_radius: int = -1
+
+
+def params(**overrides) -> _lib.Params:
+    """Matching parameters: library defaults (K 10, lambda 1e-8, r 3, q_min 1.5,
+    max_theta 1e-4, no distance gate) with keyword overrides."""
+    return _lib.default_params(None, **overrides)
+
+
+def _ptr(t: Optional[torch.Tensor], dtype=torch.float32, shape=None) -> int:
+    if t is None:
+        return 0
+    if not t.is_cuda:
+        raise ValueError("libm3s takes device tensors (got a CPU tensor)")
+    if t.dtype != dtype:
+        raise TypeError("expected %s, got %s" % (dtype, t.dtype))
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("expected shape %s, got %s" % (tuple(shape), tuple(t.shape)))
+    return t.data_ptr()
+
+
+def _stream(stream) -> int:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return s.cuda_stream
+
+
+_ws_cache: dict = {}
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    """A cached device buffer of at least nbytes (torch allocations are >= 256-byte aligned)."""
+    key = (torch.device(device).index, nbytes > 0)
+    buf = _ws_cache.get(key)
+    if buf is None or buf.numel() < nbytes:
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache[key] = buf
+    return buf
+
+
+def _pair(Xii, Xji, Dii=None, Dji=None, Qii=None, Qji=None, p_init=None) -> _lib.Pair:
+    H, W = Xii.shape[:2]
+    D = Dii.shape[2] if Dii is not None else 0
+    return _lib.Pair(H, W, D, _ptr(Xii, shape=(H, W, 3)), _ptr(Xji, shape=(H, W, 3)),
+                     _ptr(Dii, shape=(H, W, D)), _ptr(Dji, shape=(H, W, D)),
+                     _ptr(Qii, shape=(H, W)), _ptr(Qji, shape=(H, W)), _ptr(p_init, shape=(H, W, 2)))
+
+
+def _alloc_outputs(H, W, device, want_theta, want_xhat):
+    p = torch.empty((H, W, 2), dtype=torch.float32, device=device)
+    idx = torch.empty((H, W), dtype=torch.int32, device=device)
+    valid = torch.empty((H, W), dtype=torch.uint8, device=device)
+    theta = torch.empty((H, W), dtype=torch.float32, device=device) if want_theta else None
+    xhat = torch.empty((H, W, 3), dtype=torch.float32, device=device) if want_xhat else None
+    return MatchResult(p, idx, valid, theta, xhat)
+
+
+def _outputs(res: MatchResult) -> _lib.Outputs:
+    return _lib.Outputs(_ptr(res.p), _ptr(res.idx, torch.int32), _ptr(res.valid, torch.uint8),
+                        _ptr(res.theta), _ptr(res.xhat))
+
+
+def match(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, prm: Optional[_lib.Params] = None,
+          want_theta: bool = True, want_xhat: bool = False, out: Optional[MatchResult] = None,
+          stream=None) -> MatchResult:
+    """m3s_match_fwd on one pair of (H, W, 3) pointmaps and (H, W, D) descriptors."""
+    lib = _lib.load()
+    H, W = Xii.shape[:2]
+    pair = _pair(Xii, Xji, Dii, Dji, Qii, Qji, p_init)
+    prm = prm if prm is not None else params()
+    res = out if out is not None else _alloc_outputs(H, W, Xii.device, want_theta, want_xhat)
+    o = _outputs(res)
+    nbytes = lib.m3s_workspace_bytes(ctypes.byref(pair), ctypes.byref(prm))
+    ws = _workspace(nbytes, Xii.device)
+    st = lib.m3s_match_fwd(ctypes.byref(pair), ctypes.byref(prm), ctypes.byref(o), ws.data_ptr(), ws.numel(),
+                           _stream(stream))
+    _lib.check(lib, "m3s_match_fwd", st)
+    return res
+
+
+def match_backward(Xii, Xji, p, valid, grad_p, grad_xhat=None, stream=None):
+    """m3s_match_bwd: (dL/dXii, dL/dXji) through p* and xhat."""
+    lib = _lib.load()
+    H, W = Xii.shape[:2]
+    pair = _pair(Xii, Xji)
+    fwd = _lib.Outputs(_ptr(p, shape=(H, W, 2)), 0, _ptr(valid, torch.uint8, shape=(H, W)), 0, 0)
+    gXii = torch.empty((H, W, 3), dtype=torch.float32, device=Xii.device)
+    gXji = torch.empty((H, W, 3), dtype=torch.float32, device=Xii.device)
+    st = lib.m3s_match_bwd(ctypes.byref(pair), ctypes.byref(fwd), _ptr(grad_p, shape=(H, W, 2)),
+                           _ptr(grad_xhat, shape=(H, W, 3)), _ptr(gXii), _ptr(gXji), _stream(stream))
+    _lib.check(lib, "m3s_match_bwd", st)
+    return gXii, gXji
+
+
+def make_edges(inputs: Sequence[EdgeInput], want_theta=True, want_xhat=False, outs=None):
+    """Host edge table plus freshly allocated (or given) outputs."""
+    n = len(inputs)
+    table = (_lib.Edge * n)()
+    results = []
+    for k, e in enumerate(inputs):
+        H, W = e.Xii.shape[:2]
+        res = outs[k] if outs is not None else _alloc_outputs(H, W, e.Xii.device, want_theta, want_xhat)
+        table[k].in_ = _pair(e.Xii, e.Xji, e.Dii, e.Dji, e.Qii, e.Qji, e.p_init)
+        table[k].out = _outputs(res)
+        table[k].max_iter = e.max_iter
+        table[k].refine_radius = e.refine_radius
+        results.append(res)
+    return table, results
+
+
+def match_batched(inputs: Sequence[EdgeInput], prm: Optional[_lib.Params] = None, graph: bool = True,
+                  autotune: bool = False, want_theta=True, want_xhat=False, outs=None, stream=None):
+    """m3s_match_batched: every edge in one persistent launch; returns one MatchResult per edge."""
+    lib = _lib.load()
+    prm = prm if prm is not None else params()
+    table, results = make_edges(inputs, want_theta, want_xhat, outs)
+    n = len(inputs)
+    nbytes = lib.m3s_batched_workspace_bytes(table, n, ctypes.byref(prm))
+    if nbytes == 0:
+        raise _lib.M3SError("m3s_batched_workspace_bytes", _lib.M3S_OK + 2, "invalid edges")
+    ws = _workspace(nbytes, inputs[0].Xii.device)
+    flags = (_lib.M3S_BATCH_GRAPH if graph else 0) | (_lib.M3S_BATCH_AUTOTUNE if autotune else 0)
+    st = lib.m3s_match_batched(table, n, ctypes.byref(prm), flags, ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(lib, "m3s_match_batched", st)
+    return results
+
+
+def last_batched_config():
+    lib = _lib.load()
+    g, t = ctypes.c_int32(), ctypes.c_int32()
+    lib.m3s_batched_last_config(ctypes.byref(g), ctypes.byref(t))
+    return g.value, t.value
+
+
+class MatchFunction(torch.autograd.Function):
+    """Differentiable matcher: (Xii, Xji, ...) -> (p, xhat, idx, valid, theta).
+
+    Gradients reach Xii and Xji through the continuous match p* and the
+    sampled point xhat (implicit adjoint, m3s_match_bwd).  idx, valid and
+    theta are not differentiable, and descriptors, confidences and p_init get
+    no gradient (the refine offset is piecewise constant).
+    """
+
+    @staticmethod
+    def forward(ctx, Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, prm=None):
+        Xii_c, Xji_c = Xii.contiguous(), Xji.contiguous()
+        res = match(Xii_c, Xji_c, Dii.contiguous(), Dji.contiguous(),
+                    None if Qii is None else Qii.contiguous(), None if Qji is None else Qji.contiguous(),
+                    None if p_init is None else p_init.contiguous(), prm, want_theta=True, want_xhat=True)
+        ctx.save_for_backward(Xii_c, Xji_c, res.p, res.valid)
+        ctx.mark_non_differentiable(res.idx, res.valid, res.theta)
+        return res.p, res.xhat, res.idx, res.valid, res.theta
+
+    @staticmethod
+    def backward(ctx, grad_p, grad_xhat, _gi, _gv, _gt):
+        Xii, Xji, p, valid = ctx.saved_tensors
+        if grad_p is None:
+            grad_p = torch.zeros_like(p)
+        gXii, gXji = match_backward(Xii, Xji, p, valid, grad_p.contiguous(),
+                                    None if grad_xhat is None else grad_xhat.contiguous())
+        return gXii, gXji, None, None, None, None, None, None

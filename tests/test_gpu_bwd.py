@@ -1,0 +1,105 @@
+"""GPU backward (implicit adjoint) against the FP64 oracle's adjoint, and the
+autograd.Function end to end."""
+import numpy as np
+import pytest
+
+import oracle
+import parity
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m3s():
+    import paper_2412_12392_amd as m
+    m.load_library()
+    return m
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30))
+
+
+def _fed(m3s, pair, seed):
+    """Oracle p* and mask fed to both backward implementations (same inputs)."""
+    import torch
+    o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji, K=20, r=pair.r)
+    p32 = o["p"].astype(np.float32)
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gp = rng.normal(size=p32.shape).astype(np.float32)
+    gx = rng.normal(size=pair.Xii.shape).astype(np.float32)
+    gi, gj = m3s.match_backward(parity.to_dev(pair.Xii), parity.to_dev(pair.Xji), parity.to_dev(p32),
+                                torch.from_numpy(o["valid"].astype(np.uint8)).cuda(), parity.to_dev(gp),
+                                parity.to_dev(gx))
+    torch.cuda.synchronize()
+    oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, p32.astype(np.float64), o["valid"], gp, gx)
+    return gi.cpu().numpy(), gj.cpu().numpy(), oi, oj, o
+
+
+@pytest.mark.parametrize("H,W,seed", [(48, 64, 501), (384, 512, 502), (37, 53, 503)])
+def test_bwd_matches_oracle_adjoint(m3s, H, W, seed):
+    pair = synth.make_pair(H, W, seed)
+    gi, gj, oi, oj, o = _fed(m3s, pair, seed)
+    ei, ej = rel_l2(gi, oi), rel_l2(gj, oj)
+    print(dict(shape=(H, W), rel_l2_dXii=ei, rel_l2_dXji=ej))
+    assert ei <= 1e-4 and ej <= 1e-4
+    # Per query: dXji elementwise within 1e-3 of the largest entry.
+    assert np.abs(gj - oj).max() <= 1e-3 * np.abs(oj).max()
+    assert (gj[~o["valid"]] == 0).all()
+
+
+def test_bwd_deterministic_query_side(m3s):
+    pair = synth.make_pair(96, 128, 504)
+    a = _fed(m3s, pair, 1)
+    b = _fed(m3s, pair, 1)
+    assert np.array_equal(a[1], b[1])
+    assert rel_l2(a[0], b[0]) <= 1e-6
+
+
+def test_autograd_function_end_to_end(m3s):
+    """L = sum over valid matches of |xhat - x|^2 through MatchFunction; the
+    gradient equals the oracle's implicit adjoint plus the direct term, on the
+    same forward matches."""
+    import torch
+    pair = synth.make_pair(48, 64, 505, conf=False)
+    Xi = parity.to_dev(pair.Xii).requires_grad_(True)
+    Xj = parity.to_dev(pair.Xji).requires_grad_(True)
+    p, xhat, idx, valid, theta = m3s.MatchFunction.apply(Xi, Xj, parity.to_dev(pair.Dii), parity.to_dev(pair.Dji),
+                                                         None, None, None, m3s.params(max_iter=20))
+    m = valid.bool()
+    L = ((xhat - Xj) ** 2).sum(-1)[m].sum()
+    L.backward()
+    torch.cuda.synchronize()
+    pg = p.detach().cpu().numpy().astype(np.float64)
+    vg = valid.cpu().numpy().astype(bool)
+    xh = xhat.detach().cpu().numpy().astype(np.float64)
+    gx = 2.0 * (xh - pair.Xji) * vg[..., None]
+    oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, pg, vg, None, gx)
+    oj = oj - gx
+    ei = rel_l2(Xi.grad.cpu().numpy(), oi)
+    ej = rel_l2(Xj.grad.cpu().numpy(), oj)
+    print(dict(rel_l2_dXii=ei, rel_l2_dXji=ej))
+    assert ei <= 1e-4 and ej <= 1e-4
+
+
+def test_fwd_bwd_full_size_sampled(m3s):
+    """512x384 fwd then bwd on the GPU's own matches vs the oracle's fwd + bwd:
+    per-query gradients agree where both sides call the match valid."""
+    import torch
+    pair = synth.make_pair(384, 512, 5000)
+    t = parity.pair_tensors(pair)
+    res = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"], want_xhat=True)
+    v = res.valid.bool()
+    gx = (2.0 * (res.xhat - t["Xji"]) * v[..., None]).contiguous()
+    gi, gj = m3s.match_backward(t["Xii"], t["Xji"], res.p, res.valid, torch.zeros_like(res.p), gx)
+    torch.cuda.synchronize()
+    o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji)
+    ogx = 2.0 * (o["xhat"] - pair.Xji) * o["valid"][..., None]
+    oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, o["p"], o["valid"], None, ogx)
+    both = o["valid"] & res.valid.cpu().numpy().astype(bool)
+    gj = gj.cpu().numpy()
+    err = np.abs(gj - oj)[both].max() / np.abs(oj[both]).max()
+    print(dict(max_rel_dXji_valid_both=float(err), rel_l2_dXii=rel_l2(gi.cpu().numpy(), oi)))
+    assert err <= 1e-3
+    assert rel_l2(gi.cpu().numpy(), oi) <= 1e-2

@@ -1,0 +1,159 @@
+"""GPU forward parity: libm3s (fp32, gfx950) against the FP64 oracle, through the C ABI."""
+import functools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import parity
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def m3s():
+    import paper_2412_12392_amd as m
+    m.load_library()
+    return m
+
+
+@functools.lru_cache(maxsize=None)
+def _pair(H, W, seed, conf=True):
+    return synth.make_pair(H, W, seed, conf=conf)
+
+
+def run(m3s, pair, p_init=None, want_xhat=True, **prm):
+    t = parity.pair_tensors(pair)
+    res = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"],
+                    parity.to_dev(p_init), m3s.params(**prm), want_theta=True, want_xhat=want_xhat)
+    return parity.result_numpy(res)
+
+
+def ora(pair, p_init=None, **kw):
+    args = dict(oracle.DEFAULTS, K=pair.K, r=pair.r)
+    args.update(kw)
+    return oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji, p_init, **args)
+
+
+def _prm_kw(kw):
+    # oracle keyword -> library parameter name
+    names = dict(K="max_iter", r="refine_radius", lambda0="lambda_init", conf_min="conf_min",
+                 max_theta="max_theta", max_dist="max_dist")
+    return {names[k]: v for k, v in kw.items()}
+
+
+def check(m3s, pair, label, p_init=None, **kw):
+    kw.setdefault("K", pair.K)
+    kw.setdefault("r", pair.r)
+    g = run(m3s, pair, p_init, **_prm_kw(kw))
+    o = ora(pair, p_init, **kw)
+    st = parity.compare(g, o, label)
+    print(st)
+    if "xhat" in g:
+        both = g["valid"] & o["valid"]
+        assert np.abs(g["xhat"] - o["xhat"])[both].max() <= 1e-3 * max(1.0, np.abs(o["xhat"]).max())
+    return g, o, st
+
+
+def test_config_64x48(m3s):
+    """64x48 pair, identity init, 10 LM iterations, r = 3, no confidences."""
+    pair = synth.config_pair(1)
+    check(m3s, pair, "64x48")
+
+
+def test_config_512x384(m3s):
+    """512x384 pair with confidences gated at 1.5, 10 iterations, r = 3."""
+    pair = synth.config_pair(2)
+    _, _, st = check(m3s, pair, "512x384")
+    assert st["idx_compared"] > 0.9 * st["valid_both"]
+
+
+@pytest.mark.parametrize("H,W", [(2, 2), (3, 5), (37, 53), (129, 67), (5, 300), (300, 7)])
+def test_ragged_shapes(m3s, H, W):
+    """Shapes that are not multiples of any tile, down to the 2x2 minimum."""
+    check(m3s, _pair(H, W, 31 * H + W), "%dx%d" % (H, W))
+
+
+@pytest.mark.parametrize("K,r", [(0, 3), (1, 3), (3, 0), (10, 1), (15, 8), (30, 2)])
+def test_iterations_and_radius(m3s, K, r):
+    check(m3s, _pair(48, 64, 7), "K%d r%d" % (K, r), K=K, r=r)
+
+
+def test_p_init(m3s):
+    """Tracking-style initialisation from given pixels (Sec. 3.2)."""
+    pair = _pair(96, 128, 8)
+    rng = np.random.Generator(np.random.PCG64(1))
+    p_init = pair.proj + rng.normal(0, 1.5, size=pair.proj.shape)
+    check(m3s, pair, "p_init", p_init=p_init, K=5)
+
+
+def test_gates(m3s):
+    """Distance gate on, angle gate off and a stricter confidence gate."""
+    pair = _pair(96, 128, 9)
+    check(m3s, pair, "dist gate", max_dist=0.2)
+    check(m3s, pair, "no angle gate", max_theta=math.inf)
+    check(m3s, pair, "conf 3", conf_min=3.0)
+
+
+def test_bad_inputs(m3s):
+    """Non-finite and zero points, bad reference pixels, non-finite p_init."""
+    pair = _pair(48, 64, 10)
+    pair = synth.Pair(pair.H, pair.W, pair.Xii.copy(), pair.Xji.copy(), pair.Dii, pair.Dji, pair.Qii, pair.Qji,
+                      proj=pair.proj)
+    pair.Xji[0, 0] = [np.nan, 1, 1]
+    pair.Xji[1, 5] = [0, 0, 0]
+    pair.Xji[2, 7] = [np.inf, 0, 1]
+    pair.Xii[20, 30] = [np.nan, 0, 0]
+    pair.Xii[21, 31] = [0, 0, 0]
+    p_init = np.stack(synth.pixel_grid(48, 64), -1)
+    p_init[3, 3] = [np.nan, 2]
+    g, o, st = check(m3s, pair, "bad inputs", p_init=p_init)
+    for y, x in [(0, 0), (1, 5), (2, 7), (3, 3)]:
+        assert g["idx"][y, x] == -1 and not g["valid"][y, x] and g["theta"][y, x] == np.inf
+
+
+def test_identity(m3s):
+    p = synth.identity_pair(48, 64, 12)
+    g = run(m3s, p)
+    xs, ys = synth.pixel_grid(48, 64)
+    assert np.abs(g["p"][..., 0] - xs).max() <= 1e-4 and np.abs(g["p"][..., 1] - ys).max() <= 1e-4
+    assert (g["idx"] == np.arange(48 * 64).reshape(48, 64)).all()
+    assert g["valid"].all()
+
+
+def test_generic_descriptor_paths(m3s):
+    """D != 24 and misaligned descriptors take the generic path; it must give the
+    same bits as the register path for D = 24."""
+    import torch
+    pair = _pair(48, 64, 13, conf=False)
+    check(m3s, synth.make_pair(48, 64, 14, D=7), "D7")
+    check(m3s, synth.make_pair(48, 64, 15, D=64), "D64")
+    t = parity.pair_tensors(pair)
+    ref = parity.result_numpy(m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"]))
+    N = 48 * 64 * 24
+    bi = torch.empty(N + 1, device="cuda")[1:]
+    bj = torch.empty(N + 1, device="cuda")[1:]
+    bi.copy_(t["Dii"].reshape(-1))
+    bj.copy_(t["Dji"].reshape(-1))
+    assert bi.data_ptr() % 16 != 0
+    mis = parity.result_numpy(m3s.match(t["Xii"], t["Xji"], bi.view(48, 64, 24), bj.view(48, 64, 24)))
+    for k in ("p", "idx", "valid", "theta"):
+        assert np.array_equal(ref[k], mis[k]), k
+
+
+def test_tile_configs_bitwise_and_deterministic(m3s):
+    """Every tile shape and repeated runs give identical bits."""
+    pair = _pair(200, 264, 16)
+    outs = []
+    try:
+        for tc in ("0", "1", "2", "0"):
+            os.environ["M3S_TILE_CONFIG"] = tc
+            outs.append(run(m3s, pair))
+    finally:
+        os.environ.pop("M3S_TILE_CONFIG", None)
+    for o in outs[1:]:
+        for k in ("p", "idx", "valid", "theta", "xhat"):
+            assert np.array_equal(outs[0][k], o[k], equal_nan=True), k
