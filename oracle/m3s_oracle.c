@@ -50,7 +50,9 @@
  * so the derivative of p* by any input theta is -(Je^T Je)^-1 Je^T de/dtheta,
  * with Je the exact derivative of
  * the bilinear ray sampler (not the gradient-image Jacobian, which is only a
- * search direction and does not move the root).
+ * search direction and does not move the root).  A coordinate of p* held on
+ * the image bound does not move; the other coordinate's derivative then comes
+ * from its own 1-D system.
  */
 #include <math.h>
 #include <stddef.h>
@@ -446,17 +448,32 @@ int oracle_match_bwd(int H, int W, const double *Xii, const double *Xji,
             for (int c = 0; c < 4; ++c)
                 for (int k = 0; k < 3; ++k) dXii[3 * cm[c] + k] += w[c] * gx[k];
         }
-        /* mu = (Je^T Je)^-1 g_p, v = Je mu. */
+        /* mu = (Je^T Je)^-1 g_p, v = Je mu.  A coordinate of p* on its bound
+           is held by the forward, so it does not move: it drops out and the
+           other coordinate is solved alone (both held: p* does not move). */
         double a00 = 0, a01 = 0, a11 = 0;
         for (int k = 0; k < 3; ++k) {
             a00 += Je[k][0] * Je[k][0];
             a01 += Je[k][0] * Je[k][1];
             a11 += Je[k][1] * Je[k][1];
         }
-        double det = a00 * a11 - a01 * a01;
-        if (!(det > 0.0) || !isfinite(det)) continue;
-        double mu0 = (a11 * gp0 - a01 * gp1) / det;
-        double mu1 = (a00 * gp1 - a01 * gp0) / det;
+        int held_x = p[2 * n] <= 0.0 || p[2 * n] >= W - 1.0;
+        int held_y = p[2 * n + 1] <= 0.0 || p[2 * n + 1] >= H - 1.0;
+        double mu0 = 0.0, mu1 = 0.0;
+        if (held_x && held_y) {
+            /* nothing moves */
+        } else if (held_x) {
+            if (!(a11 > 0.0)) continue;
+            mu1 = gp1 / a11;
+        } else if (held_y) {
+            if (!(a00 > 0.0)) continue;
+            mu0 = gp0 / a00;
+        } else {
+            double det = a00 * a11 - a01 * a01;
+            if (!(det > 0.0) || !isfinite(det)) continue;
+            mu0 = (a11 * gp0 - a01 * gp1) / det;
+            mu1 = (a00 * gp1 - a01 * gp0) / det;
+        }
         double v[3];
         for (int k = 0; k < 3; ++k) v[k] = Je[k][0] * mu0 + Je[k][1] * mu1;
 

@@ -304,11 +304,30 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     float a00 = j0.x * j0.x + j0.y * j0.y + j0.z * j0.z;
     float a01 = j0.x * j1.x + j0.y * j1.y + j0.z * j1.z;
     float a11 = j1.x * j1.x + j1.y * j1.y + j1.z * j1.z;
-    float det = a00 * a11 - a01 * a01;
-    bool solve = det > 0.f && isfinite(det);
-    float idet = solve ? rcp(det) : 0.f;
-    float mu0 = (a11 * gp0 - a01 * gp1) * idet;
-    float mu1 = (a00 * gp1 - a01 * gp0) * idet;
+    // A coordinate of p* on the image bound is held by the forward and does not
+    // move; the other one is solved alone (both held: nothing moves).
+    bool held_x = px <= 0.f || px >= (float)(W - 1);
+    bool held_y = py <= 0.f || py >= (float)(H - 1);
+    float mu0, mu1;
+    bool solve;
+    if (held_x && held_y) {
+        solve = true;
+        mu0 = mu1 = 0.f;
+    } else if (held_x) {
+        solve = a11 > 0.f;
+        mu0 = 0.f;
+        mu1 = solve ? gp1 * rcp(a11) : 0.f;
+    } else if (held_y) {
+        solve = a00 > 0.f;
+        mu1 = 0.f;
+        mu0 = solve ? gp0 * rcp(a00) : 0.f;
+    } else {
+        float det = a00 * a11 - a01 * a01;
+        solve = det > 0.f && isfinite(det);
+        float idet = solve ? rcp(det) : 0.f;
+        mu0 = (a11 * gp0 - a01 * gp1) * idet;
+        mu1 = (a00 * gp1 - a01 * gp0) * idet;
+    }
     float3 v = f3(j0.x * mu0 + j1.x * mu1, j0.y * mu0 + j1.y * mu1, j0.z * mu0 + j1.z * mu1);
     float3 dq = solve ? norm_jac_apply(load_point(Xji, n), v) : f3(0.f, 0.f, 0.f);
     dXji[3 * n] = dq.x; dXji[3 * n + 1] = dq.y; dXji[3 * n + 2] = dq.z;

@@ -450,9 +450,65 @@ def pin_bwd_projection_jacobian(lib):
         assert err.max() <= 5e-2, "projection Jacobian row %d: %g" % (comp, err.max())
 
 
+def pin_bwd_held_border(lib):
+    """Matches held on the image border (their rays lie just outside it): the
+    held coordinate does not move and the other one follows its 1-D system.
+    Central finite differences of the loss through the forward agree with the
+    adjoint to the Gauss-Newton approximation error at a small residual (the
+    adjoint of a free coordinate would be off by far more)."""
+    H, W = 24, 32
+    R, f, cx, cy = pinhole_rays(H, W)
+    xs, ys = synth.pixel_grid(H, W)
+    z = 2.0 + 0.2 * np.sin(0.3 * xs) * np.cos(0.2 * ys)
+    Xii = R * z[..., None]
+    Xj = np.tile(np.array([0.0, 0.0, 1.0]), (H, W, 1)) * 2.0
+    queries = []
+    for k, yq in enumerate([3.3, 7.6, 12.2, 17.9]):       # beyond the right border
+        u, v = (W - 1 + 2e-4 - cx) / f, (yq - cy) / f
+        Xj[2 + 4 * k, 4] = np.array([u, v, 1.0]) * (1.5 + 0.1 * k)
+        queries.append((2 + 4 * k, 4, 0))
+    for k, xq in enumerate([5.4, 11.7, 20.1]):             # beyond the bottom border
+        u, v = (xq - cx) / f, (H - 1 + 2e-4 - cy) / f
+        Xj[3 + 4 * k, 9] = np.array([u, v, 1.0]) * (1.8 - 0.1 * k)
+        queries.append((3 + 4 * k, 9, 1))
+    mask = np.zeros((H, W), bool)
+    for (y, x, _) in queries:
+        mask[y, x] = True
+    K = 20
+    o = fwd(lib, Xii, Xj, K=K, max_theta=math.inf)
+    for (y, x, ax) in queries:
+        assert o["p"][y, x, ax] == (W - 1 if ax == 0 else H - 1), "held match not on the border"
+
+    def loss(Xi_, Xj_):
+        oo = fwd(lib, Xi_, Xj_, K=K, max_theta=math.inf)
+        d = oo["xhat"] - Xj_
+        return float((d * d).sum(-1)[mask].sum())
+
+    gx = 2.0 * (o["xhat"] - Xj) * mask[..., None]
+    dXi, dXj = oracle.match_bwd(Xii, Xj, o["p"], mask, None, gx, lib=lib)
+    dXj = dXj - gx
+    eps = 1e-6
+    checks = [("Xji", (y, x, c)) for (y, x, _) in queries for c in range(3)]
+    checks += [("Xii", (y, W - 1, c)) for y in range(2, 20, 3) for c in range(3)]
+    checks += [("Xii", (H - 1, x, c)) for x in range(4, 22, 3) for c in range(3)]
+    scale = max(np.abs(dXi).max(), np.abs(dXj).max())
+    for name, ix in checks:
+        A = Xii if name == "Xii" else Xj
+        Ap = A.copy(); Ap[ix] += eps
+        Am = A.copy(); Am[ix] -= eps
+        if name == "Xii":
+            fd = (loss(Ap, Xj) - loss(Am, Xj)) / (2 * eps)
+            g = dXi[ix]
+        else:
+            fd = (loss(Xii, Ap) - loss(Xii, Am)) / (2 * eps)
+            g = dXj[ix]
+        assert abs(fd - g) <= 2e-3 * max(abs(fd), 0.05 * scale), \
+            "held border FD %s%s: fd %.8g adjoint %.8g" % (name, ix, fd, g)
+
+
 ALL_PINS = [
     pin_identity, pin_pinhole, pin_brute_force, pin_depth_invariance, pin_border_angle,
     pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
     pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init,
-    pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian,
+    pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian, pin_bwd_held_border,
 ]

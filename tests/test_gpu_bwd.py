@@ -98,6 +98,13 @@ def test_fwd_bwd_full_size_sampled(m3s):
     ogx = 2.0 * (o["xhat"] - pair.Xji) * o["valid"][..., None]
     oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, o["p"], o["valid"], None, ogx)
     both = o["valid"] & res.valid.cpu().numpy().astype(bool)
+    # The exact sampler derivative is one-sided at bilinear cell edges, so a
+    # query whose p* lies within 1e-4 px of one may sit in different cells on
+    # the two sides: those are compared only through the L2 norm below.
+    frac = o["p"] - np.floor(o["p"])
+    edge = ((frac < 1e-4) | (frac > 1 - 1e-4)).any(-1)
+    print(dict(valid_both=int(both.sum()), cell_edge_excluded=int((both & edge).sum())))
+    both &= ~edge
     gj = gj.cpu().numpy()
     err = np.abs(gj - oj)[both].max() / np.abs(oj[both]).max()
     print(dict(max_rel_dXji_valid_both=float(err), rel_l2_dXii=rel_l2(gi.cpu().numpy(), oi)))

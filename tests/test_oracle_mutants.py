@@ -54,6 +54,8 @@ MUTANTS = {
     "bwd_one_row_derivative": [("drx[k] = (1 - b) * (R10[k] - R00[k]) + b * (R11[k] - R01[k]);",
                                 "drx[k] = (R10[k] - R00[k]);")],
     "bwd_drops_ray_norm": [("dXii[3 * cm[c] + k] -= (w[c] / rn) * out[k];", "dXii[3 * cm[c] + k] -= w[c] * out[k];")],
+    "bwd_ignores_hold": [("int held_x = p[2 * n] <= 0.0 || p[2 * n] >= W - 1.0;", "int held_x = 0;"),
+                         ("int held_y = p[2 * n + 1] <= 0.0 || p[2 * n + 1] >= H - 1.0;", "int held_y = 0;")],
     "bwd_corner_weights_swapped": [("double w[4] = {(1 - a) * (1 - b), a * (1 - b), (1 - a) * b, a * b};",
                                     "double w[4] = {(1 - a) * (1 - b), (1 - a) * b, a * (1 - b), a * b};")],
     "bwd_xhat_derivative_transposed": [("gp0 += dxx * gx[k];\n                gp1 += dxy * gx[k];",
