@@ -56,7 +56,7 @@ class PreparedPair:
 
     def __init__(self, m3s, lib, pair, device, want_xhat=False, K=None, r=None):
         import torch
-        from paper_2412_12392_amd import _lib, match as M
+        from paper_2412_12392_amd import _lib, binding as M
         t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
         self.H, self.W = pair.H, pair.W
         self.t = dict(Xii=t(pair.Xii), Xji=t(pair.Xji), Dii=t(pair.Dii), Dji=t(pair.Dji), Qii=t(pair.Qii),
@@ -150,6 +150,24 @@ def main():
                 "kernel_avg_us": round(kt["fwd"] * 1e3, 2), "prep_avg_us": round(kt["prep"] * 1e3, 2),
                 "path_achieved_GBs": round(alg_bytes / ((kt["fwd"] + kt["prep"]) * 1e-3) / 1e9, 1)}
     log("kernel timing: fwd %.2f us, prep %.2f us" % (kt["fwd"] * 1e3, kt["prep"] * 1e3))
+
+    # Forward kernel time per tile configuration (0-2: refine from global
+    # memory; 3-4: refine region staged in LDS), same pool and steps.
+    sweep = {}
+    for tc in range(5):
+        os.environ["M3S_TILE_CONFIG"] = str(tc)
+        lib.m3s_timing_reset()
+        lib.m3s_timing_enable(1)
+        for k in range(min(args.steps, 30)):
+            fwd_step(k)
+        torch.cuda.synchronize()
+        lib.m3s_timing_enable(0)
+        tot, cnt = ctypes.c_double(), ctypes.c_int64()
+        lib.m3s_timing_read(b"fwd", ctypes.byref(tot), ctypes.byref(cnt))
+        sweep[str(tc)] = round(tot.value / max(cnt.value, 1) * 1e3, 2)
+    os.environ.pop("M3S_TILE_CONFIG", None)
+    roofline["fwd_us_by_tile_config"] = sweep
+    log("fwd kernel us by tile config:", sweep)
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "matches/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(ms_per_step, 5), "higher_is_better": True,

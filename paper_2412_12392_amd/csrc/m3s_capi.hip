@@ -135,9 +135,9 @@ EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P,
 
 int env_tile_config() {
     const char* s = std::getenv("M3S_TILE_CONFIG");
-    if (!s) return 0;
+    if (!s) return m3s::kDefaultTileConfig;
     int v = std::atoi(s);
-    return (v >= 0 && v < m3s::kNumTileConfigs) ? v : 0;
+    return (v >= 0 && v < m3s::kNumTileConfigs) ? v : m3s::kDefaultTileConfig;
 }
 
 // ---------------------------------------------------------------- batched state

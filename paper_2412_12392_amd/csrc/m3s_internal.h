@@ -8,9 +8,13 @@
 
 namespace m3s {
 
-// Tile configurations of the forward kernels (query tile TX x TY, 256 lanes).
-constexpr int kNumTileConfigs = 3;
+// Tile configurations of the forward kernels (query tile TX x TY, 256 lanes):
+// 0: 32x8, 1: 16x16, 2: 64x4 with the refine reading global memory;
+// 3: 16x16, 4: 32x8 with the refine region staged in LDS (D = 24 only).
+constexpr int kNumTileConfigs = 5;
+constexpr int kDefaultTileConfig = 3;
 void tile_shape(int tile_config, int* tx, int* ty);
+bool tile_uses_lds(int tile_config);
 
 // Optional per-kernel event timing (implemented in m3s_capi.hip).  Both calls
 // are no-ops unless timing is enabled and the stream is not being captured.

@@ -16,6 +16,9 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <climits>
+#include <type_traits>
+
 #include "m3s_device.h"
 #include "m3s_internal.h"
 
@@ -91,9 +94,17 @@ struct QueryDesc<0> {
     }
 };
 
-// Match query pixel (x, y) of edge A and write its outputs.
-template <int DT>
-__device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
+// Per-query state between the phases of the forward.
+struct QState {
+    float px, py;     // p* (clamped to the image)
+    float th;         // residual angle
+    float3 xq;        // query point x_n
+    bool good;        // finite, non-zero query point and initial pixel
+};
+
+// Phase 1: Levenberg-Marquardt on Eq. 2, residual angle (Eq. 3) and xhat.
+// Writes p, theta, xhat; a bad query also gets its final idx / valid.
+__device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState& q) {
     const int H = A.H, W = A.W;
     const long n = (long)y * W + x;
     float3 xq = load_point(A.Xji, n);
@@ -110,7 +121,10 @@ __device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
     float px = clampf(px0, 0.f, (float)(W - 1)), py = clampf(py0, 0.f, (float)(H - 1));
     float n2 = xq.x * xq.x + xq.y * xq.y + xq.z * xq.z;
     if (!finite3(xq) || !(n2 > 0.f) || !isfinite(n2)) bad = true;
+    q.xq = xq;
+    q.good = !bad;
     if (bad) {
+        q.px = px; q.py = py; q.th = INFINITY;
         reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
         A.idx[n] = -1;
         A.valid[n] = 0;
@@ -120,15 +134,10 @@ __device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
     }
     float inv = rsq(n2);
     float3 t = f3(xq.x * inv, xq.y * inv, xq.z * inv);
-
-    // Levenberg-Marquardt on Eq. 2.
     float c = lm_project(A.rays, H, W, A.K, A.lambda0, t, px, py);
     reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
-
-    // Residual angle, Eq. 3 solved for theta.
     float th = 2.0f * asinf(fminf(1.0f, sqrtf(c) * 0.5f));
     if (A.theta) A.theta[n] = th;
-
     if (A.xhat) {
         int x0 = min((int)floorf(px), W - 2), y0 = min((int)floorf(py), H - 2);
         float a = px - (float)x0, b = py - (float)y0;
@@ -140,11 +149,18 @@ __device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
         A.xhat[3 * n + 1] = w00 * X00.y + w10 * X10.y + w01 * X01.y + w11 * X11.y;
         A.xhat[3 * n + 2] = w00 * X00.z + w10 * X10.z + w01 * X01.z + w11 * X11.z;
     }
+    q.px = px; q.py = py; q.th = th;
+}
 
-    // Feature refine: first maximum of the raw dot product over the window,
-    // row-major, around p* rounded half up.
-    const int r = A.r;
-    int mx0 = (int)floorf(px + 0.5f), my0 = (int)floorf(py + 0.5f);
+// Refine window centre: p* rounded half up.
+__device__ __forceinline__ int round_half_up(float v) { return (int)floorf(v + 0.5f); }
+
+// Phase 2 (global memory): first maximum of the raw dot product over the
+// window, row-major.
+template <int DT>
+__device__ __forceinline__ long refine_global(const EdgeArgs& A, long n, const QState& q) {
+    const int H = A.H, W = A.W, r = A.r;
+    int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
     QueryDesc<DT> qd;
     qd.load(A.Dji, n, A.D);
     float best = -INFINITY;
@@ -160,17 +176,67 @@ __device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
             if (s > best) { best = s; bi = m; }
         }
     }
+    return bi;
+}
 
-    // Gates: residual angle, match confidence (Sec. 3.3), 3D distance (Sec. 3.2).
-    bool ok = bi >= 0 && th <= A.max_theta;
+// Phase 2 (LDS): the same scan over a staged region of D^i_i held as six
+// float4 planes (plane k holds descriptor floats 4k..4k+3 of every region
+// pixel at a stride of 16 bytes, so neighbouring lanes read neighbouring
+// 16-byte words).  Same products in the same order as refine_global.
+template <int REGION>
+__device__ __forceinline__ long refine_lds(const EdgeArgs& A, long n, const QState& q, const float4* __restrict__ sdesc,
+                                           int rx0, int ry0, int rw) {
+    const int H = A.H, W = A.W, r = A.r;
+    int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
+    QueryDesc<24> qd;
+    qd.load(A.Dji, n, 24);
+    float best = -INFINITY;
+    long bi = -1;
+    for (int dy = -r; dy <= r; ++dy) {
+        int my = my0 + dy;
+        if (my < 0 || my >= H) continue;
+        const int row = (my - ry0) * rw - rx0;
+        for (int dx = -r; dx <= r; ++dx) {
+            int mx = mx0 + dx;
+            if (mx < 0 || mx >= W) continue;
+            const float4* d = sdesc + row + mx;
+            float acc = 0.f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                float4 v = d[k * REGION];
+                acc = fmaf(qd.q[4 * k], v.x, acc);
+                acc = fmaf(qd.q[4 * k + 1], v.y, acc);
+                acc = fmaf(qd.q[4 * k + 2], v.z, acc);
+                acc = fmaf(qd.q[4 * k + 3], v.w, acc);
+            }
+            if (acc > best) { best = acc; bi = (long)my * W + mx; }
+        }
+    }
+    return bi;
+}
+
+// Phase 3: gates (residual angle, match confidence of Sec. 3.3, 3D distance
+// of Sec. 3.2) and the refined index.
+__device__ __forceinline__ void finish(const EdgeArgs& A, long n, const QState& q, long bi) {
+    bool ok = bi >= 0 && q.th <= A.max_theta;
     if (ok && A.Qii) ok = sqrtf(A.Qii[bi] * A.Qji[n]) >= A.conf_min;
     if (ok && A.max_dist < INFINITY) {
         float3 xr = load_point(A.Xii, bi);
-        float d0 = xr.x - xq.x, d1 = xr.y - xq.y, d2 = xr.z - xq.z;
+        float d0 = xr.x - q.xq.x, d1 = xr.y - q.xq.y, d2 = xr.z - q.xq.z;
         ok = sqrtf(d0 * d0 + d1 * d1 + d2 * d2) <= A.max_dist;
     }
     A.idx[n] = (int32_t)bi;
     A.valid[n] = ok ? 1 : 0;
+}
+
+// One query end to end through global memory.
+template <int DT>
+__device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
+    QState q;
+    lm_phase(A, x, y, q);
+    if (!q.good) return;
+    const long n = (long)y * A.W + x;
+    finish(A, n, q, refine_global<DT>(A, n, q));
 }
 
 template <int TX, int TY, int DT>
@@ -179,6 +245,87 @@ __global__ void __launch_bounds__(TX * TY) fwd_kernel(EdgeArgs A) {
     int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
     if (x >= A.W || y >= A.H) return;
     match_query<DT>(A, x, y);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// Region pixels of the LDS refine: 832 px x 96 B = 78 KiB, two workgroups per CU.
+constexpr int kRegionPx = 832;
+
+// LDS needed by one tile of the LDS path.
+struct TileLds {
+    float4 desc[6 * kRegionPx];
+    int box[4 * 16];
+};
+
+// One TX x TY query tile with the LDS refine.  Every thread of the block
+// calls this (threads outside the image skip the work but join the
+// barriers).  The refine region is the bounding box of the windows of the
+// tile's good queries; if it exceeds kRegionPx pixels the tile refines from
+// global memory instead.
+template <int TX, int TY>
+__device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, TileLds& S) {
+    constexpr int NT = TX * TY;
+    const int tid = threadIdx.x;
+    const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
+    const bool inside = x < A.W && y < A.H;
+    QState q;
+    q.good = false;
+    if (inside) lm_phase(A, x, y, q);
+    const int r = A.r, W = A.W, H = A.H;
+    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    if (q.good) {
+        int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
+        lx = max(mx0 - r, 0); hx = min(mx0 + r, W - 1);
+        ly = max(my0 - r, 0); hy = min(my0 + r, H - 1);
+    }
+    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) { S.box[4 * wv] = lx; S.box[4 * wv + 1] = hx; S.box[4 * wv + 2] = ly; S.box[4 * wv + 3] = hy; }
+    __syncthreads();
+    lx = S.box[0]; hx = S.box[1]; ly = S.box[2]; hy = S.box[3];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) {
+        lx = min(lx, S.box[4 * w]); hx = max(hx, S.box[4 * w + 1]);
+        ly = min(ly, S.box[4 * w + 2]); hy = max(hy, S.box[4 * w + 3]);
+    }
+    const int rw = hx - lx + 1, rh = hy - ly + 1;
+    const bool any = hx >= lx;
+    const bool use_lds = any && rw * rh <= kRegionPx;
+    if (use_lds) {
+        const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
+        const int row_chunks = rw * 6;
+        for (int ry = 0; ry < rh; ++ry) {
+            const float4* src = src4 + ((long)(ly + ry) * W + lx) * 6;
+            for (int c = tid; c < row_chunks; c += NT) {
+                int rx = c / 6;
+                int k = c - 6 * rx;
+                S.desc[k * kRegionPx + ry * rw + rx] = src[c];
+            }
+        }
+    }
+    __syncthreads();
+    if (q.good) {
+        const long n = (long)y * W + x;
+        long bi = use_lds ? refine_lds<kRegionPx>(A, n, q, S.desc, lx, ly, rw) : refine_global<24>(A, n, q);
+        finish(A, n, q, bi);
+    }
+    __syncthreads();  // the next tile may overwrite S
+}
+
+template <int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) fwd_lds_kernel(EdgeArgs A) {
+    __shared__ TileLds S;
+    tile_lds<TX, TY>(A, blockIdx.x, blockIdx.y, S);
 }
 
 // ---------------------------------------------------------------- batched
@@ -193,8 +340,7 @@ __device__ __forceinline__ int find_edge(const EdgeArgs* __restrict__ E, int n_e
     return lo;
 }
 
-// One block of 256 pixels per prep tile; prep tiles of edge e start at
-// prep_begin[e] (stored in EdgeArgs::tiles_x of the prep table copy).
+// One block of 256 pixels per prep tile; prep tiles of edge e start at prep_begin[e].
 __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __restrict__ E, const int32_t* __restrict__ prep_begin,
                                                            int n_edges) {
     int blk = blockIdx.x;
@@ -209,10 +355,14 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
     prep_pixel(A.Xii, const_cast<float4*>(A.rays), A.H, A.W, (int)(m % A.W), (int)(m / A.W));
 }
 
-template <int TX, int TY, int DT>
+// Persistent forward over all edges: workgroups pop tile ids from a counter
+// until none is left (every workgroup exits once the counter passes the last
+// tile).  LDS tiles need D = 24 and 16-byte aligned descriptors on every edge.
+template <int TX, int TY, int DT, bool LDS>
 __global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
                                                                int32_t* __restrict__ counter) {
     __shared__ int s_tile;
+    __shared__ typename std::conditional<LDS, TileLds, int>::type S;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
@@ -220,17 +370,15 @@ __global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __
         __syncthreads();
         if (tile >= total_tiles) return;
         int e = find_edge(E, n_edges, tile);
-        EdgeArgs A = E[e];
+        const EdgeArgs A = E[e];
         int local = tile - A.tile_begin;
         int ty = local / A.tiles_x, tx = local - ty * A.tiles_x;
-        int x = tx * TX + (int)(threadIdx.x % TX);
-        int y = ty * TY + (int)(threadIdx.x / TX);
-        if (x < A.W && y < A.H) {
-            if (DT != 0 && A.D != DT) {
-                match_query<0>(A, x, y);
-            } else {
-                match_query<DT>(A, x, y);
-            }
+        if constexpr (LDS) {
+            tile_lds<TX, TY>(A, tx, ty, S);
+        } else {
+            int x = tx * TX + (int)(threadIdx.x % TX);
+            int y = ty * TY + (int)(threadIdx.x / TX);
+            if (x < A.W && y < A.H) match_query<DT>(A, x, y);
         }
     }
 }
@@ -361,33 +509,48 @@ hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t
 }
 
 template <int TX, int TY>
-static hipError_t launch_fwd_tile(const EdgeArgs& A, bool desc_regs, hipStream_t s) {
+static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, bool lds, hipStream_t s) {
     dim3 grid((A.W + TX - 1) / TX, (A.H + TY - 1) / TY);
-    if (desc_regs && A.D == 24)
+    if (lds && desc_regs)
+        fwd_lds_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A);
+    else if (desc_regs)
         fwd_kernel<TX, TY, 24><<<grid, TX * TY, 0, s>>>(A);
     else
         fwd_kernel<TX, TY, 0><<<grid, TX * TY, 0, s>>>(A);
-    return hipGetLastError();
-}
-
-hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s) {
-    hipError_t e;
-    timer_begin("fwd", s);
-    switch (tile_config) {
-        case 1: e = launch_fwd_tile<16, 16>(A, desc_regs, s); break;
-        case 2: e = launch_fwd_tile<64, 4>(A, desc_regs, s); break;
-        default: e = launch_fwd_tile<32, 8>(A, desc_regs, s); break;
-    }
-    timer_end(s);
-    return e;
 }
 
 void tile_shape(int tile_config, int* tx, int* ty) {
     switch (tile_config) {
-        case 1: *tx = 16; *ty = 16; return;
+        case 1: case 3: *tx = 16; *ty = 16; return;
         case 2: *tx = 64; *ty = 4; return;
         default: *tx = 32; *ty = 8; return;
     }
+}
+
+bool tile_uses_lds(int tile_config) { return tile_config >= 3; }
+
+hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s) {
+    timer_begin("fwd", s);
+    switch (tile_config) {
+        case 1: launch_fwd_tile<16, 16>(A, desc_regs, false, s); break;
+        case 2: launch_fwd_tile<64, 4>(A, desc_regs, false, s); break;
+        case 3: launch_fwd_tile<16, 16>(A, desc_regs, true, s); break;
+        case 4: launch_fwd_tile<32, 8>(A, desc_regs, true, s); break;
+        default: launch_fwd_tile<32, 8>(A, desc_regs, false, s); break;
+    }
+    timer_end(s);
+    return hipGetLastError();
+}
+
+template <int TX, int TY>
+static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_tiles, int32_t* counter, int grid,
+                                bool desc_regs, bool lds, hipStream_t s) {
+    if (lds && desc_regs)
+        batched_fwd_kernel<TX, TY, 24, true><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+    else if (desc_regs)
+        batched_fwd_kernel<TX, TY, 24, false><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+    else
+        batched_fwd_kernel<TX, TY, 0, false><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
 }
 
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
@@ -400,18 +563,11 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
     timer_end(s);
     timer_begin("batched_fwd", s);
     switch (tile_config) {
-        case 1:
-            if (desc_regs) batched_fwd_kernel<16, 16, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            else batched_fwd_kernel<16, 16, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            break;
-        case 2:
-            if (desc_regs) batched_fwd_kernel<64, 4, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            else batched_fwd_kernel<64, 4, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            break;
-        default:
-            if (desc_regs) batched_fwd_kernel<32, 8, 24><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            else batched_fwd_kernel<32, 8, 0><<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
-            break;
+        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
+        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
+        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, true, s); break;
+        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, true, s); break;
+        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
     }
     timer_end(s);
     return hipGetLastError();

@@ -47,19 +47,30 @@ def result_numpy(res):
     return out
 
 
-def compare(gpu: dict, ora: dict, label: str = "", strict: bool = True) -> dict:
-    """Compare one pair's outputs; returns the statistics (asserts if strict)."""
+def compare(gpu: dict, ora: dict, label: str = "", strict: bool = True, p_theta_max: float | None = None) -> dict:
+    """Compare one pair's outputs; returns the statistics (asserts if strict).
+
+    p_theta_max: compare p* and theta only where the oracle's residual angle is
+    at most this (for runs with the angle gate off, where matches beyond the
+    image border are valid but their p* is not a zero-residual root).
+    """
     vg, vo = gpu["valid"], ora["valid"]
     both = vg & vo
     n = vg.size
     agree = float((vg == vo).mean())
     st = dict(label=label, queries=int(n), valid_oracle=int(vo.sum()), valid_gpu=int(vg.sum()),
               valid_both=int(both.sum()), valid_agreement=agree)
-    if both.any():
-        dp = np.abs(gpu["p"] - ora["p"]).max(-1)[both]
+    cont = both if p_theta_max is None else both & (ora["theta"] <= p_theta_max)
+    if p_theta_max is not None:
+        st["p_compared"] = int(cont.sum())
+    if cont.any():
+        dp = np.abs(gpu["p"] - ora["p"]).max(-1)[cont]
         st["max_dp_px"] = float(dp.max())
         if "theta" in gpu:
-            st["max_dtheta"] = float(np.abs(gpu["theta"] - ora["theta"])[both].max())
+            st["max_dtheta"] = float(np.abs(gpu["theta"][cont] - ora["theta"][cont]).max())
+    else:
+        st.update(max_dp_px=0.0, max_dtheta=0.0)
+    if both.any():
         frac = ora["p"] - np.floor(ora["p"])
         straddle = (np.abs(frac - 0.5) < STRADDLE).any(-1)
         comparable = both & (ora["gap"] > GAP_MIN) & ~straddle
@@ -68,7 +79,7 @@ def compare(gpu: dict, ora: dict, label: str = "", strict: bool = True) -> dict:
         st["idx_excluded_straddle"] = int((both & straddle).sum())
         st["idx_mismatch"] = int((gpu["idx"] != ora["idx"])[comparable].sum())
     else:
-        st.update(max_dp_px=0.0, max_dtheta=0.0, idx_compared=0, idx_mismatch=0)
+        st.update(idx_compared=0, idx_mismatch=0)
     # Queries the oracle rejects as bad input must be rejected the same way.
     bad = ora["idx"] == -1
     st["bad_input_mismatch"] = int(((gpu["idx"] != -1) | vg)[bad].sum())
