@@ -49,11 +49,12 @@ extern "C" {
 #define M3S_MAX_RADIUS 8      /* largest refine radius r */
 #define M3S_MAX_ITER 1000     /* largest LM iteration count K */
 #define M3S_MAX_DESC 64       /* largest descriptor dimension D */
+#define M3S_MAX_PIXELS (1 << 26)  /* largest H * W of one frame (67,108,864 pixels) */
 
 typedef enum {
     M3S_OK = 0,
     M3S_ERR_NULL = 1,         /* a required pointer is NULL */
-    M3S_ERR_SHAPE = 2,        /* H, W < 2, D out of [1, M3S_MAX_DESC], size overflow */
+    M3S_ERR_SHAPE = 2,        /* H, W < 2, H * W > M3S_MAX_PIXELS, D out of [1, M3S_MAX_DESC] */
     M3S_ERR_PARAM = 3,        /* a parameter out of its documented range */
     M3S_ERR_WORKSPACE = 4,    /* workspace NULL, misaligned (256 B) or too small */
     M3S_ERR_HIP = 5,          /* a HIP runtime call failed */

@@ -86,7 +86,7 @@ m3s_status check_params(const m3s_params* P) {
 
 m3s_status check_shape(int32_t H, int32_t W) {
     if (H < 2 || W < 2) return fail(M3S_ERR_SHAPE, "H and W must be >= 2 (got %d x %d)", H, W);
-    if ((int64_t)H * W > (int64_t)INT32_MAX / 4) return fail(M3S_ERR_SHAPE, "H * W too large (%lld)", (long long)H * W);
+    if ((int64_t)H * W > M3S_MAX_PIXELS) return fail(M3S_ERR_SHAPE, "H * W = %lld exceeds %d", (long long)H * W, M3S_MAX_PIXELS);
     return M3S_OK;
 }
 
@@ -353,7 +353,7 @@ void m3s_default_params(m3s_params* P) {
 }
 
 size_t m3s_workspace_bytes(const m3s_pair* pair, const m3s_params*) {
-    if (!pair || pair->H < 2 || pair->W < 2 || (int64_t)pair->H * pair->W > (int64_t)INT32_MAX / 4) return 0;
+    if (!pair || pair->H < 2 || pair->W < 2 || (int64_t)pair->H * pair->W > M3S_MAX_PIXELS) return 0;
     return ray_bytes(pair->H, pair->W);
 }
 

@@ -60,28 +60,43 @@ __device__ __forceinline__ float3 unit_ray(float3 x) {
     return f3(x.x * inv, x.y * inv, x.z * inv);
 }
 
+// What the LM step needs from one evaluation of the ray error: the cost and
+// the Gauss-Newton blocks J^T J (without damping) and J^T e.
 struct Sample {
-    float c;          // ray error |e|^2 (inf for a degenerate sample)
-    float e0, e1, e2; // e = psi_hat - t
-    float jx0, jx1, jx2, jy0, jy1, jy2;  // d psi_hat / d p (gradient-image Jacobian)
+    float c;                // ray error |e|^2 (inf for a degenerate sample)
+    float a00, a01, a11;    // J^T J
+    float g0, g1;           // J^T e
 };
 
+// Ray records are read with buffer loads: one resource descriptor (base,
+// byte size) in scalar registers, a 32-bit byte offset per lane, immediate
+// offsets for the three float4s of a record.  Reads past the size return 0.
+// The host keeps 48 * H * W below 2^32.
+using RayBuf = __amdgpu_buffer_rsrc_t;
+
+__device__ __forceinline__ RayBuf ray_buffer(const float4* rec, int H, int W) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(rec), (short)0,
+                                             (int)((uint32_t)H * (uint32_t)W * (uint32_t)(kRecF4 * 16)), 0x00020000);
+}
+
+__device__ __forceinline__ float4 rec_load(RayBuf rb, uint32_t byte_off) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rb, byte_off, 0, 0));
+}
+
 // Ray error of Eq. 2 at pixel (px, py) (inside the domain) for target ray t.
-__device__ __forceinline__ void sample_ray_error(const float4* __restrict__ rec, int H, int W,
+__device__ __forceinline__ void sample_ray_error(RayBuf rec, int H, int W,
                                                  float px, float py, float3 t, Sample& s) {
     int x0 = min((int)floorf(px), W - 2);
     int y0 = min((int)floorf(py), H - 2);
     float a = px - (float)x0, b = py - (float)y0;
-    long m00 = (long)y0 * W + x0;
-    const float4* r00 = rec + kRecF4 * m00;
-    const float4* r10 = r00 + kRecF4;
-    const float4* r01 = r00 + (long)kRecF4 * W;
-    const float4* r11 = r01 + kRecF4;
+    const uint32_t rs = (uint32_t)kRecF4 * 16u;           // record stride (bytes)
+    const uint32_t o00 = ((uint32_t)y0 * (uint32_t)W + (uint32_t)x0) * rs;
+    const uint32_t o10 = o00 + rs, o01 = o00 + (uint32_t)W * rs, o11 = o01 + rs;
     float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
-    float4 A0 = r00[0], A1 = r00[1], A2 = r00[2];
-    float4 B0 = r10[0], B1 = r10[1], B2 = r10[2];
-    float4 C0 = r01[0], C1 = r01[1], C2 = r01[2];
-    float4 D0 = r11[0], D1 = r11[1], D2 = r11[2];
+    float4 A0 = rec_load(rec, o00), A1 = rec_load(rec, o00 + 16), A2 = rec_load(rec, o00 + 32);
+    float4 B0 = rec_load(rec, o10), B1 = rec_load(rec, o10 + 16), B2 = rec_load(rec, o10 + 32);
+    float4 C0 = rec_load(rec, o01), C1 = rec_load(rec, o01 + 16), C2 = rec_load(rec, o01 + 32);
+    float4 D0 = rec_load(rec, o11), D1 = rec_load(rec, o11 + 16), D2 = rec_load(rec, o11 + 32);
 #define M3S_BL(i, c) (w00 * A##i.c + w10 * B##i.c + w01 * C##i.c + w11 * D##i.c)
     float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
     float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
@@ -90,41 +105,38 @@ __device__ __forceinline__ void sample_ray_error(const float4* __restrict__ rec,
     float n2 = rx * rx + ry * ry + rz * rz;
     if (!(n2 > 0.0f) || !isfinite(n2)) {
         s.c = INFINITY;
-        s.e0 = s.e1 = s.e2 = 0.f;
-        s.jx0 = s.jx1 = s.jx2 = s.jy0 = s.jy1 = s.jy2 = 0.f;
+        s.a00 = s.a01 = s.a11 = s.g0 = s.g1 = 0.f;
         return;
     }
     float inv = rsq(n2);
     float p0 = rx * inv, p1 = ry * inv, p2 = rz * inv;
     float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
     float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
-    s.jx0 = (gxx - p0 * pgx) * inv;
-    s.jx1 = (gxy - p1 * pgx) * inv;
-    s.jx2 = (gxz - p2 * pgx) * inv;
-    s.jy0 = (gyx - p0 * pgy) * inv;
-    s.jy1 = (gyy - p1 * pgy) * inv;
-    s.jy2 = (gyz - p2 * pgy) * inv;
-    s.e0 = p0 - t.x;
-    s.e1 = p1 - t.y;
-    s.e2 = p2 - t.z;
-    s.c = s.e0 * s.e0 + s.e1 * s.e1 + s.e2 * s.e2;
+    // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
+    float jx0 = (gxx - p0 * pgx) * inv, jx1 = (gxy - p1 * pgx) * inv, jx2 = (gxz - p2 * pgx) * inv;
+    float jy0 = (gyx - p0 * pgy) * inv, jy1 = (gyy - p1 * pgy) * inv, jy2 = (gyz - p2 * pgy) * inv;
+    float e0 = p0 - t.x, e1 = p1 - t.y, e2 = p2 - t.z;
+    s.c = e0 * e0 + e1 * e1 + e2 * e2;
+    s.a00 = jx0 * jx0 + jx1 * jx1 + jx2 * jx2;
+    s.a01 = jx0 * jy0 + jx1 * jy1 + jx2 * jy2;
+    s.a11 = jy0 * jy0 + jy1 * jy1 + jy2 * jy2;
+    s.g0 = jx0 * e0 + jx1 * e1 + jx2 * e2;
+    s.g1 = jy0 * e0 + jy1 * e1 + jy2 * e2;
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
 // K Levenberg-Marquardt iterations from (px, py); returns the final cost.
-__device__ __forceinline__ float lm_project(const float4* __restrict__ rec, int H, int W, int K, float lambda0,
+__device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int H, int W, int K, float lambda0,
                                             float3 t, float& px, float& py) {
+    const RayBuf rec = ray_buffer(rays, H, W);
     Sample cur, nxt;
     sample_ray_error(rec, H, W, px, py, t, cur);
     float lambda = lambda0;
     const float xmax = (float)(W - 1), ymax = (float)(H - 1);
     for (int it = 0; it < K; ++it) {
-        float a00 = cur.jx0 * cur.jx0 + cur.jx1 * cur.jx1 + cur.jx2 * cur.jx2 + lambda;
-        float a01 = cur.jx0 * cur.jy0 + cur.jx1 * cur.jy1 + cur.jx2 * cur.jy2;
-        float a11 = cur.jy0 * cur.jy0 + cur.jy1 * cur.jy1 + cur.jy2 * cur.jy2 + lambda;
-        float g0 = cur.jx0 * cur.e0 + cur.jx1 * cur.e1 + cur.jx2 * cur.e2;
-        float g1 = cur.jy0 * cur.e0 + cur.jy1 * cur.e1 + cur.jy2 * cur.e2;
+        float a00 = cur.a00 + lambda, a01 = cur.a01, a11 = cur.a11 + lambda;
+        float g0 = cur.g0, g1 = cur.g1;
         float idet = rcp(a00 * a11 - a01 * a01);
         float dx = -(a11 * g0 - a01 * g1) * idet;
         float dy = -(a00 * g1 - a01 * g0) * idet;
@@ -140,12 +152,17 @@ __device__ __forceinline__ float lm_project(const float4* __restrict__ rec, int 
         }
         float qx = clampf(px + dx, 0.f, xmax), qy = clampf(py + dy, 0.f, ymax);
         sample_ray_error(rec, H, W, qx, qy, t, nxt);
-        if (nxt.c < cur.c) {
-            px = qx; py = qy; cur = nxt;
-            lambda *= 0.1f;
-        } else {
-            lambda *= 10.f;
-        }
+        // Accept on strictly lower cost: selects, no branch.
+        const bool acc = nxt.c < cur.c;
+        px = acc ? qx : px;
+        py = acc ? qy : py;
+        cur.c = acc ? nxt.c : cur.c;
+        cur.a00 = acc ? nxt.a00 : cur.a00;
+        cur.a01 = acc ? nxt.a01 : cur.a01;
+        cur.a11 = acc ? nxt.a11 : cur.a11;
+        cur.g0 = acc ? nxt.g0 : cur.g0;
+        cur.g1 = acc ? nxt.g1 : cur.g1;
+        lambda = acc ? lambda * 0.1f : lambda * 10.f;
     }
     return cur.c;
 }
