@@ -152,9 +152,9 @@ def main():
     log("kernel timing: fwd %.2f us, prep %.2f us" % (kt["fwd"] * 1e3, kt["prep"] * 1e3))
 
     # Forward kernel time per tile configuration (0-2: refine from global
-    # memory; 3-4: refine region staged in LDS), same pool and steps.
+    # memory; 3-4: refine region staged in LDS; 5: fp16 pre-filter), same pool and steps.
     sweep = {}
-    for tc in range(5):
+    for tc in range(6):
         os.environ["M3S_TILE_CONFIG"] = str(tc)
         lib.m3s_timing_reset()
         lib.m3s_timing_enable(1)

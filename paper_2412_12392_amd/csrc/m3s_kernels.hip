@@ -322,6 +322,215 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     __syncthreads();  // the next tile may overwrite S
 }
 
+// ---------------------------------------------------------------- fp16 pre-filtered refine
+//
+// Exact first-maximum refine with an fp16 pre-filter (D = 24, r <= 5).  The
+// staged region holds D^i_i in fp16 (three planes of eight halves: 48 B per
+// pixel), so one pass scores every window candidate with v_dot2_f32_f16.
+// Any candidate whose fp32 score could equal the fp32 maximum has an fp16
+// score within tau of the running fp16 maximum, where tau bounds twice the
+// sum of the fp16 error (conversion of both operands with round-to-nearest,
+// relative 2^-11, absolute 2^-14 for values that may flush, plus fp32
+// accumulation) and the fp32 error of the exact dot (24 u32 |q||d|).  Those
+// candidates are rescored exactly from global memory in row-major order with
+// the same products and order as every other refine path, so the result is
+// the same index.
+
+typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
+
+constexpr int kRegionPx16 = 832;          // 832 px x 48 B = 39 KiB: four workgroups per CU
+constexpr float kF16Max = 60000.f;        // larger magnitudes fall back to the exact scan
+constexpr float kU16 = 4.8828125e-4f;     // 2^-11
+constexpr float kU32x24 = 1.4305115e-6f;  // 24 * 2^-24
+constexpr float kFlush16 = 6.1035156e-5f; // 2^-14
+
+struct TileLds16 {
+    uint4 desc[3 * kRegionPx16];
+    int box[4 * 16];
+    float stat[3 * 16];                   // per wave: max partial |d|^2, max partial |d|_1, max |d_k|
+};
+
+__device__ __forceinline__ uint32_t pack_h2(float a, float b) {
+    h2_t v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ float dot16(const uint32_t* q16, uint4 a, uint4 b, uint4 c) {
+    float acc = 0.f;
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[0]), __builtin_bit_cast(h2_t, a.x), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[1]), __builtin_bit_cast(h2_t, a.y), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[2]), __builtin_bit_cast(h2_t, a.z), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[3]), __builtin_bit_cast(h2_t, a.w), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[4]), __builtin_bit_cast(h2_t, b.x), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[5]), __builtin_bit_cast(h2_t, b.y), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[6]), __builtin_bit_cast(h2_t, b.z), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[7]), __builtin_bit_cast(h2_t, b.w), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[8]), __builtin_bit_cast(h2_t, c.x), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[9]), __builtin_bit_cast(h2_t, c.y), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[10]), __builtin_bit_cast(h2_t, c.z), acc, false);
+    acc = __builtin_amdgcn_fdot2(__builtin_bit_cast(h2_t, q16[11]), __builtin_bit_cast(h2_t, c.w), acc, false);
+    return acc;
+}
+
+// Exact fp32 score of reference pixel m, same products and order as QueryDesc<24>::dot.
+__device__ __forceinline__ float exact24(const float* __restrict__ q, const float* __restrict__ Dii, long m) {
+    const float4* s = reinterpret_cast<const float4*>(Dii + 24 * m);
+    float acc = 0.f;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        float4 v = s[k];
+        acc = fmaf(q[4 * k], v.x, acc);
+        acc = fmaf(q[4 * k + 1], v.y, acc);
+        acc = fmaf(q[4 * k + 2], v.z, acc);
+        acc = fmaf(q[4 * k + 3], v.w, acc);
+    }
+    return acc;
+}
+
+// dnorm: bound on |d| over the region, dl1: bound on |d|_1.
+__device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QState& q, const uint4* __restrict__ sd,
+                                           int rx0, int ry0, int rw, float dnorm, float dl1) {
+    const int H = A.H, W = A.W, r = A.r, side = 2 * r + 1;
+    int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
+    QueryDesc<24> qd;
+    qd.load(A.Dji, n, 24);
+    float qn2 = 0.f, ql1 = 0.f, qmax = 0.f;
+    uint32_t q16[12];
+#pragma unroll
+    for (int k = 0; k < 24; ++k) {
+        qn2 = fmaf(qd.q[k], qd.q[k], qn2);
+        ql1 += fabsf(qd.q[k]);
+        qmax = fmaxf(qmax, fabsf(qd.q[k]));
+    }
+#pragma unroll
+    for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k], qd.q[2 * k + 1]);
+    const float qn = sqrtf(qn2);
+    if (!(qmax <= kF16Max) || !isfinite(ql1)) return refine_global<24>(A, n, q);
+    const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (ql1 + dl1);
+    const float eps32 = kU32x24 * qn * dnorm;
+    const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
+
+    // Pass 1: fp16 scores; seed the running maximum with the window centre.
+    const uint4* c0 = sd + (my0 - ry0) * rw + (mx0 - rx0);
+    float run = dot16(q16, c0[0], c0[kRegionPx16], c0[2 * kRegionPx16]);
+    uint64_t mask0 = 0, mask1 = 0;
+    int k = 0;
+    for (int dy = -r; dy <= r; ++dy) {
+        int my = my0 + dy;
+        const bool row_in = my >= 0 && my < H;
+        const int row = (my - ry0) * rw - rx0;
+        for (int dx = -r; dx <= r; ++dx, ++k) {
+            int mx = mx0 + dx;
+            if (!row_in || mx < 0 || mx >= W) continue;
+            const uint4* d = sd + row + mx;
+            float s16 = dot16(q16, d[0], d[kRegionPx16], d[2 * kRegionPx16]);
+            run = fmaxf(run, s16);
+            if (s16 >= run - tau) {
+                if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
+            }
+        }
+    }
+    // Pass 2: exact scores of the survivors in row-major order.
+    float best = -INFINITY;
+    long bi = -1;
+    while (mask0 | mask1) {
+        int kk;
+        if (mask0) { kk = __builtin_ctzll(mask0); mask0 &= mask0 - 1; }
+        else { kk = 64 + __builtin_ctzll(mask1); mask1 &= mask1 - 1; }
+        int dy = kk / side, dx = kk - dy * side;
+        long m = (long)(my0 + dy - r) * W + (mx0 + dx - r);
+        float sc = exact24(qd.q, A.Dii, m);
+        if (sc > best) { best = sc; bi = m; }
+    }
+    return bi;
+}
+
+// One TX x TY tile with the fp16 pre-filtered refine.  Falls back to the exact
+// global scan for the whole tile when the region does not fit, r > 5, or a
+// region value is non-finite or too large for fp16.
+template <int TX, int TY>
+__device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16& S) {
+    constexpr int NT = TX * TY;
+    const int tid = threadIdx.x;
+    const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
+    const bool inside = x < A.W && y < A.H;
+    QState q;
+    q.good = false;
+    if (inside) lm_phase(A, x, y, q);
+    const int r = A.r, W = A.W, H = A.H;
+    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    if (q.good) {
+        int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
+        lx = max(mx0 - r, 0); hx = min(mx0 + r, W - 1);
+        ly = max(my0 - r, 0); hy = min(my0 + r, H - 1);
+    }
+    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    const int wv = tid >> 6;
+    if ((tid & 63) == 0) { S.box[4 * wv] = lx; S.box[4 * wv + 1] = hx; S.box[4 * wv + 2] = ly; S.box[4 * wv + 3] = hy; }
+    __syncthreads();
+    lx = S.box[0]; hx = S.box[1]; ly = S.box[2]; hy = S.box[3];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) {
+        lx = min(lx, S.box[4 * w]); hx = max(hx, S.box[4 * w + 1]);
+        ly = min(ly, S.box[4 * w + 2]); hy = max(hy, S.box[4 * w + 3]);
+    }
+    const int rw = hx - lx + 1, rh = hy - ly + 1;
+    const bool any = hx >= lx;
+    bool use16 = any && rw * rh <= kRegionPx16 && r <= 5;
+    float pn2 = 0.f, pl1 = 0.f, pmax = 0.f;
+    if (use16) {
+        // Stage: thread c handles pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7).
+        const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
+        const int row_chunks = rw * 3;
+        for (int ry = 0; ry < rh; ++ry) {
+            const float4* src = src4 + ((long)(ly + ry) * W + lx) * 6;
+            for (int c = tid; c < row_chunks; c += NT) {
+                int rx = c / 3;
+                int k = c - 3 * rx;
+                float4 u = src[6 * rx + 2 * k], v = src[6 * rx + 2 * k + 1];
+                float e2 = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w + v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+                float e1 = fabsf(u.x) + fabsf(u.y) + fabsf(u.z) + fabsf(u.w) + fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
+                float em = fmaxf(fmaxf(fmaxf(fabsf(u.x), fabsf(u.y)), fmaxf(fabsf(u.z), fabsf(u.w))),
+                                 fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+                // NaN propagates through the sums and fails the range test below.
+                pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
+                pl1 = fmaxf(pl1, isfinite(e1) ? e1 : INFINITY);
+                pmax = fmaxf(pmax, (em == em) ? em : INFINITY);
+                S.desc[k * kRegionPx16 + ry * rw + rx] =
+                    make_uint4(pack_h2(u.x, u.y), pack_h2(u.z, u.w), pack_h2(v.x, v.y), pack_h2(v.z, v.w));
+            }
+        }
+    }
+    // Region bounds: |d|^2 <= 3 max partial, |d|_1 <= 3 max partial.
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
+        pl1 = fmaxf(pl1, __shfl_xor(pl1, o, 64));
+        pmax = fmaxf(pmax, __shfl_xor(pmax, o, 64));
+    }
+    if ((tid & 63) == 0) { S.stat[3 * wv] = pn2; S.stat[3 * wv + 1] = pl1; S.stat[3 * wv + 2] = pmax; }
+    __syncthreads();
+    pn2 = S.stat[0]; pl1 = S.stat[1]; pmax = S.stat[2];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) {
+        pn2 = fmaxf(pn2, S.stat[3 * w]); pl1 = fmaxf(pl1, S.stat[3 * w + 1]); pmax = fmaxf(pmax, S.stat[3 * w + 2]);
+    }
+    use16 = use16 && pmax <= kF16Max && isfinite(pn2) && isfinite(pl1);
+    if (q.good) {
+        const long n = (long)y * W + x;
+        long bi = use16 ? refine_f16(A, n, q, S.desc, lx, ly, rw, sqrtf(3.f * pn2) * 1.0001f, 3.f * pl1 * 1.0001f)
+                        : refine_global<24>(A, n, q);
+        finish(A, n, q, bi);
+    }
+    __syncthreads();  // the next tile may overwrite S
+}
+
+template <int TX, int TY>
+__global__ void __launch_bounds__(TX * TY) fwd_f16_kernel(EdgeArgs A) {
+    __shared__ TileLds16 S;
+    tile_f16<TX, TY>(A, blockIdx.x, blockIdx.y, S);
+}
+
 template <int TX, int TY>
 __global__ void __launch_bounds__(TX * TY) fwd_lds_kernel(EdgeArgs A) {
     __shared__ TileLds S;
@@ -358,11 +567,12 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
 // Persistent forward over all edges: workgroups pop tile ids from a counter
 // until none is left (every workgroup exits once the counter passes the last
 // tile).  LDS tiles need D = 24 and 16-byte aligned descriptors on every edge.
-template <int TX, int TY, int DT, bool LDS>
+// MODE 0: refine from global memory; 1: fp32 region in LDS; 2: fp16 pre-filter.
+template <int TX, int TY, int DT, int MODE>
 __global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
                                                                int32_t* __restrict__ counter) {
     __shared__ int s_tile;
-    __shared__ typename std::conditional<LDS, TileLds, int>::type S;
+    __shared__ typename std::conditional<MODE == 1, TileLds, typename std::conditional<MODE == 2, TileLds16, int>::type>::type S;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
@@ -373,8 +583,10 @@ __global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __
         const EdgeArgs A = E[e];
         int local = tile - A.tile_begin;
         int ty = local / A.tiles_x, tx = local - ty * A.tiles_x;
-        if constexpr (LDS) {
+        if constexpr (MODE == 1) {
             tile_lds<TX, TY>(A, tx, ty, S);
+        } else if constexpr (MODE == 2) {
+            tile_f16<TX, TY>(A, tx, ty, S);
         } else {
             int x = tx * TX + (int)(threadIdx.x % TX);
             int y = ty * TY + (int)(threadIdx.x / TX);
@@ -509,9 +721,11 @@ hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t
 }
 
 template <int TX, int TY>
-static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, bool lds, hipStream_t s) {
+static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, int mode, hipStream_t s) {
     dim3 grid((A.W + TX - 1) / TX, (A.H + TY - 1) / TY);
-    if (lds && desc_regs)
+    if (mode == 2 && desc_regs)
+        fwd_f16_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A);
+    else if (mode == 1 && desc_regs)
         fwd_lds_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A);
     else if (desc_regs)
         fwd_kernel<TX, TY, 24><<<grid, TX * TY, 0, s>>>(A);
@@ -521,7 +735,7 @@ static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, bool lds, hipStre
 
 void tile_shape(int tile_config, int* tx, int* ty) {
     switch (tile_config) {
-        case 1: case 3: *tx = 16; *ty = 16; return;
+        case 1: case 3: case 5: *tx = 16; *ty = 16; return;
         case 2: *tx = 64; *ty = 4; return;
         default: *tx = 32; *ty = 8; return;
     }
@@ -532,11 +746,12 @@ bool tile_uses_lds(int tile_config) { return tile_config >= 3; }
 hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s) {
     timer_begin("fwd", s);
     switch (tile_config) {
-        case 1: launch_fwd_tile<16, 16>(A, desc_regs, false, s); break;
-        case 2: launch_fwd_tile<64, 4>(A, desc_regs, false, s); break;
-        case 3: launch_fwd_tile<16, 16>(A, desc_regs, true, s); break;
-        case 4: launch_fwd_tile<32, 8>(A, desc_regs, true, s); break;
-        default: launch_fwd_tile<32, 8>(A, desc_regs, false, s); break;
+        case 1: launch_fwd_tile<16, 16>(A, desc_regs, 0, s); break;
+        case 2: launch_fwd_tile<64, 4>(A, desc_regs, 0, s); break;
+        case 3: launch_fwd_tile<16, 16>(A, desc_regs, 1, s); break;
+        case 4: launch_fwd_tile<32, 8>(A, desc_regs, 1, s); break;
+        case 5: launch_fwd_tile<16, 16>(A, desc_regs, 2, s); break;
+        default: launch_fwd_tile<32, 8>(A, desc_regs, 0, s); break;
     }
     timer_end(s);
     return hipGetLastError();
@@ -544,13 +759,15 @@ hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStr
 
 template <int TX, int TY>
 static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_tiles, int32_t* counter, int grid,
-                                bool desc_regs, bool lds, hipStream_t s) {
-    if (lds && desc_regs)
-        batched_fwd_kernel<TX, TY, 24, true><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+                                bool desc_regs, int mode, hipStream_t s) {
+    if (mode == 2 && desc_regs)
+        batched_fwd_kernel<TX, TY, 24, 2><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+    else if (mode == 1 && desc_regs)
+        batched_fwd_kernel<TX, TY, 24, 1><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
     else if (desc_regs)
-        batched_fwd_kernel<TX, TY, 24, false><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+        batched_fwd_kernel<TX, TY, 24, 0><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
     else
-        batched_fwd_kernel<TX, TY, 0, false><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+        batched_fwd_kernel<TX, TY, 0, 0><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
 }
 
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
@@ -563,11 +780,12 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
     timer_end(s);
     timer_begin("batched_fwd", s);
     switch (tile_config) {
-        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
-        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
-        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, true, s); break;
-        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, true, s); break;
-        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, false, s); break;
+        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
+        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
+        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, s); break;
+        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, s); break;
+        case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, s); break;
+        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
     }
     timer_end(s);
     return hipGetLastError();

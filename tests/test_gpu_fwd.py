@@ -1,5 +1,6 @@
 """GPU forward parity: libm3s (fp32, gfx950) against the FP64 oracle, through the C ABI."""
 import functools
+import zlib
 import math
 import os
 
@@ -161,7 +162,7 @@ def test_tile_configs_bitwise_and_deterministic(m3s):
     pair = _pair(200, 264, 16)
     outs = []
     try:
-        for tc in ("0", "1", "2", "3", "4", "3"):
+        for tc in ("0", "1", "2", "3", "4", "5", "3"):
             os.environ["M3S_TILE_CONFIG"] = tc
             outs.append(run(m3s, pair))
     finally:
@@ -169,3 +170,57 @@ def test_tile_configs_bitwise_and_deterministic(m3s):
     for o in outs[1:]:
         for k in ("p", "idx", "valid", "theta", "xhat"):
             assert np.array_equal(outs[0][k], o[k], equal_nan=True), k
+
+
+def _run_cfg(m3s, pair, cfg, **prm):
+    os.environ["M3S_TILE_CONFIG"] = cfg
+    try:
+        return run(m3s, pair, **prm)
+    finally:
+        os.environ.pop("M3S_TILE_CONFIG", None)
+
+
+def _with_desc(pair, Dii, Dji):
+    return synth.Pair(pair.H, pair.W, pair.Xii, pair.Xji, np.ascontiguousarray(Dii, np.float32),
+                      np.ascontiguousarray(Dji, np.float32), pair.Qii, pair.Qji, K=pair.K, r=pair.r, proj=pair.proj)
+
+
+@pytest.mark.parametrize("case", ["near_ties", "exact_ties", "huge", "tiny", "nan_ref", "unnormalised",
+                                  "r4", "r5", "r6"])
+def test_fp16_prefilter_is_exact(m3s, case):
+    """The fp16 pre-filtered refine (tile configuration 5) returns the same bits
+    as the exact global-memory scan (configuration 0) on adversarial descriptors:
+    near-ties within the fp16 error, exact ties, magnitudes outside fp16, values
+    in the fp16 subnormal range, NaN in the reference region, non-unit norms, and
+    radii that need two candidate masks or fall back to the exact scan."""
+    base = _pair(96, 128, 17)
+    rng = np.random.Generator(np.random.PCG64(zlib.crc32(case.encode())))
+    Dii, Dji = base.Dii.astype(np.float64), base.Dji.astype(np.float64)
+    prm = {}
+    if case == "near_ties":
+        Dii = Dii[..., :1].repeat(24, -1) * 0 + 1.0 / np.sqrt(24)
+        Dii = Dii + rng.normal(0, 2e-5, Dii.shape)
+        Dji = np.full_like(Dji, 1.0 / np.sqrt(24))
+    elif case == "exact_ties":
+        Dii = np.round(Dii * 4) / 4
+        Dji = np.round(Dji * 4) / 4
+    elif case == "huge":
+        Dii = Dii * 1e5
+    elif case == "tiny":
+        Dii = Dii * 3e-6
+        Dji = Dji * 7e-6
+    elif case == "nan_ref":
+        Dii = Dii.copy()
+        Dii[40:43, 60:63, 5] = np.nan
+    elif case == "unnormalised":
+        Dii = Dii * rng.uniform(0.1, 30.0, Dii.shape[:2])[..., None]
+        Dji = Dji * rng.uniform(0.1, 30.0, Dji.shape[:2])[..., None]
+    elif case in ("r4", "r5", "r6"):
+        prm["refine_radius"] = int(case[1])
+    pair = _with_desc(base, Dii, Dji)
+    a = _run_cfg(m3s, pair, "0", **prm)
+    b = _run_cfg(m3s, pair, "5", **prm)
+    c = _run_cfg(m3s, pair, "3", **prm)
+    for k in ("p", "idx", "valid", "theta"):
+        assert np.array_equal(a[k], b[k], equal_nan=True), "%s: %s (fp16 pre-filter)" % (case, k)
+        assert np.array_equal(a[k], c[k], equal_nan=True), "%s: %s (fp32 LDS)" % (case, k)
