@@ -25,7 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle_m3s.so")
 
 # Defaults of the matching workloads: 10 LM iterations, lambda 1e-8, refine
 # radius 3, confidence gate 1.5, residual-angle gate 1e-4 rad, 3D gate off.
-DEFAULTS = dict(K=10, lambda0=1e-8, r=3, conf_min=1.5, max_theta=1e-4, max_dist=math.inf)
+DEFAULTS = dict(K=10, lambda0=1e-8, r=3, levels=1, conf_min=1.5, max_theta=1e-4, max_dist=math.inf)
 
 
 def compile_oracle(src: str = _SRC, out: str = _LIB_PATH, extra_flags=()) -> str:
@@ -59,7 +59,7 @@ def _declare(lib):
     up = ctypes.POINTER(ctypes.c_uint8)
     c_int, c_long, c_double = ctypes.c_int, ctypes.c_long, ctypes.c_double
     lib.oracle_match_fwd.argtypes = [c_int, c_int, c_int, dp, dp, dp, dp, dp, dp, dp,
-                                     c_int, c_double, c_int, c_double, c_double, c_double,
+                                     c_int, c_double, c_int, c_int, c_double, c_double, c_double,
                                      dp, ip, up, dp, dp, dp, c_int]
     lib.oracle_match_fwd.restype = c_int
     lib.oracle_cost_grid.argtypes = [c_int, c_int, dp, dp, c_long, dp, dp, dp]
@@ -88,7 +88,7 @@ def _ptr(a, ctype=ctypes.c_double):
     return a.ctypes.data_as(ctypes.POINTER(ctype))
 
 
-def match_fwd(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, *, K=10, lambda0=1e-8, r=3,
+def match_fwd(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, *, K=10, lambda0=1e-8, r=3, levels=1,
               conf_min=1.5, max_theta=1e-4, max_dist=math.inf, nthreads=0, lib=None):
     """Run the oracle forward.  Arrays are (H, W, 3) / (H, W, D) / (H, W) / (H, W, 2).
 
@@ -108,7 +108,7 @@ def match_fwd(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, *, K=10, lamb
     p = np.empty((N, 2)); theta = np.empty(N); xhat = np.empty((N, 3)); gap = np.empty(N)
     idx = np.empty(N, np.int32); valid = np.empty(N, np.uint8)
     rc = lib.oracle_match_fwd(H, W, D, _ptr(Xii), _ptr(Xji), _ptr(Dii), _ptr(Dji), _ptr(Qii), _ptr(Qji),
-                              _ptr(p_init), int(K), float(lambda0), int(r), float(conf_min),
+                              _ptr(p_init), int(K), float(lambda0), int(r), int(levels), float(conf_min),
                               float(max_theta), float(max_dist), _ptr(p), _ptr(idx, ctypes.c_int32),
                               _ptr(valid, ctypes.c_uint8), _ptr(theta), _ptr(xhat), _ptr(gap), int(nthreads))
     if rc != 0:
@@ -160,6 +160,14 @@ def ray_images(Xii, lib=None):
     if lib.oracle_ray_images(H, W, _ptr(X), _ptr(R), _ptr(Gx), _ptr(Gy)) != 0:
         raise ValueError("oracle_ray_images failed")
     return R.reshape(H, W, 3), Gx.reshape(H, W, 3), Gy.reshape(H, W, 3)
+
+
+def match_stats(idx, valid):
+    """Keyframe statistics of one match set (Sec. 3.4): the number of valid
+    matches and the number of distinct reference pixels they land on."""
+    idx = np.asarray(idx).reshape(-1)
+    valid = np.asarray(valid).reshape(-1).astype(bool)
+    return int(valid.sum()), int(np.unique(idx[valid]).size)
 
 
 def max_threads(lib=None) -> int:

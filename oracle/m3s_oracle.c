@@ -37,8 +37,10 @@
  *   K iterations exactly, no early exit; damping lambda I, x10 on a rejected
  *     step, /10 on an accepted one, acceptance on strictly lower cost;
  *   theta = 2 asin(min(1, sqrt(c) / 2)), which is Eq. 3 solved for theta;
- *   refine: single level, radius r around round-half-up of p*, raw dot
- *     products, first strict maximum in row-major window order;
+ *   refine: radius r around round-half-up of p*, raw dot products, first
+ *     strict maximum in row-major window order; coarse-to-fine as `levels`
+ *     levels of spacing 2^(levels-1), ..., 2, 1, each around the previous
+ *     level's best (one level is the plain window);
  *   a reference pixel whose point is non-finite or zero has a zero ray; a
  *     sample whose interpolated ray is zero has infinite cost and a zero
  *     Jacobian; a query point that is non-finite or zero, or a non-finite
@@ -174,7 +176,7 @@ static double clampd(double v, double lo, double hi) { return v < lo ? lo : (v >
 /* ------------------------------------------------------------------ */
 
 typedef struct {
-    int H, W, D, K, r;
+    int H, W, D, K, r, levels;
     double lambda0, conf_min, max_theta, max_dist;
     const double *Xii, *Xji, *Dii, *Dji, *Qii, *Qji, *p_init;
     ray_map rm;
@@ -263,25 +265,38 @@ static void match_one(const fwd_ctx *C, long n)
         bilerp3(C->Xii, &cl, C->xhat + 3 * n);
     }
 
-    /* Feature refine (Sec. 3.2): best raw descriptor dot product in the
-       (2r+1)^2 window around the rounded match, first strict maximum. */
+    /* Feature refine (Sec. 3.2): coarse-to-fine search for the best raw
+       descriptor dot product.  Level l, from levels-1 down to 0, scans the
+       (2r+1)^2 grid of spacing 2^l around the current centre (first strict
+       maximum in row-major order) and moves the centre there; the first
+       centre is the match rounded half up.  One level is the plain window. */
     int mx0 = (int)floor(px + 0.5), my0 = (int)floor(py + 0.5);
     const double *dq = C->Dji + (long)C->D * n;
     double best = -INFINITY, second = -INFINITY;
     long best_m = -1;
-    for (int dy = -C->r; dy <= C->r; ++dy) {
-        int my = my0 + dy;
-        if (my < 0 || my >= H) continue;
-        for (int dx = -C->r; dx <= C->r; ++dx) {
-            int mx = mx0 + dx;
-            if (mx < 0 || mx >= W) continue;
-            long m = (long)my * W + mx;
-            const double *dr = C->Dii + (long)C->D * m;
-            double s = 0.0;
-            for (int k = 0; k < C->D; ++k) s += dq[k] * dr[k];
-            if (s > best) { second = best; best = s; best_m = m; }
-            else if (s > second) second = s;
+    for (int lev = C->levels - 1; lev >= 0; --lev) {
+        const int sp = 1 << lev;
+        long lev_m = -1;
+        best = -INFINITY;
+        second = -INFINITY;
+        for (int dy = -C->r; dy <= C->r; ++dy) {
+            int my = my0 + sp * dy;
+            if (my < 0 || my >= H) continue;
+            for (int dx = -C->r; dx <= C->r; ++dx) {
+                int mx = mx0 + sp * dx;
+                if (mx < 0 || mx >= W) continue;
+                long m = (long)my * W + mx;
+                const double *dr = C->Dii + (long)C->D * m;
+                double s = 0.0;
+                for (int k = 0; k < C->D; ++k) s += dq[k] * dr[k];
+                if (s > best) { second = best; best = s; lev_m = m; }
+                else if (s > second) second = s;
+            }
         }
+        if (lev_m < 0) break;
+        best_m = lev_m;
+        mx0 = (int)(lev_m % W);
+        my0 = (int)(lev_m / W);
     }
     C->idx[n] = (int32_t)best_m;
     if (C->gap) C->gap[n] = best - second;
@@ -302,27 +317,29 @@ static void match_one(const fwd_ctx *C, long n)
  *   H, W >= 2, D >= 1; arrays row-major, pixel m = y * W + x:
  *   Xii, Xji [H*W*3]; Dii, Dji [H*W*D]; Qii, Qji [H*W] or both NULL;
  *   p_init [H*W*2] as (x, y) or NULL for the identity initialisation.
+ * levels >= 1: coarse-to-fine refine levels (1 = single window).
  * Outputs: p [H*W*2] (continuous p* before refine), idx [H*W] (refined
  *   linear index, -1 if none), valid [H*W]; optional (may be NULL): theta
  *   [H*W], xhat [H*W*3] (bilinear X^i_i at p*), gap [H*W] (best minus
- *   second-best window score, +inf if there is one candidate).
+ *   second-best window score of the last level, +inf if there is one
+ *   candidate).
  * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on bad sizes.
  */
 int oracle_match_fwd(int H, int W, int D,
                      const double *Xii, const double *Xji, const double *Dii, const double *Dji,
                      const double *Qii, const double *Qji, const double *p_init,
-                     int K, double lambda0, int r, double conf_min, double max_theta, double max_dist,
+                     int K, double lambda0, int r, int levels, double conf_min, double max_theta, double max_dist,
                      double *p, int32_t *idx, uint8_t *valid, double *theta, double *xhat, double *gap,
                      int nthreads)
 {
-    if (H < 2 || W < 2 || D < 1 || K < 0 || r < 0) return -1;
+    if (H < 2 || W < 2 || D < 1 || K < 0 || r < 0 || levels < 1 || levels > 16) return -1;
     long N = (long)H * W;
     double *R = malloc(sizeof(double) * 3 * N), *Gx = malloc(sizeof(double) * 3 * N),
            *Gy = malloc(sizeof(double) * 3 * N);
     if (!R || !Gx || !Gy) { free(R); free(Gx); free(Gy); return -2; }
     ray_image(H, W, Xii, R);
     gradient_images(H, W, R, Gx, Gy);
-    fwd_ctx C = {H, W, D, K, r, lambda0, conf_min, max_theta, max_dist,
+    fwd_ctx C = {H, W, D, K, r, levels, lambda0, conf_min, max_theta, max_dist,
                  Xii, Xji, Dii, Dji, (Qii && Qji) ? Qii : NULL, (Qii && Qji) ? Qji : NULL, p_init,
                  {H, W, R, Gx, Gy}, p, theta, xhat, gap, idx, valid};
 #ifdef _OPENMP

@@ -342,6 +342,60 @@ def pin_p_init(lib):
     assert np.abs(o2["p"] - ref["p"])[m].max() <= 1e-9
 
 
+def _position_code(xs, ys, n_dir=16, omega=0.04):
+    """Unit descriptors whose dot product sum_k cos(omega u_k . (a - b)) / n_dir
+    is isotropic and falls monotonically with pixel distance up to ~2.4/omega."""
+    ang = np.arange(n_dir) * np.pi / n_dir
+    u = np.stack([np.cos(ang), np.sin(ang)], -1)
+    ph = omega * (np.asarray(xs)[..., None] * u[:, 0] + np.asarray(ys)[..., None] * u[:, 1])
+    return np.concatenate([np.cos(ph), np.sin(ph)], -1) / np.sqrt(n_dir)
+
+
+def pin_refine_coarse_to_fine(lib):
+    """Coarse-to-fine refine (Sec. 3.2): with a similarity that falls with pixel
+    distance, L levels of spacing 2^(L-1)..1 and radius r land exactly on a
+    target up to r (2^L - 1) px from the rounded match; one level cannot reach
+    beyond r."""
+    pair = _pair(96, 128, 21, False)
+    H, W = pair.H, pair.W
+    base = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji)
+    m0 = np.floor(base["p"] + 0.5).astype(int)
+    xs, ys = synth.pixel_grid(H, W)
+    Dii = _position_code(xs, ys)
+    rng = np.random.Generator(np.random.PCG64(4))
+    r = 3
+    for L in (2, 3):
+        reach = r * (2 ** L - 1) - 1
+        off = rng.integers(-reach, reach + 1, size=(H, W, 2))
+        tx = m0[..., 0] + off[..., 0]
+        ty = m0[..., 1] + off[..., 1]
+        ok = (tx >= 0) & (tx < W) & (ty >= 0) & (ty < H) & base["valid"]
+        Dji = _position_code(tx, ty)
+        o = fwd(lib, pair.Xii, pair.Xji, Dii, Dji, r=r, levels=L)
+        want = ty * W + tx
+        assert ok.sum() > 1000
+        assert (o["idx"][ok] == want[ok]).all(), "coarse-to-fine with %d levels" % L
+        far = ok & (np.abs(off).max(-1) > r)
+        o1 = fwd(lib, pair.Xii, pair.Xji, Dii, Dji, r=r, levels=1)
+        assert far.sum() > 100 and not (o1["idx"][far] == want[far]).any(), "one level reaches only r"
+    one = fwd(lib, pair.Xii, pair.Xji, pair.Dii, pair.Dji, r=r, levels=1)
+    assert np.array_equal(one["idx"], base["idx"]), "one level is the plain window"
+
+
+def pin_match_stats(lib):
+    """Keyframe statistics (Sec. 3.4): valid count and distinct matched reference
+    pixels, on cases with known answers."""
+    p = synth.identity_pair(12, 16, 3)
+    o = fwd(lib, p.Xii, p.Xji, p.Dii, p.Dji)
+    assert oracle.match_stats(o["idx"], o["valid"]) == (192, 192)
+    idx = np.full((12, 16), 7, np.int32)
+    valid = np.zeros((12, 16), bool)
+    valid[:3] = True
+    assert oracle.match_stats(idx, valid) == (48, 1)
+    idx2 = np.arange(192, dtype=np.int32).reshape(12, 16) // 2
+    assert oracle.match_stats(idx2, np.ones((12, 16), bool)) == (192, 96)
+
+
 # --------------------------------------------------------------- backward pins
 
 def _fd_setup(lib, K=20):
@@ -509,6 +563,6 @@ def pin_bwd_held_border(lib):
 ALL_PINS = [
     pin_identity, pin_pinhole, pin_brute_force, pin_depth_invariance, pin_border_angle,
     pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
-    pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init,
+    pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init, pin_refine_coarse_to_fine, pin_match_stats,
     pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian, pin_bwd_held_border,
 ]

@@ -32,8 +32,11 @@ MUTANTS = {
                                  ("else if (hold_y) { dy = 0.0; dx = -g0 / a00; }", "else if (hold_y) { dy = 0.0; dx = -g0 / a11; }")],
     "theta_is_chord": [("double th = 2.0 * asin(fmin(1.0, sqrt(cur.c) / 2.0));", "double th = sqrt(cur.c);")],
     "window_short": [("for (int dy = -C->r; dy <= C->r; ++dy) {", "for (int dy = -C->r; dy < C->r; ++dy) {")],
-    "tie_takes_last": [("if (s > best) { second = best; best = s; best_m = m; }",
-                        "if (s >= best) { second = best; best = s; best_m = m; }")],
+    "window_wrong_stride": [("int mx = mx0 + sp * dx;", "int mx = mx0 + dx;")],
+    "tie_takes_last": [("if (s > best) { second = best; best = s; lev_m = m; }",
+                        "if (s >= best) { second = best; best = s; lev_m = m; }")],
+    "levels_same_spacing": [("const int sp = 1 << lev;", "const int sp = 1;")],
+    "levels_centre_not_moved": [("        mx0 = (int)(lev_m % W);\n        my0 = (int)(lev_m / W);\n", "")],
     "refine_rounds_down": [("int mx0 = (int)floor(px + 0.5), my0 = (int)floor(py + 0.5);",
                             "int mx0 = (int)floor(px), my0 = (int)floor(py);")],
     "conf_gate_strict": [("sqrt(C->Qii[best_m] * C->Qji[n]) >= C->conf_min", "sqrt(C->Qii[best_m] * C->Qji[n]) > C->conf_min")],
