@@ -50,6 +50,7 @@ extern "C" {
 #define M3S_MAX_ITER 1000     /* largest LM iteration count K */
 #define M3S_MAX_DESC 64       /* largest descriptor dimension D */
 #define M3S_MAX_PIXELS (1 << 26)  /* largest H * W of one frame (67,108,864 pixels) */
+#define M3S_MAX_LEVELS 4      /* largest number of coarse-to-fine refine levels */
 
 typedef enum {
     M3S_OK = 0,
@@ -64,13 +65,14 @@ typedef enum {
 /*
  * Matching parameters (Sec. 3.2 and 3.3).  m3s_default_params fills the
  * values of the paper's setting: K = 10 iterations ("within 10 iterations"),
- * lambda 1e-8, refine radius 3, confidence gate 1.5, residual-angle gate
- * 1e-4 rad and no 3D-distance gate.
+ * lambda 1e-8, refine radius 3 with one level, confidence gate 1.5,
+ * residual-angle gate 1e-4 rad and no 3D-distance gate.
  */
 typedef struct {
     int32_t max_iter;       /* K in [0, M3S_MAX_ITER]: LM iterations, run exactly (no early exit) */
     float   lambda_init;    /* initial Levenberg damping, finite and > 0 */
     int32_t refine_radius;  /* r in [0, M3S_MAX_RADIUS]: window (2r+1)^2; 0 = round(p*) */
+    int32_t refine_levels;  /* L in [1, M3S_MAX_LEVELS]: coarse-to-fine levels of spacing 2^(L-1)..1 */
     float   conf_min;       /* q_min: valid needs sqrt(Qii[idx] * Qji[n]) >= conf_min (if Q given); finite */
     float   max_theta;      /* valid needs residual angle <= max_theta (rad); >= 0, may be +inf */
     float   max_dist;       /* valid needs |Xii[idx] - Xji[n]| <= max_dist; > 0, +inf disables the gate */
@@ -102,7 +104,8 @@ typedef struct {
     float   *xhat;          /* [H*W*3] X^i_i sampled bilinearly at p*, or NULL */
 } m3s_outputs;
 
-/* One edge of a batch: its pair, its outputs, and optional per-edge K and r (< 0: use the common ones). */
+/* One edge of a batch: its pair, its outputs, and optional per-edge K and r (< 0: use the common ones);
+   the refine levels are the common ones. */
 typedef struct {
     m3s_pair    in;
     m3s_outputs out;
@@ -127,9 +130,11 @@ size_t m3s_workspace_bytes(const m3s_pair *pair, const m3s_params *params);
  *   pixel, K Levenberg-Marquardt iterations on |psi_hat(p) - t|^2 with the
  *   bilinearly sampled, renormalised ray psi_hat, damping lambda I (x10 on a
  *   rejected step, /10 on an accepted one), every iterate clamped to the
- *   image; residual angle 2 asin(|e| / 2); refine to the first maximum of the
- *   raw descriptor dot product over the (2r+1)^2 window around round(p*);
- *   gates.
+ *   image (a coordinate on its bound whose step points outward is held);
+ *   residual angle 2 asin(|e| / 2); refine to the first maximum of the raw
+ *   descriptor dot product over the (2r+1)^2 window around round(p*), or
+ *   coarse to fine over L levels of spacing 2^(L-1), ..., 1, each around the
+ *   previous level's best (Sec. 3.2, feature refinement); gates.
  * ws must be 256-byte aligned device memory of >= m3s_workspace_bytes().
  */
 m3s_status m3s_match_fwd(const m3s_pair *pair, const m3s_params *params, const m3s_outputs *out,
@@ -152,6 +157,19 @@ m3s_status m3s_match_fwd(const m3s_pair *pair, const m3s_params *params, const m
 m3s_status m3s_match_bwd(const m3s_pair *pair, const m3s_outputs *fwd,
                          const float *grad_p, const float *grad_xhat,
                          float *grad_Xii, float *grad_Xji, void *stream);
+
+/*
+ * Keyframe statistics of one match set (Sec. 3.4: tracking adds a keyframe
+ * when the number of valid matches or of distinct matched keyframe pixels
+ * falls below a fraction of the pixels).  From the forward's idx and valid
+ * (H*W queries matched into an H x W reference frame), writes the DEVICE
+ * array counts[2] = {number of valid queries, number of distinct idx among
+ * them} (overwritten).  ws: 256-byte aligned device memory of at least
+ * m3s_stats_workspace_bytes(H, W) (a bitmap of the reference pixels).
+ */
+size_t m3s_stats_workspace_bytes(int32_t H, int32_t W);
+m3s_status m3s_match_stats(const m3s_outputs *fwd, int32_t H, int32_t W, int32_t *counts,
+                           void *ws, size_t ws_bytes, void *stream);
 
 /* Flags of m3s_match_batched. */
 #define M3S_BATCH_GRAPH    0x1u  /* capture the launch sequence in a hipGraph and replay it */

@@ -5,5 +5,5 @@ ABI of include/m3s.h.  This package is its thin Python binding over torch device
 tensors.  Build the library with ``python -m paper_2412_12392_amd.build``.
 """
 from .binding import (EdgeInput, MatchFunction, MatchResult, last_batched_config, make_edges, match,  # noqa: F401
-                    match_backward, match_batched, params)
+                    match_backward, match_batched, match_stats, params)
 from ._lib import M3SError, load as load_library  # noqa: F401

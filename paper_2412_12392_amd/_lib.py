@@ -18,7 +18,7 @@ c_fp = ctypes.POINTER(ctypes.c_float)
 
 class Params(ctypes.Structure):
     _fields_ = [("max_iter", ctypes.c_int32), ("lambda_init", ctypes.c_float),
-                ("refine_radius", ctypes.c_int32), ("conf_min", ctypes.c_float),
+                ("refine_radius", ctypes.c_int32), ("refine_levels", ctypes.c_int32), ("conf_min", ctypes.c_float),
                 ("max_theta", ctypes.c_float), ("max_dist", ctypes.c_float)]
 
 
@@ -49,7 +49,8 @@ class M3SError(RuntimeError):
 EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_match_bwd",
            "m3s_batched_workspace_bytes", "m3s_match_batched", "m3s_batched_last_config",
            "m3s_clear_caches", "m3s_status_string", "m3s_last_error", "m3s_version",
-           "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset"]
+           "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
+           "m3s_match_stats"]
 
 _lib = None
 
@@ -92,6 +93,10 @@ def load(path: str = LIB_PATH):
     lib.m3s_timing_read.restype = ctypes.c_int
     lib.m3s_timing_reset.argtypes = []
     lib.m3s_timing_reset.restype = None
+    lib.m3s_stats_workspace_bytes.argtypes = [i32, i32]
+    lib.m3s_stats_workspace_bytes.restype = sz
+    lib.m3s_match_stats.argtypes = [PO, i32, i32, vp, vp, sz, vp]
+    lib.m3s_match_stats.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib

@@ -168,6 +168,20 @@ def match_batched(inputs: Sequence[EdgeInput], prm: Optional[_lib.Params] = None
     return results
 
 
+def match_stats(res: MatchResult, stream=None) -> torch.Tensor:
+    """m3s_match_stats: device int32 tensor [valid count, distinct matched reference pixels]."""
+    lib = _lib.load()
+    H, W = res.idx.shape
+    fwd = _lib.Outputs(0, _ptr(res.idx, torch.int32, shape=(H, W)), _ptr(res.valid, torch.uint8, shape=(H, W)), 0, 0)
+    counts = torch.empty(2, dtype=torch.int32, device=res.idx.device)
+    nbytes = lib.m3s_stats_workspace_bytes(H, W)
+    ws = _workspace(nbytes, res.idx.device)
+    st = lib.m3s_match_stats(ctypes.byref(fwd), H, W, _ptr(counts, torch.int32), ws.data_ptr(), ws.numel(),
+                             _stream(stream))
+    _lib.check(lib, "m3s_match_stats", st)
+    return counts
+
+
 def last_batched_config():
     lib = _lib.load()
     g, t = ctypes.c_int32(), ctypes.c_int32()

@@ -78,6 +78,8 @@ m3s_status check_params(const m3s_params* P) {
     if (!(std::isfinite(P->lambda_init) && P->lambda_init > 0.f)) return fail(M3S_ERR_PARAM, "lambda_init must be finite and > 0");
     if (P->refine_radius < 0 || P->refine_radius > M3S_MAX_RADIUS)
         return fail(M3S_ERR_PARAM, "refine_radius %d outside [0, %d]", P->refine_radius, M3S_MAX_RADIUS);
+    if (P->refine_levels < 1 || P->refine_levels > M3S_MAX_LEVELS)
+        return fail(M3S_ERR_PARAM, "refine_levels %d outside [1, %d]", P->refine_levels, M3S_MAX_LEVELS);
     if (!std::isfinite(P->conf_min)) return fail(M3S_ERR_PARAM, "conf_min must be finite");
     if (std::isnan(P->max_theta) || P->max_theta < 0.f) return fail(M3S_ERR_PARAM, "max_theta must be >= 0");
     if (std::isnan(P->max_dist) || !(P->max_dist > 0.f)) return fail(M3S_ERR_PARAM, "max_dist must be > 0 (inf disables)");
@@ -125,7 +127,7 @@ bool desc_in_regs(const m3s_pair* A) {
 EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P, int K, int r, const float4* rays) {
     EdgeArgs E;
     std::memset(&E, 0, sizeof E);
-    E.H = A->H; E.W = A->W; E.D = A->D; E.K = K; E.r = r;
+    E.H = A->H; E.W = A->W; E.D = A->D; E.K = K; E.r = r; E.levels = P->refine_levels;
     E.lambda0 = P->lambda_init; E.conf_min = P->conf_min; E.max_theta = P->max_theta; E.max_dist = P->max_dist;
     E.Xii = A->Xii; E.Xji = A->Xji; E.Dii = A->Dii; E.Dji = A->Dji;
     E.Qii = A->Qii; E.Qji = A->Qji; E.p_init = A->p_init; E.rays = rays;
@@ -216,7 +218,7 @@ m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, i
     plan->total_tiles = (int)tiles;
     plan->total_prep = (int)prep;
     plan->total_bytes = off;
-    plan->signature = sig + (plan->desc_regs ? "R" : "G");
+    plan->signature = sig + (plan->desc_regs ? "R" : "G") + "L" + std::to_string(P->refine_levels);
     return M3S_OK;
 }
 
@@ -347,6 +349,7 @@ void m3s_default_params(m3s_params* P) {
     P->max_iter = 10;
     P->lambda_init = 1e-8f;
     P->refine_radius = 3;
+    P->refine_levels = 1;
     P->conf_min = 1.5f;
     P->max_theta = 1e-4f;
     P->max_dist = INFINITY;
@@ -398,6 +401,30 @@ m3s_status m3s_match_bwd(const m3s_pair* pair, const m3s_outputs* fwd, const flo
     hipError_t e = m3s::launch_bwd(pair->H, pair->W, pair->Xii, pair->Xji, fwd->p, fwd->valid, grad_p, grad_xhat,
                                    grad_Xii, grad_Xji, reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+size_t m3s_stats_workspace_bytes(int32_t H, int32_t W) {
+    if (H < 2 || W < 2 || (int64_t)H * W > M3S_MAX_PIXELS) return 0;
+    return align_up(((size_t)H * W + 31) / 32 * sizeof(uint32_t));
+}
+
+m3s_status m3s_match_stats(const m3s_outputs* fwd, int32_t H, int32_t W, int32_t* counts, void* ws, size_t ws_bytes,
+                           void* stream) {
+    m3s_status s = check_shape(H, W);
+    if (s != M3S_OK) return s;
+    if (!fwd || !fwd->idx || !fwd->valid || !counts) return fail(M3S_ERR_NULL, "idx, valid and counts are required");
+    if (!aligned(fwd->idx, 4) || !aligned(counts, 4)) return fail(M3S_ERR_PARAM, "idx and counts must be 4-byte aligned");
+    size_t need = m3s_stats_workspace_bytes(H, W);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need, ws_bytes);
+    int dev;
+    DeviceInfo info;
+    if ((s = current_device(&dev, &info)) != M3S_OK) return s;
+    hipError_t e = m3s::launch_stats(fwd->idx, fwd->valid, H, W, reinterpret_cast<uint32_t*>(ws), counts,
+                                     reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "statistics launch");
     g_last_error.clear();
     return M3S_OK;
 }

@@ -13,7 +13,7 @@ namespace m3s {
 // Everything one edge needs on the device.  Lives in kernel arguments for the
 // single-pair launch and in the workspace edge table for the batched launch.
 struct EdgeArgs {
-    int32_t H, W, D, K, r;
+    int32_t H, W, D, K, r, levels;
     int32_t tiles_x, tiles_y;      // query tiles of this edge (batched path)
     int32_t tile_begin;            // first global tile id of this edge (batched path)
     float lambda0, conf_min, max_theta, max_dist;

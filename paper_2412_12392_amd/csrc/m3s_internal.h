@@ -28,6 +28,8 @@ hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStr
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
                           int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs,
                           hipStream_t s);
+hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, uint32_t* bitmap, int32_t* counts,
+                        hipStream_t s);
 hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
                       const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s);
 

@@ -156,25 +156,34 @@ __device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState
 __device__ __forceinline__ int round_half_up(float v) { return (int)floorf(v + 0.5f); }
 
 // Phase 2 (global memory): first maximum of the raw dot product over the
-// window, row-major.
+// window, row-major; with L > 1 levels, coarse to fine: level l scans the
+// grid of spacing 2^l around the previous level's best.
 template <int DT>
 __device__ __forceinline__ long refine_global(const EdgeArgs& A, long n, const QState& q) {
     const int H = A.H, W = A.W, r = A.r;
     int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
     QueryDesc<DT> qd;
     qd.load(A.Dji, n, A.D);
-    float best = -INFINITY;
     long bi = -1;
-    for (int dy = -r; dy <= r; ++dy) {
-        int my = my0 + dy;
-        if (my < 0 || my >= H) continue;
-        for (int dx = -r; dx <= r; ++dx) {
-            int mx = mx0 + dx;
-            if (mx < 0 || mx >= W) continue;
-            long m = (long)my * W + mx;
-            float s = qd.dot(A.Dii, m, A.D);
-            if (s > best) { best = s; bi = m; }
+    for (int lev = A.levels - 1; lev >= 0; --lev) {
+        const int sp = 1 << lev;
+        float best = -INFINITY;
+        long lb = -1;
+        for (int dy = -r; dy <= r; ++dy) {
+            int my = my0 + sp * dy;
+            if (my < 0 || my >= H) continue;
+            for (int dx = -r; dx <= r; ++dx) {
+                int mx = mx0 + sp * dx;
+                if (mx < 0 || mx >= W) continue;
+                long m = (long)my * W + mx;
+                float s = qd.dot(A.Dii, m, A.D);
+                if (s > best) { best = s; lb = m; }
+            }
         }
+        if (lb < 0) break;
+        bi = lb;
+        mx0 = (int)(lb % W);
+        my0 = (int)(lb / W);
     }
     return bi;
 }
@@ -300,7 +309,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     }
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
-    const bool use_lds = any && rw * rh <= kRegionPx;
+    const bool use_lds = any && rw * rh <= kRegionPx && A.levels == 1;
     if (use_lds) {
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
         const int row_chunks = rw * 6;
@@ -476,7 +485,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     }
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
-    bool use16 = any && rw * rh <= kRegionPx16 && r <= 5;
+    bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
     float pn2 = 0.f, pl1 = 0.f, pmax = 0.f;
     if (use16) {
         // Stage: thread c handles pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7).
@@ -708,6 +717,37 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     }
 }
 
+// ---------------------------------------------------------------- match statistics
+
+__global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ a, long count) {
+    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    long stride = (long)gridDim.x * blockDim.x;
+    for (; i < count; i += stride) a[i] = 0u;
+}
+
+// counts[0] += valid queries, counts[1] += reference pixels whose bit this
+// lane set first; one pair of atomics per wave.
+__global__ void __launch_bounds__(256) stats_kernel(const int32_t* __restrict__ idx, const uint8_t* __restrict__ valid,
+                                                    long N, long M, uint32_t* __restrict__ bitmap,
+                                                    int32_t* __restrict__ counts) {
+    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    bool v = false, first = false;
+    if (n < N && valid[n]) {
+        int32_t m = idx[n];
+        if (m >= 0 && m < M) {
+            v = true;
+            uint32_t bit = 1u << (m & 31);
+            uint32_t old = atomicOr(bitmap + (m >> 5), bit);
+            first = (old & bit) == 0u;
+        }
+    }
+    unsigned long long bv = __ballot(v), bf = __ballot(first);
+    if ((threadIdx.x & 63) == 0) {
+        if (bv) atomicAdd(counts, (int32_t)__popcll(bv));
+        if (bf) atomicAdd(counts + 1, (int32_t)__popcll(bf));
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static inline unsigned blocks_for(long count, int per) { return (unsigned)((count + per - 1) / per); }
@@ -787,6 +827,20 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
         case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, s); break;
         default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
     }
+    timer_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, uint32_t* bitmap, int32_t* counts,
+                        hipStream_t s) {
+    long N = (long)H * W;
+    long words = (N + 31) / 32;
+    timer_begin("stats_fill", s);
+    fill_u32_kernel<<<min(blocks_for(words + 2, 256), 1024u), 256, 0, s>>>(bitmap, words);
+    fill_u32_kernel<<<1, 64, 0, s>>>(reinterpret_cast<uint32_t*>(counts), 2);
+    timer_end(s);
+    timer_begin("stats", s);
+    stats_kernel<<<blocks_for(N, 256), 256, 0, s>>>(idx, valid, N, N, bitmap, counts);
     timer_end(s);
     return hipGetLastError();
 }

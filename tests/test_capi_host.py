@@ -48,7 +48,7 @@ def test_struct_layout_matches_c(tmp_path):
 int main(void) {
   printf("%zu %zu %zu %zu\n", sizeof(m3s_params), sizeof(m3s_pair), sizeof(m3s_outputs), sizeof(m3s_edge));
   printf("%zu %zu %zu %zu\n", offsetof(m3s_pair, Xii), offsetof(m3s_pair, p_init), offsetof(m3s_edge, out), offsetof(m3s_edge, refine_radius));
-  printf("%zu %zu\n", offsetof(m3s_params, max_dist), offsetof(m3s_outputs, xhat));
+  printf("%zu %zu %zu\n", offsetof(m3s_params, max_dist), offsetof(m3s_outputs, xhat), offsetof(m3s_params, refine_levels));
   return 0;
 }''')
     exe = tmp_path / "layout"
@@ -57,12 +57,12 @@ int main(void) {
     assert vals == [ctypes.sizeof(_lib.Params), ctypes.sizeof(_lib.Pair), ctypes.sizeof(_lib.Outputs),
                     ctypes.sizeof(_lib.Edge),
                     _lib.Pair.Xii.offset, _lib.Pair.p_init.offset, _lib.Edge.out.offset, _lib.Edge.refine_radius.offset,
-                    _lib.Params.max_dist.offset, _lib.Outputs.xhat.offset]
+                    _lib.Params.max_dist.offset, _lib.Outputs.xhat.offset, _lib.Params.refine_levels.offset]
 
 
 def test_defaults_and_strings(lib):
     p = _lib.default_params(lib)
-    assert (p.max_iter, p.refine_radius) == (10, 3)
+    assert (p.max_iter, p.refine_radius, p.refine_levels) == (10, 3, 1)
     assert abs(p.lambda_init - 1e-8) < 1e-15 and abs(p.conf_min - 1.5) < 1e-7 and abs(p.max_theta - 1e-4) < 1e-10
     assert p.max_dist == float("inf")
     assert lib.m3s_version() == 1
@@ -115,6 +115,8 @@ def _fwd(lib, pair, prm=None, outs=None, ws=0, ws_bytes=0):
     (dict(prm=dict(max_iter=-1)), 3),
     (dict(prm=dict(max_iter=1001)), 3),
     (dict(prm=dict(refine_radius=9)), 3),
+    (dict(prm=dict(refine_levels=0)), 3),
+    (dict(prm=dict(refine_levels=5)), 3),
     (dict(prm=dict(lambda_init=0.0)), 3),
     (dict(prm=dict(lambda_init=float("nan"))), 3),
     (dict(prm=dict(max_theta=-1.0)), 3),
@@ -157,6 +159,18 @@ def test_bwd_validation(lib):
     assert st == 1
     st = lib.m3s_match_bwd(ctypes.byref(_pair()), ctypes.byref(fwd), _addr + 1, 0, _addr, _addr, None)
     assert st == 3
+
+
+def test_stats_validation(lib):
+    outs = _outs()
+    base = (ctypes.addressof(_ws) + 255) // 256 * 256
+    assert lib.m3s_stats_workspace_bytes(384, 512) >= 384 * 512 // 8
+    assert lib.m3s_stats_workspace_bytes(1, 512) == 0
+    assert lib.m3s_match_stats(None, 4, 4, _addr, base, 1024, None) == 1
+    assert lib.m3s_match_stats(ctypes.byref(outs), 1, 4, _addr, base, 1024, None) == 2
+    assert lib.m3s_match_stats(ctypes.byref(outs), 4, 4, 0, base, 1024, None) == 1
+    assert lib.m3s_match_stats(ctypes.byref(outs), 4, 4, _addr, 0, 0, None) == 4
+    assert lib.m3s_match_stats(ctypes.byref(outs), 4, 4, _addr, base + 4, 1024, None) == 4
 
 
 def test_batched_validation(lib):

@@ -42,7 +42,7 @@ def ora(pair, p_init=None, **kw):
 def _prm_kw(kw):
     # oracle keyword -> library parameter name
     names = dict(K="max_iter", r="refine_radius", lambda0="lambda_init", conf_min="conf_min",
-                 max_theta="max_theta", max_dist="max_dist")
+                 max_theta="max_theta", max_dist="max_dist", levels="refine_levels")
     return {names[k]: v for k, v in kw.items()}
 
 
@@ -224,3 +224,57 @@ def test_fp16_prefilter_is_exact(m3s, case):
     for k in ("p", "idx", "valid", "theta"):
         assert np.array_equal(a[k], b[k], equal_nan=True), "%s: %s (fp16 pre-filter)" % (case, k)
         assert np.array_equal(a[k], c[k], equal_nan=True), "%s: %s (fp32 LDS)" % (case, k)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_refine_levels(m3s, levels):
+    """Coarse-to-fine refine (Sec. 3.2) vs the oracle on the 512x384 workload,
+    and on position-code descriptors whose targets lie up to r(2^L - 1) px away;
+    every tile configuration gives the same bits."""
+    pair = synth.config_pair(2)
+    check(m3s, pair, "levels %d" % levels, levels=levels)
+    sys_path_pins()
+    import pins
+    base = _pair(96, 128, 21, conf=False)
+    o0 = ora(base)
+    m0 = np.floor(o0["p"] + 0.5).astype(int)
+    xs, ys = synth.pixel_grid(base.H, base.W)
+    rng = np.random.Generator(np.random.PCG64(40 + levels))
+    reach = 3 * (2 ** levels - 1) - 1
+    off = rng.integers(-reach, reach + 1, size=(base.H, base.W, 2))
+    code = _with_desc(base, pins._position_code(xs, ys), pins._position_code(m0[..., 0] + off[..., 0], m0[..., 1] + off[..., 1]))
+    g, o, st = check(m3s, code, "position code L%d" % levels, levels=levels)
+    outs = [_run_cfg(m3s, code, c, refine_levels=levels) for c in ("0", "3", "5")]
+    for k in ("p", "idx", "valid", "theta"):
+        assert np.array_equal(outs[0][k], outs[1][k]) and np.array_equal(outs[0][k], outs[2][k]), k
+
+
+def sys_path_pins():
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    if here not in sys.path:
+        sys.path.insert(0, here)
+
+
+@pytest.mark.parametrize("H,W,frac", [(48, 64, 0.7), (384, 512, 0.9), (7, 5, 1.0), (33, 65, 0.0)])
+def test_match_stats(m3s, H, W, frac):
+    """Keyframe statistics on seeded idx / valid arrays (duplicates, -1 entries,
+    all-invalid) equal the oracle's counts exactly."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(H * W))
+    N = H * W
+    idx = rng.integers(0, N, size=N).astype(np.int32)
+    idx[rng.uniform(size=N) < 0.05] = -1
+    idx[: N // 3] = idx[N // 3: 2 * (N // 3)]          # duplicates
+    valid = (rng.uniform(size=N) < frac) & (idx >= 0)
+    res = m3s.MatchResult(torch.zeros((H, W, 2), device="cuda"), torch.from_numpy(idx.reshape(H, W)).cuda(),
+                          torch.from_numpy(valid.reshape(H, W).astype(np.uint8)).cuda(), None, None)
+    got = m3s.match_stats(res).cpu().numpy().tolist()
+    assert got == list(oracle.match_stats(idx, valid)), (got, oracle.match_stats(idx, valid))
+    # End to end on a real match set: within the valid-flag disagreement.
+    pair = _pair(48, 64, 7)
+    t = parity.pair_tensors(pair)
+    r = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"])
+    gs = m3s.match_stats(r).cpu().numpy()
+    os_ = oracle.match_stats(*[ora(pair)[k] for k in ("idx", "valid")])
+    assert abs(int(gs[0]) - os_[0]) <= 0.001 * 48 * 64 + 1 and abs(int(gs[1]) - os_[1]) <= 0.001 * 48 * 64 + 1
