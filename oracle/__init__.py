@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "m3s_oracle.c")
+_TRACK_SRC = os.path.join(_HERE, "m3s_track_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle_m3s.so")
 
 # Defaults of the matching workloads: 10 LM iterations, lambda 1e-8, refine
@@ -28,11 +29,11 @@ _LIB_PATH = os.path.join(_HERE, "liboracle_m3s.so")
 DEFAULTS = dict(K=10, lambda0=1e-8, r=3, levels=1, conf_min=1.5, max_theta=1e-4, max_dist=math.inf)
 
 
-def compile_oracle(src: str = _SRC, out: str = _LIB_PATH, extra_flags=()) -> str:
-    """Compile the C oracle into a shared library (gcc, -O2, OpenMP)."""
+def compile_oracle(src: str = _SRC, out: str = _LIB_PATH, extra_flags=(), track_src: str = _TRACK_SRC) -> str:
+    """Compile the C oracle (matching and tracking sources) into a shared library (gcc, -O2, OpenMP)."""
     tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
-           "-ffp-contract=off", *extra_flags, src, "-o", tmp, "-lm"]
+           "-ffp-contract=off", *extra_flags, src, track_src, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -47,7 +48,8 @@ def load(path: str | None = None):
     if path is not None:
         return _declare(ctypes.CDLL(path))
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
+                                                                               os.path.getmtime(_TRACK_SRC)):
             compile_oracle()
         _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
@@ -70,6 +72,14 @@ def _declare(lib):
     lib.oracle_match_bwd.restype = c_int
     lib.oracle_max_threads.argtypes = []
     lib.oracle_max_threads.restype = c_int
+    lp = ctypes.POINTER(ctypes.c_long)
+    lib.oracle_track_pose.argtypes = [c_int, c_int, dp, dp, ip, up, dp, dp, c_double, c_double, c_double, c_double,
+                                      c_int, dp, dp, lp, dp, dp]
+    lib.oracle_track_pose.restype = c_int
+    lib.oracle_sim3_exp.argtypes = [dp, dp]
+    lib.oracle_sim3_exp.restype = None
+    lib.oracle_track_residual.argtypes = [dp, dp, dp, dp, dp]
+    lib.oracle_track_residual.restype = None
     return lib
 
 
@@ -168,6 +178,46 @@ def match_stats(idx, valid):
     idx = np.asarray(idx).reshape(-1)
     valid = np.asarray(valid).reshape(-1).astype(bool)
     return int(valid.sum()), int(np.unique(idx[valid]).size)
+
+
+# Tracking pose solve defaults (Sec. 3.3; the paper gives no values): confidence
+# gate 1.5, ray sigma 0.003, distance sigma 0.1, Huber width 1.345, 10 iterations.
+TRACK_DEFAULTS = dict(q_min=1.5, sigma_ray=0.003, sigma_dist=0.1, huber=1.345, iters=10)
+
+
+def sim3_exp(tau, lib=None):
+    """Exp of sim(3), tau = (v, omega, sigma) -> 3x4 [sR | t] (Eq. 1)."""
+    lib = lib or load()
+    t = _f64(tau, (7,))
+    T = np.empty(12)
+    lib.oracle_sim3_exp(_ptr(t), _ptr(T))
+    return T.reshape(3, 4)
+
+
+def track_residual(T, Xf_m, Xk_n, lib=None):
+    """Ray (3) and distance (1) residuals of one match and their 4x7 Jacobian."""
+    lib = lib or load()
+    r = np.empty(4); J = np.empty(28)
+    lib.oracle_track_residual(_ptr(_f64(T, (12,))), _ptr(_f64(Xf_m, (3,))), _ptr(_f64(Xk_n, (3,))), _ptr(r), _ptr(J))
+    return r, J.reshape(4, 7)
+
+
+def track_pose(Xk, Xf, idx, valid, Qf, Qk, T0, *, q_min=1.5, sigma_ray=0.003, sigma_dist=0.1, huber=1.345,
+               iters=10, lib=None):
+    """Gauss-Newton IRLS tracking pose (Sec. 3.3).  Returns (T 3x4, info dict)."""
+    lib = lib or load()
+    H, W = np.shape(Xk)[:2]
+    N = H * W
+    T = _f64(T0, (12,)).copy()
+    cost = ctypes.c_double(); count = ctypes.c_long()
+    Hm = np.empty(49); g = np.empty(7)
+    idx = np.ascontiguousarray(np.asarray(idx).reshape(N), dtype=np.int32)
+    valid = np.ascontiguousarray(np.asarray(valid).reshape(N).astype(np.uint8))
+    solved = lib.oracle_track_pose(H, W, _ptr(_f64(Xk, (N, 3))), _ptr(_f64(Xf, (N, 3))), _ptr(idx, ctypes.c_int32),
+                                   _ptr(valid, ctypes.c_uint8), _ptr(_f64(Qf, (N,))), _ptr(_f64(Qk, (N,))),
+                                   float(q_min), float(sigma_ray), float(sigma_dist), float(huber), int(iters),
+                                   _ptr(T), ctypes.byref(cost), ctypes.byref(count), _ptr(Hm), _ptr(g))
+    return T.reshape(3, 4), dict(solved=solved, cost=cost.value, count=count.value, H=Hm.reshape(7, 7), g=g)
 
 
 def max_threads(lib=None) -> int:

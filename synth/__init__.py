@@ -238,3 +238,54 @@ def batched_uneven(seed_base: int = 4000, limit: int | None = None):
     if limit is not None:
         spec = spec[:limit]
     return [make_pair(H, W, seed_base + 1 + e, K=K, r=r, conf=True) for e, (H, W, K, r) in enumerate(spec)]
+
+
+@dataclass
+class TrackingProblem:
+    """Inputs of the tracking pose solve (Sec. 3.3) with its ground truth.
+
+    Xk: canonical keyframe points (measured), Xf: current-frame points,
+    idx[n]: frame pixel matched to keyframe pixel n, valid, Qf, Qk confidences,
+    T_true: the 3x4 Sim(3) [sR | t] with Xk[n] = T_true Xf[idx[n]] (+ noise)
+    for inliers; `outlier` marks the matches displaced on purpose.
+    """
+
+    H: int
+    W: int
+    Xk: np.ndarray
+    Xf: np.ndarray
+    idx: np.ndarray
+    valid: np.ndarray
+    Qf: np.ndarray
+    Qk: np.ndarray
+    T_true: np.ndarray
+    outlier: np.ndarray
+
+
+def make_tracking(H: int, W: int, seed: int, *, max_deg: float = 5.0, max_t: float = 0.05,
+                  scale_range=(0.95, 1.05), noise: float = 0.0, outlier_frac: float = 0.0,
+                  outlier_mag: float = 0.5, valid_frac: float = 0.95, pure_rotation: bool = False) -> TrackingProblem:
+    """Frame points on the procedural pinhole surface, a random Sim(3), matches
+    that shift pixels by a few columns, optional noise and gross outliers."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs, ys = pixel_grid(H, W)
+    Xf = surface_points(H, W, xs, ys)
+    if pure_rotation:
+        s, R, t = 1.0, random_rotation(rng, max_deg), np.zeros(3)
+    else:
+        s, R, t = random_sim3(rng, max_deg, max_t, *scale_range)
+    T = np.concatenate([s * R, t[:, None]], 1)
+    shift = rng.integers(-3, 4)
+    mx = np.clip(xs.astype(int) + shift, 0, W - 1)
+    idx = (ys.astype(int) * W + mx).reshape(-1)
+    P = Xf.reshape(-1, 3)[idx]
+    Xk = P @ T[:, :3].T + T[:, 3]
+    Xk = Xk + rng.normal(0.0, noise, size=Xk.shape) if noise > 0 else Xk
+    outlier = rng.uniform(size=H * W) < outlier_frac
+    Xk[outlier] += rng.normal(0.0, outlier_mag, size=(int(outlier.sum()), 3))
+    valid = rng.uniform(size=H * W) < valid_frac
+    Qf = rng.uniform(1.0, 5.0, size=H * W)
+    Qk = rng.uniform(1.0, 5.0, size=H * W)
+    f32 = lambda a, shape: np.ascontiguousarray(a.reshape(shape), dtype=np.float32)
+    return TrackingProblem(H, W, f32(Xk, (H, W, 3)), f32(Xf, (H, W, 3)), idx.reshape(H, W).astype(np.int32),
+                           valid.reshape(H, W), f32(Qf, (H, W)), f32(Qk, (H, W)), T, outlier.reshape(H, W))

@@ -396,6 +396,142 @@ def pin_match_stats(lib):
     assert oracle.match_stats(idx2, np.ones((12, 16), bool)) == (192, 96)
 
 
+# --------------------------------------------------------------- tracking pins
+
+def _sim3_generator_expm(tau):
+    import scipy.linalg as sl
+    v, w, s = tau[:3], tau[3:6], tau[6]
+    S = np.array([[0, -w[2], w[1]], [w[2], 0, -w[0]], [-w[1], w[0], 0]])
+    M = np.zeros((4, 4))
+    M[:3, :3] = S + s * np.eye(3)
+    M[:3, 3] = v
+    return sl.expm(M)[:3]
+
+
+def pin_sim3_exp(lib):
+    """Exp of sim(3) (Eq. 1) equals the matrix exponential of the 4x4 generator
+    [[[omega]_x + sigma I, v], [0, 0]], including near theta = 0 and sigma = 0."""
+    rng = np.random.Generator(np.random.PCG64(12))
+    for scale in (1e-9, 1e-6, 1e-4, 1e-3, 1e-2, 0.3, 1.5):
+        for _ in range(10):
+            tau = rng.normal(size=7) * scale
+            assert np.abs(oracle.sim3_exp(tau, lib) - _sim3_generator_expm(tau)).max() <= 1e-10, "Exp at %g" % scale
+    for tau in ([0.1, 0.2, 0.3, 1e-5, 0, 0, 0.2], [0.1, 0.2, 0.3, 0.5, 0.1, 0, 1e-5], [0.1, -0.2, 0.3, 0, 0, 0, 0]):
+        tau = np.array(tau)
+        assert np.abs(oracle.sim3_exp(tau, lib) - _sim3_generator_expm(tau)).max() <= 1e-10
+
+
+def _compose(A, T):
+    out = np.zeros((3, 4))
+    out[:, :3] = A[:, :3] @ T[:, :3]
+    out[:, 3] = A[:, :3] @ T[:, 3] + A[:, 3]
+    return out
+
+
+def pin_track_jacobians(lib):
+    """Ray and distance Jacobians w.r.t. a left perturbation of the pose (Supp. A,
+    Eq. point_jac, norm_jac, dist_jac) vs central differences of the residuals
+    under Exp(eps e_k) o T."""
+    rng = np.random.Generator(np.random.PCG64(13))
+    for _ in range(20):
+        T = oracle.sim3_exp(rng.normal(size=7) * 0.3, lib)
+        Xf = rng.normal(size=3) + np.array([0, 0, 3.0])
+        Xk = rng.normal(size=3) + np.array([0, 0, 3.0])
+        r, J = oracle.track_residual(T, Xf, Xk, lib)
+        eps = 1e-6
+        for k in range(7):
+            e = np.zeros(7); e[k] = eps
+            rp, _ = oracle.track_residual(_compose(oracle.sim3_exp(e, lib), T), Xf, Xk, lib)
+            rm, _ = oracle.track_residual(_compose(oracle.sim3_exp(-e, lib), T), Xf, Xk, lib)
+            fd = (rp - rm) / (2 * eps)
+            assert np.abs(fd - J[:, k]).max() <= 1e-7 * max(1.0, np.abs(J).max()), "Jacobian column %d" % k
+    # The ray residual does not depend on the scale (psi is depth invariant).
+    assert (J[:3, 6] == 0).all()
+
+
+def pin_track_recovers_pose(lib):
+    """Noise-free matches: 10 Gauss-Newton iterations from the identity recover
+    the true Sim(3) (Eq. gauss_newton with the left-plus update of Eq. 1)."""
+    for seed in (1, 2, 3):
+        tp = synth.make_tracking(24, 32, seed)
+        T0 = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+        T, info = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, lib=lib)
+        err = np.abs(T - tp.T_true).max()
+        assert info["solved"] == 10 and err <= 1e-6, "pose error %g" % err
+        assert np.abs(info["g"]).max() <= 1e-6 * max(1.0, np.abs(info["H"]).max())
+    # A large motion (90 deg, unit translation, scale 1.6) started near the truth:
+    # the step is a left perturbation, so it must be applied on the left.
+    tp = synth.make_tracking(24, 32, 9, max_deg=90.0, max_t=1.0, scale_range=(1.5, 1.7))
+    rng = np.random.Generator(np.random.PCG64(9))
+    T0 = _compose(oracle.sim3_exp(rng.normal(size=7) * 0.02, lib), tp.T_true)
+    T, info = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, iters=6, lib=lib)
+    assert np.abs(T - tp.T_true).max() <= 1e-6, "large-motion pose error %g" % np.abs(T - tp.T_true).max()
+
+
+def pin_track_distance_term(lib):
+    """Sec. 3.3: the ray residual alone leaves scale unobservable (its scale column
+    is zero), so the system is singular; the distance term makes it solvable,
+    also under pure rotation."""
+    tp = synth.make_tracking(24, 32, 4, pure_rotation=True)
+    T0 = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+    _, info = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, sigma_dist=math.inf, lib=lib)
+    assert info["solved"] == 0, "ray-only system must be singular"
+    T, info = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, lib=lib)
+    assert info["solved"] == 10 and np.abs(T - tp.T_true).max() <= 1e-6
+
+
+def pin_track_robust(lib):
+    """Huber weights (Sec. 3.3) bound the influence of gross outliers: with 20 %
+    displaced matches the robust pose is far closer to the truth than the
+    least-squares one; giving the outliers confidences below q_min removes them."""
+    tp = synth.make_tracking(24, 32, 5, noise=1e-3, outlier_frac=0.2)
+    T0 = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+    Tr, _ = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, iters=20, lib=lib)
+    Tl, _ = oracle.track_pose(tp.Xk, tp.Xf, tp.idx, tp.valid, tp.Qf, tp.Qk, T0, iters=20, huber=math.inf, lib=lib)
+    er, el = np.abs(Tr - tp.T_true).max(), np.abs(Tl - tp.T_true).max()
+    assert er < 0.2 * el, "robust %g vs least squares %g" % (er, el)
+    Qk = tp.Qk.copy()
+    Qk[tp.outlier] = 0.25                 # q = sqrt(Qf Qk) <= sqrt(5 * 0.25) < 1.5
+    tp_clean = synth.make_tracking(24, 32, 5, noise=0.0, outlier_frac=0.2)
+    Qk2 = tp_clean.Qk.copy()
+    Qk2[tp_clean.outlier] = 0.25
+    Tg, _ = oracle.track_pose(tp_clean.Xk, tp_clean.Xf, tp_clean.idx, tp_clean.valid, tp_clean.Qf, Qk2, T0,
+                              huber=math.inf, lib=lib)
+    assert np.abs(Tg - tp_clean.T_true).max() <= 1e-6, "confidence gate"
+
+
+def pin_track_confidence_weight(lib):
+    """The per-match weight is q / sigma^2 (Sec. 3.3, w(q, sigma^2) = sigma^2 / q):
+    one match of confidence 2q acts exactly like two identical matches of
+    confidence q.  Two groups of matches with different noise pull the pose
+    differently, so a weight not linear in q changes the result."""
+    H, W = 16, 32
+    tp = synth.make_tracking(H, W // 2, 8, noise=2e-2, valid_frac=1.0)
+    Xk = np.concatenate([tp.Xk, tp.Xk], 1)
+    Xf = tp.Xf
+    Xf2 = np.concatenate([Xf, Xf], 1)
+    idx_half = tp.idx
+    ys = np.arange(H)[:, None]
+    # Remap frame indices from the (H, W/2) frame to the (H, W) frame (left half).
+    idx_l = (idx_half // (W // 2)) * W + idx_half % (W // 2)
+    idx = np.concatenate([idx_l, idx_l], 1).astype(np.int32)
+    group2 = (np.arange(W // 2)[None, :] >= W // 4) & np.ones((H, 1), bool)
+    T0 = np.concatenate([np.eye(3), np.zeros((3, 1))], 1)
+    # A: left half only; group 1 with q = 2, group 2 with q = 4.
+    Qf = np.full((H, W), 2.0)
+    QkA = np.concatenate([np.where(group2, 8.0, 2.0), np.ones((H, W // 2))], 1)
+    validA = np.concatenate([np.ones((H, W // 2), bool), np.zeros((H, W // 2), bool)], 1)
+    # B: both halves; every match with q = 2, group 2 duplicated in the right half.
+    QkB = np.full((H, W), 2.0)
+    validB = np.concatenate([np.ones((H, W // 2), bool), group2], 1)
+    kw = dict(q_min=0.5, huber=math.inf, iters=15, lib=lib)
+    TA, _ = oracle.track_pose(Xk, Xf2, idx, validA, Qf, QkA, T0, **kw)
+    TB, _ = oracle.track_pose(Xk, Xf2, idx, validB, Qf, QkB, T0, **kw)
+    TC, _ = oracle.track_pose(Xk, Xf2, idx, validA, Qf, np.full((H, W), 2.0), T0, **kw)
+    assert np.abs(TA - TB).max() <= 1e-9, "weight must be linear in q"
+    assert np.abs(TA - TC).max() > 1e-5, "the two groups must pull the pose apart"
+
+
 # --------------------------------------------------------------- backward pins
 
 def _fd_setup(lib, K=20):
@@ -565,4 +701,6 @@ ALL_PINS = [
     pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
     pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init, pin_refine_coarse_to_fine, pin_match_stats,
     pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian, pin_bwd_held_border,
+    pin_sim3_exp, pin_track_jacobians, pin_track_recovers_pose, pin_track_distance_term, pin_track_robust,
+    pin_track_confidence_weight,
 ]

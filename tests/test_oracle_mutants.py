@@ -65,6 +65,28 @@ MUTANTS = {
                                         "gp0 += dxy * gx[k];\n                gp1 += dxx * gx[k];")],
 }
 
+# Edits of oracle/m3s_track_oracle.c; a third element True replaces every
+# occurrence (the same expression appears in the solver and in the residual
+# function).
+TRACK_MUTANTS = {
+    "track_rotation_jacobian_sign": [("J[i][3 + j] = -S[i][j] / d;", "J[i][3 + j] = S[i][j] / d;"),
+                                     ("J[7 * i + 3 + j] = -S[i][j] / d;", "J[7 * i + 3 + j] = S[i][j] / d;")],
+    "track_norm_jacobian_missing_1_over_d": [("J[i][j] = ((i == j ? 1.0 : 0.0) - u[i] * u[j]) / d;",
+                                              "J[i][j] = ((i == j ? 1.0 : 0.0) - u[i] * u[j]);"),
+                                             ("J[7 * i + j] = ((i == j ? 1.0 : 0.0) - u[i] * u[j]) / d;",
+                                              "J[7 * i + j] = ((i == j ? 1.0 : 0.0) - u[i] * u[j]);")],
+    "track_dist_scale_jacobian": [("J[3][6] = d;", "J[3][6] = 1.0;"), ("J[27] = d;", "J[27] = 1.0;")],
+    "track_right_plus_update": [("        compose(E, T);\n",
+                                 "        { double tmp[12]; memcpy(tmp, T, sizeof tmp); memcpy(T, E, sizeof tmp); compose(tmp, T); }\n")],
+    "track_exp_without_V": [("tv += V * v[j];", "tv += (i == j ? 1.0 : 0.0) * v[j];")],
+    "track_huber_weight_inverted": [("return a <= width ? 1.0 : width / a;", "return a <= width ? 1.0 : a / width;")],
+    "track_confidence_gate_ignored": [("if (!(q > q_min)) continue;", "")],
+    "track_weight_ignores_q": [("double w_ray = q / (sigma_ray * sigma_ray)", "double w_ray = 1.0 / (sigma_ray * sigma_ray)"),
+                               ("double w_dist = q / (sigma_dist * sigma_dist)", "double w_dist = 1.0 / (sigma_dist * sigma_dist)")],
+    "track_ray_residual_sign": [("double r[3] = {u[0] - Y[0] / dy, u[1] - Y[1] / dy, u[2] - Y[2] / dy};",
+                                 "double r[3] = {Y[0] / dy - u[0], Y[1] / dy - u[1], Y[2] / dy - u[2]};")],
+}
+
 _BATTERY = r"""
 import sys
 sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
@@ -79,15 +101,19 @@ print("SURVIVED"); sys.exit(3)
 """
 
 
-def _build_and_run(name, edits, tmpdir):
-    src = open(oracle._SRC).read()
+def _build_and_run(name, edits, tmpdir, which="match"):
+    path = oracle._SRC if which == "match" else oracle._TRACK_SRC
+    src = open(path).read()
     for old, new in edits:
         assert src.count(old) == 1, "mutant %s: snippet not found exactly once: %r" % (name, old)
         src = src.replace(old, new)
     cpath = os.path.join(tmpdir, name + ".c")
     with open(cpath, "w") as f:
         f.write(src)
-    lib = oracle.compile_oracle(cpath, os.path.join(tmpdir, "lib_" + name + ".so"))
+    if which == "match":
+        lib = oracle.compile_oracle(cpath, os.path.join(tmpdir, "lib_" + name + ".so"))
+    else:
+        lib = oracle.compile_oracle(oracle._SRC, os.path.join(tmpdir, "lib_" + name + ".so"), track_src=cpath)
     code = _BATTERY % dict(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=lib)
     env = dict(os.environ, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600, env=env)
@@ -95,8 +121,9 @@ def _build_and_run(name, edits, tmpdir):
 
 
 def test_every_mutant_is_caught(tmp_path):
+    jobs = [(k, v, "match") for k, v in MUTANTS.items()] + [(k, v, "track") for k, v in TRACK_MUTANTS.items()]
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
-        results = list(ex.map(lambda kv: _build_and_run(kv[0], kv[1], str(tmp_path)), MUTANTS.items()))
+        results = list(ex.map(lambda j: _build_and_run(j[0], j[1], str(tmp_path), j[2]), jobs))
     survived = [(n, out) for n, rc, out in results if rc == 3]
     for n, rc, out in results:
         print("%-32s rc=%d %s" % (n, rc, out.splitlines()[-1] if out else ""))
