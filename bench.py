@@ -144,7 +144,7 @@ def main():
         kt[name] = tot.value / max(cnt.value, 1)
     alg_bytes = FWD_BYTES_PER_QUERY * N
     achieved = alg_bytes / (kt["fwd"] * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": "fwd_kernel<32,8,24>", "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": "fwd_f16_kernel<16,16>", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None, "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_avg_us": round(kt["fwd"] * 1e3, 2), "prep_avg_us": round(kt["prep"] * 1e3, 2),
@@ -154,8 +154,9 @@ def main():
     # Forward kernel time per tile configuration (0-2: refine from global
     # memory; 3-4: refine region staged in LDS; 5: fp16 pre-filter), same pool and steps.
     sweep = {}
-    for tc in range(6):
+    for tc, remap in [(t, "1") for t in range(6)] + [(3, "0"), (5, "0")]:
         os.environ["M3S_TILE_CONFIG"] = str(tc)
+        os.environ["M3S_XCD_REMAP"] = remap
         lib.m3s_timing_reset()
         lib.m3s_timing_enable(1)
         for k in range(min(args.steps, 30)):
@@ -164,8 +165,9 @@ def main():
         lib.m3s_timing_enable(0)
         tot, cnt = ctypes.c_double(), ctypes.c_int64()
         lib.m3s_timing_read(b"fwd", ctypes.byref(tot), ctypes.byref(cnt))
-        sweep[str(tc)] = round(tot.value / max(cnt.value, 1) * 1e3, 2)
+        sweep["%d%s" % (tc, "" if remap == "1" else "_no_xcd_remap")] = round(tot.value / max(cnt.value, 1) * 1e3, 2)
     os.environ.pop("M3S_TILE_CONFIG", None)
+    os.environ.pop("M3S_XCD_REMAP", None)
     roofline["fwd_us_by_tile_config"] = sweep
     log("fwd kernel us by tile config:", sweep)
 

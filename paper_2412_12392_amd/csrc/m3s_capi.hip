@@ -135,6 +135,12 @@ EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P,
     return E;
 }
 
+// Tile-to-XCD band mapping of the single-pair launch (M3S_XCD_REMAP=0 turns it off).
+bool env_xcd_remap() {
+    const char* s = std::getenv("M3S_XCD_REMAP");
+    return !(s && s[0] == '0');
+}
+
 int env_tile_config() {
     const char* s = std::getenv("M3S_TILE_CONFIG");
     if (!s) return m3s::kDefaultTileConfig;
@@ -380,7 +386,7 @@ m3s_status m3s_match_fwd(const m3s_pair* pair, const m3s_params* params, const m
     EdgeArgs A = make_edge(pair, out, P, P->max_iter, P->refine_radius, rays);
     hipError_t e = m3s::launch_prep(pair->Xii, rays, pair->H, pair->W, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
-    e = m3s::launch_fwd(A, env_tile_config(), desc_in_regs(pair), st);
+    e = m3s::launch_fwd(A, env_tile_config(), desc_in_regs(pair), env_xcd_remap(), st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     g_last_error.clear();
     return M3S_OK;

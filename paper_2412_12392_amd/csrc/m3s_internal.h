@@ -14,7 +14,7 @@ namespace m3s {
 // 5: 16x16 with an fp16 copy of the region and an exact fp32 rescoring of the
 // candidates that can be the maximum (D = 24, r <= 5).
 constexpr int kNumTileConfigs = 6;
-constexpr int kDefaultTileConfig = 3;
+constexpr int kDefaultTileConfig = 5;
 void tile_shape(int tile_config, int* tx, int* ty);
 bool tile_uses_lds(int tile_config);
 
@@ -24,7 +24,7 @@ void timer_begin(const char* name, hipStream_t s);
 void timer_end(hipStream_t s);
 
 hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s);
-hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s);
+hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool xcd_remap, hipStream_t s);
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
                           int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs,
                           hipStream_t s);

@@ -51,6 +51,18 @@ __global__ void __launch_bounds__(256) prep_kernel(const float* __restrict__ X, 
     prep_pixel(X, rec, H, W, (int)(m % W), (int)(m / W));
 }
 
+// Tile of workgroup b in a 1-D launch over `tiles` tiles.  Workgroups are
+// dispatched to the 8 XCDs round-robin, so with remap on, XCD j (b % 8 == j)
+// takes the j-th contiguous band of tiles and neighbouring tiles share that
+// XCD's L2; returns -1 for the padding workgroups of the last band.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int tile_of_block(int b, int tiles, bool remap) {
+    if (!remap) return b < tiles ? b : -1;
+    const int per = (tiles + kXcds - 1) / kXcds;
+    const int t = (b % kXcds) * per + b / kXcds;
+    return t < tiles ? t : -1;
+}
+
 // ---------------------------------------------------------------- forward
 
 // Descriptor dot product of the query (in registers for a compile-time D)
@@ -249,9 +261,12 @@ __device__ __forceinline__ void match_query(const EdgeArgs& A, int x, int y) {
 }
 
 template <int TX, int TY, int DT>
-__global__ void __launch_bounds__(TX * TY) fwd_kernel(EdgeArgs A) {
-    int x = blockIdx.x * TX + (int)(threadIdx.x % TX);
-    int y = blockIdx.y * TY + (int)(threadIdx.x / TX);
+__global__ void __launch_bounds__(TX * TY) fwd_kernel(EdgeArgs A, int remap) {
+    const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
+    const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
+    if (t < 0) return;
+    int x = (t % tiles_x) * TX + (int)(threadIdx.x % TX);
+    int y = (t / tiles_x) * TY + (int)(threadIdx.x / TX);
     if (x >= A.W || y >= A.H) return;
     match_query<DT>(A, x, y);
 }
@@ -265,6 +280,12 @@ __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
     return v;
+}
+
+// ceil(2^32 / d): for 0 <= n < 2^16 and 1 <= d < 2^16, umulhi(n, magic) = n / d
+// (the rounding excess n (magic d - 2^32) / 2^32 stays below 1/d).
+__device__ __forceinline__ uint32_t div_magic(int d) {
+    return (uint32_t)((0x100000000ull + (unsigned long long)d - 1ull) / (unsigned long long)d);
 }
 
 // Region pixels of the LDS refine: 832 px x 96 B = 78 KiB, two workgroups per CU.
@@ -311,16 +332,23 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     const bool any = hx >= lx;
     const bool use_lds = any && rw * rh <= kRegionPx && A.levels == 1;
     if (use_lds) {
+        // Direct global -> LDS loads (no registers, all in flight at once).  LDS
+        // slot c = k * kRegionPx + pix holds float4 k of region pixel pix; each
+        // wave fills 64 consecutive slots, lane i the slot base + i.
+        constexpr int kSlots = 6 * kRegionPx;
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
-        const int row_chunks = rw * 6;
-        for (int ry = 0; ry < rh; ++ry) {
-            const float4* src = src4 + ((long)(ly + ry) * W + lx) * 6;
-            for (int c = tid; c < row_chunks; c += NT) {
-                int rx = c / 6;
-                int k = c - 6 * rx;
-                S.desc[k * kRegionPx + ry * rw + rx] = src[c];
+        const int np = rw * rh;
+        const uint32_t magic = div_magic(rw);
+        for (int c0 = tid & ~63; c0 < kSlots; c0 += NT) {
+            const int c = c0 + (tid & 63);
+            const int k = c / kRegionPx, pix = c - (c / kRegionPx) * kRegionPx;
+            if (k < 6 && pix < np) {
+                const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+                __builtin_amdgcn_global_load_lds(src4 + ((long)(ly + ry) * W + lx + rx) * 6 + k,
+                                                 (__attribute__((address_space(3))) void*)(S.desc + c0), 16, 0, 0);
             }
         }
+        __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     if (q.good) {
@@ -488,25 +516,43 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
     float pn2 = 0.f, pl1 = 0.f, pmax = 0.f;
     if (use16) {
-        // Stage: thread c handles pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7).
+        // Stage: chunk c is pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7),
+        // in batches of kBatch chunks per thread whose loads are all issued
+        // before their conversions and stores.
+        constexpr int kBatch = 5;
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
-        const int row_chunks = rw * 3;
-        for (int ry = 0; ry < rh; ++ry) {
-            const float4* src = src4 + ((long)(ly + ry) * W + lx) * 6;
-            for (int c = tid; c < row_chunks; c += NT) {
-                int rx = c / 3;
-                int k = c - 3 * rx;
-                float4 u = src[6 * rx + 2 * k], v = src[6 * rx + 2 * k + 1];
-                float e2 = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w + v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
-                float e1 = fabsf(u.x) + fabsf(u.y) + fabsf(u.z) + fabsf(u.w) + fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
-                float em = fmaxf(fmaxf(fmaxf(fabsf(u.x), fabsf(u.y)), fmaxf(fabsf(u.z), fabsf(u.w))),
-                                 fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-                // NaN propagates through the sums and fails the range test below.
-                pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
-                pl1 = fmaxf(pl1, isfinite(e1) ? e1 : INFINITY);
-                pmax = fmaxf(pmax, (em == em) ? em : INFINITY);
-                S.desc[k * kRegionPx16 + ry * rw + rx] =
-                    make_uint4(pack_h2(u.x, u.y), pack_h2(u.z, u.w), pack_h2(v.x, v.y), pack_h2(v.z, v.w));
+        const int total = rw * rh * 3;
+        const uint32_t magic = div_magic(rw);
+        for (int c00 = 0; c00 < total; c00 += kBatch * NT) {
+            float4 lu[kBatch], lv[kBatch];
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                const int c = c00 + tid + i * NT;
+                if (c < total) {
+                    const int pix = c / 3, k = c - 3 * (c / 3);
+                    const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+                    const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6 + 2 * k;
+                    lu[i] = src[0];
+                    lv[i] = src[1];
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < kBatch; ++i) {
+                const int c = c00 + tid + i * NT;
+                if (c < total) {
+                    const int pix = c / 3, k = c - 3 * (c / 3);
+                    const float4 u = lu[i], v = lv[i];
+                    float e2 = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w + v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+                    float e1 = fabsf(u.x) + fabsf(u.y) + fabsf(u.z) + fabsf(u.w) + fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
+                    float em = fmaxf(fmaxf(fmaxf(fabsf(u.x), fabsf(u.y)), fmaxf(fabsf(u.z), fabsf(u.w))),
+                                     fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+                    // NaN propagates through the sums and fails the range test below.
+                    pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
+                    pl1 = fmaxf(pl1, isfinite(e1) ? e1 : INFINITY);
+                    pmax = fmaxf(pmax, (em == em) ? em : INFINITY);
+                    S.desc[k * kRegionPx16 + pix] =
+                        make_uint4(pack_h2(u.x, u.y), pack_h2(u.z, u.w), pack_h2(v.x, v.y), pack_h2(v.z, v.w));
+                }
             }
         }
     }
@@ -534,16 +580,23 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     __syncthreads();  // the next tile may overwrite S
 }
 
+// Four workgroups of 256 lanes fit a CU by LDS; keep the registers within that too.
 template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) fwd_f16_kernel(EdgeArgs A) {
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4))) fwd_f16_kernel(EdgeArgs A, int remap) {
     __shared__ TileLds16 S;
-    tile_f16<TX, TY>(A, blockIdx.x, blockIdx.y, S);
+    const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
+    const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
+    if (t < 0) return;
+    tile_f16<TX, TY>(A, t % tiles_x, t / tiles_x, S);
 }
 
 template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) fwd_lds_kernel(EdgeArgs A) {
+__global__ void __launch_bounds__(TX * TY) fwd_lds_kernel(EdgeArgs A, int remap) {
     __shared__ TileLds S;
-    tile_lds<TX, TY>(A, blockIdx.x, blockIdx.y, S);
+    const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
+    const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
+    if (t < 0) return;
+    tile_lds<TX, TY>(A, t % tiles_x, t / tiles_x, S);
 }
 
 // ---------------------------------------------------------------- batched
@@ -578,7 +631,8 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
 // tile).  LDS tiles need D = 24 and 16-byte aligned descriptors on every edge.
 // MODE 0: refine from global memory; 1: fp32 region in LDS; 2: fp16 pre-filter.
 template <int TX, int TY, int DT, int MODE>
-__global__ void __launch_bounds__(TX * TY) batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? 4 : 1)))
+batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
                                                                int32_t* __restrict__ counter) {
     __shared__ int s_tile;
     __shared__ typename std::conditional<MODE == 1, TileLds, typename std::conditional<MODE == 2, TileLds16, int>::type>::type S;
@@ -761,16 +815,18 @@ hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t
 }
 
 template <int TX, int TY>
-static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, int mode, hipStream_t s) {
-    dim3 grid((A.W + TX - 1) / TX, (A.H + TY - 1) / TY);
+static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, int mode, bool remap, hipStream_t s) {
+    const int tiles = ((A.W + TX - 1) / TX) * ((A.H + TY - 1) / TY);
+    const int grid = remap ? ((tiles + kXcds - 1) / kXcds) * kXcds : tiles;
+    const int rm = remap ? 1 : 0;
     if (mode == 2 && desc_regs)
-        fwd_f16_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A);
+        fwd_f16_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A, rm);
     else if (mode == 1 && desc_regs)
-        fwd_lds_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A);
+        fwd_lds_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A, rm);
     else if (desc_regs)
-        fwd_kernel<TX, TY, 24><<<grid, TX * TY, 0, s>>>(A);
+        fwd_kernel<TX, TY, 24><<<grid, TX * TY, 0, s>>>(A, rm);
     else
-        fwd_kernel<TX, TY, 0><<<grid, TX * TY, 0, s>>>(A);
+        fwd_kernel<TX, TY, 0><<<grid, TX * TY, 0, s>>>(A, rm);
 }
 
 void tile_shape(int tile_config, int* tx, int* ty) {
@@ -783,15 +839,15 @@ void tile_shape(int tile_config, int* tx, int* ty) {
 
 bool tile_uses_lds(int tile_config) { return tile_config >= 3; }
 
-hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, hipStream_t s) {
+hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool xcd_remap, hipStream_t s) {
     timer_begin("fwd", s);
     switch (tile_config) {
-        case 1: launch_fwd_tile<16, 16>(A, desc_regs, 0, s); break;
-        case 2: launch_fwd_tile<64, 4>(A, desc_regs, 0, s); break;
-        case 3: launch_fwd_tile<16, 16>(A, desc_regs, 1, s); break;
-        case 4: launch_fwd_tile<32, 8>(A, desc_regs, 1, s); break;
-        case 5: launch_fwd_tile<16, 16>(A, desc_regs, 2, s); break;
-        default: launch_fwd_tile<32, 8>(A, desc_regs, 0, s); break;
+        case 1: launch_fwd_tile<16, 16>(A, desc_regs, 0, xcd_remap, s); break;
+        case 2: launch_fwd_tile<64, 4>(A, desc_regs, 0, xcd_remap, s); break;
+        case 3: launch_fwd_tile<16, 16>(A, desc_regs, 1, xcd_remap, s); break;
+        case 4: launch_fwd_tile<32, 8>(A, desc_regs, 1, xcd_remap, s); break;
+        case 5: launch_fwd_tile<16, 16>(A, desc_regs, 2, xcd_remap, s); break;
+        default: launch_fwd_tile<32, 8>(A, desc_regs, 0, xcd_remap, s); break;
     }
     timer_end(s);
     return hipGetLastError();
