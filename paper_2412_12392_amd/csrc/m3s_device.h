@@ -83,21 +83,12 @@ __device__ __forceinline__ float4 rec_load(RayBuf rb, uint32_t byte_off) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rb, byte_off, 0, 0));
 }
 
-// Ray error of Eq. 2 at pixel (px, py) (inside the domain) for target ray t.
-__device__ __forceinline__ void sample_ray_error(RayBuf rec, int H, int W,
-                                                 float px, float py, float3 t, Sample& s) {
-    int x0 = min((int)floorf(px), W - 2);
-    int y0 = min((int)floorf(py), H - 2);
-    float a = px - (float)x0, b = py - (float)y0;
-    const uint32_t rs = (uint32_t)kRecF4 * 16u;           // record stride (bytes)
-    const uint32_t o00 = ((uint32_t)y0 * (uint32_t)W + (uint32_t)x0) * rs;
-    const uint32_t o10 = o00 + rs, o01 = o00 + (uint32_t)W * rs, o11 = o01 + rs;
+// Ray error of Eq. 2 from the four ray records around p (A = (x0, y0),
+// B = (x0+1, y0), C = (x0, y0+1), D = (x0+1, y0+1)) with bilinear weights a, b.
+__device__ __forceinline__ void ray_error_from(const float4* A, const float4* B, const float4* C, const float4* D,
+                                               float a, float b, float3 t, Sample& s) {
     float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
-    float4 A0 = rec_load(rec, o00), A1 = rec_load(rec, o00 + 16), A2 = rec_load(rec, o00 + 32);
-    float4 B0 = rec_load(rec, o10), B1 = rec_load(rec, o10 + 16), B2 = rec_load(rec, o10 + 32);
-    float4 C0 = rec_load(rec, o01), C1 = rec_load(rec, o01 + 16), C2 = rec_load(rec, o01 + 32);
-    float4 D0 = rec_load(rec, o11), D1 = rec_load(rec, o11 + 16), D2 = rec_load(rec, o11 + 32);
-#define M3S_BL(i, c) (w00 * A##i.c + w10 * B##i.c + w01 * C##i.c + w11 * D##i.c)
+#define M3S_BL(i, c) (w00 * A[i].c + w10 * B[i].c + w01 * C[i].c + w11 * D[i].c)
     float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
     float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
     float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = M3S_BL(2, x);
@@ -124,17 +115,83 @@ __device__ __forceinline__ void sample_ray_error(RayBuf rec, int H, int W,
     s.g1 = jy0 * e0 + jy1 * e1 + jy2 * e2;
 }
 
+// Ray records from the workspace in global memory.
+struct GlobalRays {
+    RayBuf rb;
+    int W;
+    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D) const {
+        const uint32_t rs = (uint32_t)kRecF4 * 16u;
+        const uint32_t o00 = ((uint32_t)y0 * (uint32_t)W + (uint32_t)x0) * rs;
+        const uint32_t o10 = o00 + rs, o01 = o00 + (uint32_t)W * rs, o11 = o01 + rs;
+#pragma unroll
+        for (int j = 0; j < kRecF4; ++j) {
+            A[j] = rec_load(rb, o00 + 16 * j);
+            B[j] = rec_load(rb, o10 + 16 * j);
+            C[j] = rec_load(rb, o01 + 16 * j);
+            D[j] = rec_load(rb, o11 + 16 * j);
+        }
+    }
+};
+
+// Ray records of a window [rx0, rx0 + rw) x [ry0, ry0 + rh) staged in LDS
+// (record of window pixel k at lds[3k .. 3k+2]); cells outside the window
+// are read from global memory.  Same values either way.
+struct WindowRays {
+    const float4* lds;
+    int rx0, ry0, rw, rh;
+    GlobalRays g;
+    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D) const {
+        const int lx = x0 - rx0, ly = y0 - ry0;
+        if (lx >= 0 && ly >= 0 && lx + 1 < rw && ly + 1 < rh) {
+            const float4* a = lds + kRecF4 * (ly * rw + lx);
+            const float4* c = a + kRecF4 * rw;
+#pragma unroll
+            for (int j = 0; j < kRecF4; ++j) {
+                A[j] = a[j];
+                B[j] = a[kRecF4 + j];
+                C[j] = c[j];
+                D[j] = c[kRecF4 + j];
+            }
+        } else {
+            g.fetch(x0, y0, A, B, C, D);
+        }
+    }
+};
+
+// Ray error of Eq. 2 at pixel (px, py) (inside the domain) for target ray t.
+template <class Src>
+__device__ __forceinline__ void sample_ray_error(const Src& src, int H, int W, float px, float py, float3 t, Sample& s) {
+    int x0 = min((int)floorf(px), W - 2);
+    int y0 = min((int)floorf(py), H - 2);
+    float a = px - (float)x0, b = py - (float)y0;
+    float4 A[kRecF4], B[kRecF4], C[kRecF4], D[kRecF4];
+    src.fetch(x0, y0, A, B, C, D);
+    ray_error_from(A, B, C, D, a, b, t, s);
+}
+
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
 
-// K Levenberg-Marquardt iterations from (px, py); returns the final cost.
-__device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int H, int W, int K, float lambda0,
-                                            float3 t, float& px, float& py) {
-    const RayBuf rec = ray_buffer(rays, H, W);
-    Sample cur, nxt;
-    sample_ray_error(rec, H, W, px, py, t, cur);
-    float lambda = lambda0;
+// Levenberg-Marquardt state of one query: current pixel, damping and the
+// sample at the current pixel.
+struct LMState {
+    float px, py, lambda;
+    Sample cur;
+};
+
+template <class Src>
+__device__ __forceinline__ void lm_start(const Src& src, int H, int W, float lambda0, float3 t, LMState& st) {
+    sample_ray_error(src, H, W, st.px, st.py, t, st.cur);
+    st.lambda = lambda0;
+}
+
+// `iters` LM iterations on Eq. 2: damped 2x2 step, bound hold, clamp,
+// acceptance on strictly lower cost.
+template <class Src>
+__device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 t, int iters, LMState& st) {
     const float xmax = (float)(W - 1), ymax = (float)(H - 1);
-    for (int it = 0; it < K; ++it) {
+    float px = st.px, py = st.py, lambda = st.lambda;
+    Sample cur = st.cur, nxt;
+    for (int it = 0; it < iters; ++it) {
         float a00 = cur.a00 + lambda, a01 = cur.a01, a11 = cur.a11 + lambda;
         float g0 = cur.g0, g1 = cur.g1;
         float idet = rcp(a00 * a11 - a01 * a01);
@@ -151,7 +208,7 @@ __device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int
             dy = hold_y ? 0.f : fy;
         }
         float qx = clampf(px + dx, 0.f, xmax), qy = clampf(py + dy, 0.f, ymax);
-        sample_ray_error(rec, H, W, qx, qy, t, nxt);
+        sample_ray_error(src, H, W, qx, qy, t, nxt);
         // Accept on strictly lower cost: selects, no branch.
         const bool acc = nxt.c < cur.c;
         px = acc ? qx : px;
@@ -164,7 +221,19 @@ __device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int
         cur.g1 = acc ? nxt.g1 : cur.g1;
         lambda = acc ? lambda * 0.1f : lambda * 10.f;
     }
-    return cur.c;
+    st.px = px; st.py = py; st.lambda = lambda; st.cur = cur;
+}
+
+// K Levenberg-Marquardt iterations from (px, py) reading global memory; returns the final cost.
+__device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int H, int W, int K, float lambda0,
+                                            float3 t, float& px, float& py) {
+    const GlobalRays g{ray_buffer(rays, H, W), W};
+    LMState st;
+    st.px = px; st.py = py;
+    lm_start(g, H, W, lambda0, t, st);
+    lm_iterate(g, H, W, t, K, st);
+    px = st.px; py = st.py;
+    return st.cur.c;
 }
 
 }  // namespace m3s

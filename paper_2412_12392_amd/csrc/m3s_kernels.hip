@@ -114,9 +114,9 @@ struct QState {
     bool good;        // finite, non-zero query point and initial pixel
 };
 
-// Phase 1: Levenberg-Marquardt on Eq. 2, residual angle (Eq. 3) and xhat.
-// Writes p, theta, xhat; a bad query also gets its final idx / valid.
-__device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState& q) {
+// Phase 1a: query setup.  Reads x_n and the initial pixel; a bad query gets
+// its final outputs here and returns false.
+__device__ __forceinline__ bool lm_setup(const EdgeArgs& A, int x, int y, QState& q, float3& t, LMState& st) {
     const int H = A.H, W = A.W;
     const long n = (long)y * W + x;
     float3 xq = load_point(A.Xji, n);
@@ -135,20 +135,29 @@ __device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState
     if (!finite3(xq) || !(n2 > 0.f) || !isfinite(n2)) bad = true;
     q.xq = xq;
     q.good = !bad;
+    q.px = px; q.py = py; q.th = INFINITY;
     if (bad) {
-        q.px = px; q.py = py; q.th = INFINITY;
         reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
         A.idx[n] = -1;
         A.valid[n] = 0;
         if (A.theta) A.theta[n] = INFINITY;
         if (A.xhat) { A.xhat[3 * n] = NAN; A.xhat[3 * n + 1] = NAN; A.xhat[3 * n + 2] = NAN; }
-        return;
+        return false;
     }
     float inv = rsq(n2);
-    float3 t = f3(xq.x * inv, xq.y * inv, xq.z * inv);
-    float c = lm_project(A.rays, H, W, A.K, A.lambda0, t, px, py);
+    t = f3(xq.x * inv, xq.y * inv, xq.z * inv);
+    st.px = px;
+    st.py = py;
+    return true;
+}
+
+// Phase 1c: outputs of the LM: p*, residual angle (Eq. 3 solved for theta), xhat.
+__device__ __forceinline__ void lm_finish(const EdgeArgs& A, int x, int y, const LMState& st, QState& q) {
+    const int H = A.H, W = A.W;
+    const long n = (long)y * W + x;
+    const float px = st.px, py = st.py;
     reinterpret_cast<float2*>(A.p)[n] = make_float2(px, py);
-    float th = 2.0f * asinf(fminf(1.0f, sqrtf(c) * 0.5f));
+    float th = 2.0f * asinf(fminf(1.0f, sqrtf(st.cur.c) * 0.5f));
     if (A.theta) A.theta[n] = th;
     if (A.xhat) {
         int x0 = min((int)floorf(px), W - 2), y0 = min((int)floorf(py), H - 2);
@@ -162,6 +171,17 @@ __device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState
         A.xhat[3 * n + 2] = w00 * X00.z + w10 * X10.z + w01 * X01.z + w11 * X11.z;
     }
     q.px = px; q.py = py; q.th = th;
+}
+
+// Phase 1 through global memory: LM on Eq. 2, residual angle and xhat.
+__device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState& q) {
+    float3 t;
+    LMState st;
+    if (!lm_setup(A, x, y, q, t, st)) return;
+    const GlobalRays g{ray_buffer(A.rays, A.H, A.W), A.W};
+    lm_start(g, A.H, A.W, A.lambda0, t, st);
+    lm_iterate(g, A.H, A.W, t, A.K, st);
+    lm_finish(A, x, y, st, q);
 }
 
 // Refine window centre: p* rounded half up.
@@ -288,12 +308,91 @@ __device__ __forceinline__ uint32_t div_magic(int d) {
     return (uint32_t)((0x100000000ull + (unsigned long long)d - 1ull) / (unsigned long long)d);
 }
 
+// Bounding box (lx, hx, ly, hy) over the block: min / max of every lane's
+// values (INT_MAX / INT_MIN for lanes without one).  Ends with a barrier.
+template <int NT>
+__device__ __forceinline__ void block_box(int& lx, int& hx, int& ly, int& hy, int* box) {
+    const int tid = threadIdx.x;
+    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    const int wv = tid >> 6;
+    __syncthreads();  // earlier readers of box are done
+    if ((tid & 63) == 0) { box[4 * wv] = lx; box[4 * wv + 1] = hx; box[4 * wv + 2] = ly; box[4 * wv + 3] = hy; }
+    __syncthreads();
+    lx = box[0]; hx = box[1]; ly = box[2]; hy = box[3];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) {
+        lx = min(lx, box[4 * w]); hx = max(hx, box[4 * w + 1]);
+        ly = min(ly, box[4 * w + 2]); hy = max(hy, box[4 * w + 3]);
+    }
+}
+
+// Margin (pixels) of the staged ray window around the bilinear cells of the
+// tile's queries after the first LM iteration.
+constexpr int kRayMargin = 2;
+
+// Phase 1 of a tile with the ray records staged in LDS.  The first LM
+// iteration reads global memory; the window around the cells it reached
+// (plus kRayMargin) is then copied into `lds` (at most cap_px pixels, direct
+// global -> LDS loads) and the remaining iterations read it, falling back to
+// global memory for cells outside it.  All lanes of the block call this.
+template <int NT>
+__device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool inside, QState& q,
+                                        float4* lds, int cap_px, int* box) {
+    const int H = A.H, W = A.W, tid = threadIdx.x;
+    float3 t;
+    LMState st;
+    q.good = false;
+    const bool act = inside && lm_setup(A, x, y, q, t, st);
+    const GlobalRays g{ray_buffer(A.rays, H, W), W};
+    const int first = min(A.K, 1);
+    if (act) {
+        lm_start(g, H, W, A.lambda0, t, st);
+        lm_iterate(g, H, W, t, first, st);
+    }
+    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    if (act) {
+        const int cx = min((int)floorf(st.px), W - 2), cy = min((int)floorf(st.py), H - 2);
+        lx = max(cx - kRayMargin, 0); hx = min(cx + 1 + kRayMargin, W - 1);
+        ly = max(cy - kRayMargin, 0); hy = min(cy + 1 + kRayMargin, H - 1);
+    }
+    block_box<NT>(lx, hx, ly, hy, box);
+    const int rw = hx - lx + 1, rh = hy - ly + 1;
+    const bool stage = A.K > first && hx >= lx && rw * rh <= cap_px;
+    if (stage) {
+        const int slots = kRecF4 * rw * rh;
+        const uint32_t magic = div_magic(rw);
+        for (int c0 = tid & ~63; c0 < slots; c0 += NT) {
+            const int c = c0 + (tid & 63);
+            if (c < slots) {
+                const int pix = c / kRecF4, j = c - kRecF4 * (c / kRecF4);
+                const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+                __builtin_amdgcn_global_load_lds(A.rays + ((long)(ly + ry) * W + lx + rx) * kRecF4 + j,
+                                                 (__attribute__((address_space(3))) void*)(lds + c0), 16, 0, 0);
+            }
+        }
+        __builtin_amdgcn_s_waitcnt(0);
+    }
+    __syncthreads();
+    if (act) {
+        if (stage) {
+            const WindowRays wr{lds, lx, ly, rw, rh, g};
+            lm_iterate(wr, H, W, t, A.K - first, st);
+        } else {
+            lm_iterate(g, H, W, t, A.K - first, st);
+        }
+        lm_finish(A, x, y, st, q);
+    }
+}
+
 // Region pixels of the LDS refine: 832 px x 96 B = 78 KiB, two workgroups per CU.
 constexpr int kRegionPx = 832;
 
 // LDS needed by one tile of the LDS path.
 struct TileLds {
-    float4 desc[6 * kRegionPx];
+    union {
+        float4 desc[6 * kRegionPx];        // refine region (six planes)
+        float4 rays[6 * kRegionPx];        // LM ray window (records of up to 2 * kRegionPx pixels)
+    };
     int box[4 * 16];
 };
 
@@ -309,8 +408,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    q.good = false;
-    if (inside) lm_phase(A, x, y, q);
+    tile_lm<NT>(A, x, y, inside, q, S.rays, 2 * kRegionPx, S.box);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (q.good) {
@@ -318,16 +416,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
         lx = max(mx0 - r, 0); hx = min(mx0 + r, W - 1);
         ly = max(my0 - r, 0); hy = min(my0 + r, H - 1);
     }
-    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
-    const int wv = tid >> 6;
-    if ((tid & 63) == 0) { S.box[4 * wv] = lx; S.box[4 * wv + 1] = hx; S.box[4 * wv + 2] = ly; S.box[4 * wv + 3] = hy; }
-    __syncthreads();
-    lx = S.box[0]; hx = S.box[1]; ly = S.box[2]; hy = S.box[3];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) {
-        lx = min(lx, S.box[4 * w]); hx = max(hx, S.box[4 * w + 1]);
-        ly = min(ly, S.box[4 * w + 2]); hy = max(hy, S.box[4 * w + 3]);
-    }
+    block_box<NT>(lx, hx, ly, hy, S.box);
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
     const bool use_lds = any && rw * rh <= kRegionPx && A.levels == 1;
@@ -382,7 +471,10 @@ constexpr float kU32x24 = 1.4305115e-6f;  // 24 * 2^-24
 constexpr float kFlush16 = 6.1035156e-5f; // 2^-14
 
 struct TileLds16 {
-    uint4 desc[3 * kRegionPx16];
+    union {
+        uint4 desc[3 * kRegionPx16];       // refine region (three fp16 planes)
+        float4 rays[3 * kRegionPx16];      // LM ray window (records of up to kRegionPx16 pixels)
+    };
     int box[4 * 16];
     float stat[3 * 16];                   // per wave: max partial |d|^2, max partial |d|_1, max |d_k|
 };
@@ -492,8 +584,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    q.good = false;
-    if (inside) lm_phase(A, x, y, q);
+    tile_lm<NT>(A, x, y, inside, q, S.rays, kRegionPx16, S.box);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (q.good) {
@@ -501,16 +592,8 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
         lx = max(mx0 - r, 0); hx = min(mx0 + r, W - 1);
         ly = max(my0 - r, 0); hy = min(my0 + r, H - 1);
     }
-    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy);
+    block_box<NT>(lx, hx, ly, hy, S.box);
     const int wv = tid >> 6;
-    if ((tid & 63) == 0) { S.box[4 * wv] = lx; S.box[4 * wv + 1] = hx; S.box[4 * wv + 2] = ly; S.box[4 * wv + 3] = hy; }
-    __syncthreads();
-    lx = S.box[0]; hx = S.box[1]; ly = S.box[2]; hy = S.box[3];
-#pragma unroll
-    for (int w = 1; w < NT / 64; ++w) {
-        lx = min(lx, S.box[4 * w]); hx = max(hx, S.box[4 * w + 1]);
-        ly = min(ly, S.box[4 * w + 2]); hy = max(hy, S.box[4 * w + 3]);
-    }
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
     bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
