@@ -80,6 +80,8 @@ def _declare(lib):
     lib.oracle_sim3_exp.restype = None
     lib.oracle_track_residual.argtypes = [dp, dp, dp, dp, dp]
     lib.oracle_track_residual.restype = None
+    lib.oracle_fuse.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp]
+    lib.oracle_fuse.restype = None
     return lib
 
 
@@ -218,6 +220,17 @@ def track_pose(Xk, Xf, idx, valid, Qf, Qk, T0, *, q_min=1.5, sigma_ray=0.003, si
                                    float(q_min), float(sigma_ray), float(sigma_dist), float(huber), int(iters),
                                    _ptr(T), ctypes.byref(cost), ctypes.byref(count), _ptr(Hm), _ptr(g))
     return T.reshape(3, 4), dict(solved=solved, cost=cost.value, count=count.value, H=Hm.reshape(7, 7), g=g)
+
+
+def fuse(T, Xc, Cc, X, C, lib=None):
+    """Canonical pointmap update (Sec. 3.3, Eq. 8): returns the new (Xc, Cc) as fp64 arrays."""
+    lib = lib or load()
+    shape = np.shape(Xc)
+    N = int(np.prod(shape[:-1]))
+    Xc2 = _f64(Xc, (N, 3)).copy()
+    Cc2 = _f64(Cc, (N,)).copy()
+    lib.oracle_fuse(N, _ptr(_f64(T, (12,))), _ptr(Xc2), _ptr(Cc2), _ptr(_f64(X, (N, 3))), _ptr(_f64(C, (N,))))
+    return Xc2.reshape(shape), Cc2.reshape(shape[:-1])
 
 
 def max_threads(lib=None) -> int:

@@ -34,6 +34,9 @@
  * Cholesky, the step skipped if it is not positive definite.
  *
  * Pose layout: double T[12] = row-major 3x4 [sR | t].
+ *
+ * The file also holds the canonical pointmap fusion that follows the pose
+ * solve (Eq. 8), oracle_fuse.
  */
 #include <math.h>
 #include <stdint.h>
@@ -284,4 +287,27 @@ void oracle_track_residual(const double T[12], const double Xf_m[3], const doubl
     r[3] = d - dy;
     for (int j = 0; j < 3; ++j) { J[21 + j] = u[j]; J[24 + j] = 0.0; }
     J[27] = d;
+}
+
+/*
+ * oracle_fuse: the canonical pointmap update after tracking (Sec. 3.3, Eq. 8),
+ * per keyframe pixel n:
+ *   Xc[n] <- (Cc[n] Xc[n] + C[n] (T X[n])) / (Cc[n] + C[n]),  Cc[n] <- Cc[n] + C[n]
+ * where X is the frame's prediction of the keyframe's pointmap (X^k_f) and T
+ * the solved pose T_kf.  Reading where the paper is silent: a pixel whose
+ * summed confidence is not positive keeps its point (only Cc is updated).
+ * Xc (N*3) and Cc (N) are updated in place.
+ */
+void oracle_fuse(long N, const double T[12], double *Xc, double *Cc, const double *X, const double *C)
+{
+    for (long n = 0; n < N; ++n) {
+        double x[3];
+        apply_pose(T, X + 3 * n, x);
+        double c_old = Cc[n], c_new = C[n];
+        double c_sum = c_old + c_new;
+        if (c_sum > 0.0) {
+            for (int k = 0; k < 3; ++k) Xc[3 * n + k] = (c_old * Xc[3 * n + k] + c_new * x[k]) / c_sum;
+        }
+        Cc[n] = c_sum;
+    }
 }

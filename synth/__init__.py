@@ -289,3 +289,48 @@ def make_tracking(H: int, W: int, seed: int, *, max_deg: float = 5.0, max_t: flo
     f32 = lambda a, shape: np.ascontiguousarray(a.reshape(shape), dtype=np.float32)
     return TrackingProblem(H, W, f32(Xk, (H, W, 3)), f32(Xf, (H, W, 3)), idx.reshape(H, W).astype(np.int32),
                            valid.reshape(H, W), f32(Qf, (H, W)), f32(Qk, (H, W)), T, outlier.reshape(H, W))
+
+
+@dataclass
+class FusionProblem:
+    """Inputs of the canonical pointmap update (Sec. 3.3, Eq. 8).
+
+    Xc, Cc: the keyframe's canonical pointmap and its summed confidence;
+    X: a frame's prediction of the keyframe pixels' points in the frame's
+    coordinates (X^k_f), C its confidence; T: the 3x4 Sim(3) T_kf with
+    T X = P (+ noise) for the keyframe-frame points P.
+    """
+
+    H: int
+    W: int
+    Xc: np.ndarray
+    Cc: np.ndarray
+    X: np.ndarray
+    C: np.ndarray
+    T: np.ndarray
+    P: np.ndarray
+
+
+def make_fusion(H: int, W: int, seed: int, *, noise: float = 1e-2, zero_conf_frac: float = 0.02,
+                max_deg: float = 10.0, max_t: float = 0.1) -> FusionProblem:
+    """Keyframe surface points P; canonical map = P + noise with confidence
+    U(0.5, 20) (a few zeros); the frame's view of P through the inverse of a
+    random Sim(3) with its own noise and confidence U(1, 5) (a few zeros)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs, ys = pixel_grid(H, W)
+    P = surface_points(H, W, xs, ys).reshape(-1, 3)
+    s, R, t = random_sim3(rng, max_deg, max_t)
+    T = np.concatenate([s * R, t[:, None]], 1)
+    Xc = P + rng.normal(0.0, noise, size=P.shape)
+    Cc = rng.uniform(0.5, 20.0, size=H * W)
+    Cc[rng.uniform(size=H * W) < zero_conf_frac] = 0.0
+    Pn = P + rng.normal(0.0, noise, size=P.shape)
+    X = ((Pn - t) @ R) / s                      # T^-1 applied to the noisy points
+    C = rng.uniform(1.0, 5.0, size=H * W)
+    C[rng.uniform(size=H * W) < zero_conf_frac] = 0.0
+    both = rng.uniform(size=H * W) < zero_conf_frac
+    Cc[both] = 0.0
+    C[both] = 0.0
+    f32 = lambda a, shape: np.ascontiguousarray(a.reshape(shape), dtype=np.float32)
+    return FusionProblem(H, W, f32(Xc, (H, W, 3)), f32(Cc, (H, W)), f32(X, (H, W, 3)), f32(C, (H, W)), T,
+                         P.reshape(H, W, 3))

@@ -696,11 +696,53 @@ def pin_bwd_held_border(lib):
             "held border FD %s%s: fd %.8g adjoint %.8g" % (name, ix, fd, g)
 
 
+def pin_fuse_sequence_is_weighted_mean(lib):
+    """Eq. 8 folded over several frames is the confidence-weighted mean of the
+    transformed points, with the confidences summed (a closed form that
+    involves no running update), and a zero-confidence start returns T X."""
+    H, W = 12, 16
+    rng = np.random.Generator(np.random.PCG64(77))
+    P = rng.normal(size=(H * W, 3)) + np.array([0.0, 0.0, 3.0])
+    Xc = np.zeros((H * W, 3))
+    Cc = np.zeros(H * W)
+    num = np.zeros((H * W, 3))
+    den = np.zeros(H * W)
+    for k in range(4):
+        s, R, t = synth.random_sim3(rng, 30.0, 0.5, 0.7, 1.4)
+        T = np.concatenate([s * R, t[:, None]], 1)
+        Pk = P + rng.normal(0.0, 0.05, size=P.shape)
+        X = ((Pk - t) @ R) / s                     # the frame sees Pk through T^-1
+        C = rng.uniform(0.1, 5.0, size=H * W)
+        Xc, Cc = oracle.fuse(T, Xc, Cc, X, C, lib=lib)
+        num += C[:, None] * Pk
+        den += C
+        if k == 0:
+            assert np.abs(Xc - Pk).max() < 1e-12, "fusion into an empty map must give T X"
+    assert np.abs(Cc - den).max() < 1e-12
+    assert np.abs(Xc - num / den[:, None]).max() < 1e-12
+
+
+def pin_fuse_degenerate(lib):
+    """Zero new confidence keeps the map; zero summed confidence keeps the point."""
+    fp = synth.make_fusion(8, 10, 5)
+    C0 = np.zeros_like(fp.C, dtype=np.float64)
+    Xc, Cc = oracle.fuse(fp.T, fp.Xc, fp.Cc, fp.X, C0, lib=lib)
+    assert np.array_equal(Xc, fp.Xc.astype(np.float64)) and np.array_equal(Cc, fp.Cc.astype(np.float64))
+    Xc, Cc = oracle.fuse(fp.T, fp.Xc, np.zeros_like(Cc), fp.X, C0, lib=lib)
+    assert np.array_equal(Xc, fp.Xc.astype(np.float64)) and not Cc.any()
+    # Equal confidences: the midpoint of the old point and the transformed new one.
+    Xc, Cc = oracle.fuse(fp.T, fp.Xc, np.ones_like(Cc), fp.X, np.ones_like(Cc), lib=lib)
+    TX, _ = oracle.fuse(fp.T, np.zeros_like(fp.Xc), np.zeros_like(Cc), fp.X, np.ones_like(Cc), lib=lib)
+    assert np.abs(Xc - 0.5 * (fp.Xc + TX)).max() < 1e-12 and np.all(Cc == 2.0)
+    # T X is the keyframe-frame point up to the generator's noise (0.01 per axis).
+    assert np.abs(TX - fp.P).max() < 0.1
+
+
 ALL_PINS = [
     pin_identity, pin_pinhole, pin_brute_force, pin_depth_invariance, pin_border_angle,
     pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
     pin_dist_gate, pin_theta_gate, pin_bad_inputs, pin_p_init, pin_refine_coarse_to_fine, pin_match_stats,
     pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian, pin_bwd_held_border,
     pin_sim3_exp, pin_track_jacobians, pin_track_recovers_pose, pin_track_distance_term, pin_track_robust,
-    pin_track_confidence_weight,
+    pin_track_confidence_weight, pin_fuse_sequence_is_weighted_mean, pin_fuse_degenerate,
 ]

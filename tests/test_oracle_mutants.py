@@ -85,6 +85,10 @@ TRACK_MUTANTS = {
                                ("double w_dist = q / (sigma_dist * sigma_dist)", "double w_dist = 1.0 / (sigma_dist * sigma_dist)")],
     "track_ray_residual_sign": [("double r[3] = {u[0] - Y[0] / dy, u[1] - Y[1] / dy, u[2] - Y[2] / dy};",
                                  "double r[3] = {Y[0] / dy - u[0], Y[1] / dy - u[1], Y[2] / dy - u[2]};")],
+    "fuse_weights_swapped": [("(c_old * Xc[3 * n + k] + c_new * x[k])", "(c_new * Xc[3 * n + k] + c_old * x[k])")],
+    "fuse_untransformed": [("+ c_new * x[k]) / c_sum", "+ c_new * X[3 * n + k]) / c_sum")],
+    "fuse_confidence_not_summed": [("        Cc[n] = c_sum;\n", "        Cc[n] = c_new;\n")],
+    "fuse_no_normalisation": [(") / c_sum;", ") / (c_sum + 1.0);")],
 }
 
 _BATTERY = r"""
