@@ -22,6 +22,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "m3s_oracle.c")
 _TRACK_SRC = os.path.join(_HERE, "m3s_track_oracle.c")
+_BACKEND_SRC = os.path.join(_HERE, "m3s_backend_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle_m3s.so")
 
 # Defaults of the matching workloads: 10 LM iterations, lambda 1e-8, refine
@@ -29,11 +30,12 @@ _LIB_PATH = os.path.join(_HERE, "liboracle_m3s.so")
 DEFAULTS = dict(K=10, lambda0=1e-8, r=3, levels=1, conf_min=1.5, max_theta=1e-4, max_dist=math.inf)
 
 
-def compile_oracle(src: str = _SRC, out: str = _LIB_PATH, extra_flags=(), track_src: str = _TRACK_SRC) -> str:
-    """Compile the C oracle (matching and tracking sources) into a shared library (gcc, -O2, OpenMP)."""
+def compile_oracle(src: str = _SRC, out: str = _LIB_PATH, extra_flags=(), track_src: str = _TRACK_SRC,
+                   backend_src: str = _BACKEND_SRC) -> str:
+    """Compile the C oracle (matching, tracking and backend sources) into a shared library (gcc, -O2, OpenMP)."""
     tmp = out + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-fno-fast-math",
-           "-ffp-contract=off", *extra_flags, src, track_src, "-o", tmp, "-lm"]
+           "-ffp-contract=off", *extra_flags, src, track_src, backend_src, "-o", tmp, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, out)
     return out
@@ -48,8 +50,8 @@ def load(path: str | None = None):
     if path is not None:
         return _declare(ctypes.CDLL(path))
     if _lib is None:
-        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < max(os.path.getmtime(_SRC),
-                                                                               os.path.getmtime(_TRACK_SRC)):
+        newest = max(os.path.getmtime(f) for f in (_SRC, _TRACK_SRC, _BACKEND_SRC))
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < newest:
             compile_oracle()
         _lib = _declare(ctypes.CDLL(_LIB_PATH))
     return _lib
@@ -82,6 +84,11 @@ def _declare(lib):
     lib.oracle_track_residual.restype = None
     lib.oracle_fuse.argtypes = [ctypes.c_long, dp, dp, dp, dp, dp]
     lib.oracle_fuse.restype = None
+    lib.oracle_backend_residual.argtypes = [dp, dp, dp, dp, dp, dp, dp]
+    lib.oracle_backend_residual.restype = c_int
+    lib.oracle_backend_gn.argtypes = [c_int, c_int, c_int, dp, dp, c_int, ip, ip, ip, up, c_double, c_double,
+                                      c_double, c_double, c_int, c_double, dp, dp, ctypes.POINTER(c_long), dp]
+    lib.oracle_backend_gn.restype = c_int
     return lib
 
 
@@ -231,6 +238,43 @@ def fuse(T, Xc, Cc, X, C, lib=None):
     Cc2 = _f64(Cc, (N,)).copy()
     lib.oracle_fuse(N, _ptr(_f64(T, (12,))), _ptr(Xc2), _ptr(Cc2), _ptr(_f64(X, (N, 3))), _ptr(_f64(C, (N,))))
     return Xc2.reshape(shape), Cc2.reshape(shape[:-1])
+
+
+def backend_residual(Ti, Tj, Xj_n, Xi_m, lib=None):
+    """Ray (3) and distance (1) residuals of one backend match and their 4x7 Jacobians
+    w.r.t. the world poses of keyframes i and j (Sec. 3.5, Supp. A)."""
+    lib = lib or load()
+    r = np.empty(4); Ji = np.empty(28); Jj = np.empty(28)
+    ok = lib.oracle_backend_residual(_ptr(_f64(Ti, (12,))), _ptr(_f64(Tj, (12,))), _ptr(_f64(Xj_n, (3,))),
+                                     _ptr(_f64(Xi_m, (3,))), _ptr(r), _ptr(Ji), _ptr(Jj))
+    if not ok:
+        raise ValueError("degenerate point")
+    return r, Ji.reshape(4, 7), Jj.reshape(4, 7)
+
+
+BACKEND_DEFAULTS = dict(q_min=1.5, sigma_ray=0.003, sigma_dist=0.1, huber=1.345, iters=10, step_tol=0.0)
+
+
+def backend_gn(Xc, Q, edges, idx, valid, T_WC, *, q_min=1.5, sigma_ray=0.003, sigma_dist=0.1, huber=1.345,
+               iters=10, step_tol=0.0, lib=None):
+    """Backend Gauss-Newton over keyframe poses (Sec. 3.5).  Xc (N, H, W, 3), Q (N, H, W),
+    edges (E, 2) as (i, j), idx/valid (E, H, W), T_WC (N, 3, 4).  Returns (T_WC, info)."""
+    lib = lib or load()
+    N, H, W = np.shape(Xc)[:3]
+    E = len(edges)
+    HW = H * W
+    edges = np.asarray(edges, np.int32).reshape(E, 2)
+    ei = np.ascontiguousarray(edges[:, 0]); ej = np.ascontiguousarray(edges[:, 1])
+    idx = np.ascontiguousarray(np.asarray(idx).reshape(E * HW), dtype=np.int32)
+    valid = np.ascontiguousarray(np.asarray(valid).reshape(E * HW).astype(np.uint8))
+    T = _f64(T_WC, (N * 12,)).copy()
+    cost = ctypes.c_double(); count = ctypes.c_long(); last = ctypes.c_double()
+    applied = lib.oracle_backend_gn(N, H, W, _ptr(_f64(Xc, (N * HW, 3))), _ptr(_f64(Q, (N * HW,))), E,
+                                    _ptr(ei, ctypes.c_int32), _ptr(ej, ctypes.c_int32), _ptr(idx, ctypes.c_int32),
+                                    _ptr(valid, ctypes.c_uint8), float(q_min), float(sigma_ray), float(sigma_dist),
+                                    float(huber), int(iters), float(step_tol), _ptr(T), ctypes.byref(cost),
+                                    ctypes.byref(count), ctypes.byref(last))
+    return T.reshape(N, 3, 4), dict(applied=applied, cost=cost.value, count=count.value, last_step=last.value)
 
 
 def max_threads(lib=None) -> int:

@@ -334,3 +334,94 @@ def make_fusion(H: int, W: int, seed: int, *, noise: float = 1e-2, zero_conf_fra
     f32 = lambda a, shape: np.ascontiguousarray(a.reshape(shape), dtype=np.float32)
     return FusionProblem(H, W, f32(Xc, (H, W, 3)), f32(Cc, (H, W)), f32(X, (H, W, 3)), f32(C, (H, W)), T,
                          P.reshape(H, W, 3))
+
+
+@dataclass
+class BackendProblem:
+    """Inputs of the backend pose-graph optimisation (Sec. 3.5).
+
+    N keyframes of one H x W resolution.  Xc[k]: canonical pointmap of keyframe
+    k in its own camera; Q[k]: its confidence; edges[e] = (i, j) with idx[e][n]
+    the pixel of keyframe i matched to pixel n of keyframe j and valid[e][n];
+    T_true[k] / T_init[k]: 3x4 world poses (keyframe 0 is the same in both).
+    """
+
+    N: int
+    H: int
+    W: int
+    Xc: np.ndarray
+    Q: np.ndarray
+    edges: np.ndarray
+    idx: np.ndarray
+    valid: np.ndarray
+    T_true: np.ndarray
+    T_init: np.ndarray
+
+
+def _sim3_matrix(s, R, t):
+    return np.concatenate([s * R, np.asarray(t, np.float64)[:, None]], 1)
+
+
+def _sim3_mul(A, B):
+    return np.concatenate([A[:, :3] @ B[:, :3], (A[:, :3] @ B[:, 3] + A[:, 3])[:, None]], 1)
+
+
+def _sim3_inv(T):
+    s = np.cbrt(np.linalg.det(T[:, :3]))
+    Ri = T[:, :3].T / (s * s)
+    return np.concatenate([Ri, (-Ri @ T[:, 3])[:, None]], 1)
+
+
+def make_backend(N: int, H: int, W: int, seed: int, *, loops: int = 1, scramble: bool = True,
+                 noise: float = 0.0, outlier_frac: float = 0.0, valid_frac: float = 0.95,
+                 init_deg: float = 2.0, init_t: float = 0.02, init_scale=(0.98, 1.02)) -> BackendProblem:
+    """World points on the procedural surface seen by N keyframes along a path.
+
+    Keyframe k's pixel pi_k(p) sees world point P[p] (pi_k a random pixel
+    permutation when `scramble`, else the identity), so an edge (i, j) matches
+    pixel n of j to pi_i(pi_j^-1(n)).  Edges: both directions between
+    consecutive keyframes, plus `loops` closures (k, N-1-k).  Initial poses:
+    the true ones times a small random Sim(3), keyframe 0 exact."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    xs, ys = pixel_grid(H, W)
+    P0 = surface_points(H, W, xs, ys).reshape(-1, 3)
+    HW = H * W
+    T_true = np.zeros((N, 3, 4))
+    T_init = np.zeros((N, 3, 4))
+    for k in range(N):
+        if k == 0:
+            T_true[k] = _sim3_matrix(1.0, np.eye(3), np.zeros(3))
+        else:
+            s, R, t = random_sim3(rng, 8.0, 0.15, 0.9, 1.1)
+            T_true[k] = _sim3_mul(T_true[k - 1], _sim3_matrix(s, R, t))
+        ds, dR, dt = random_sim3(rng, init_deg, init_t, *init_scale)
+        T_init[k] = T_true[k] if k == 0 else _sim3_mul(_sim3_matrix(ds, dR, dt), T_true[k])
+    perms = [rng.permutation(HW) if scramble else np.arange(HW) for _ in range(N)]
+    Xc = np.zeros((N, HW, 3))
+    for k in range(N):
+        Tinv = _sim3_inv(T_true[k])
+        Xk = np.zeros((HW, 3))
+        Xk[perms[k]] = P0 @ Tinv[:, :3].T + Tinv[:, 3]
+        if noise > 0:
+            Xk = Xk + rng.normal(0.0, noise, size=Xk.shape)
+        Xc[k] = Xk
+    pairs = []
+    for k in range(1, N):
+        pairs += [(k - 1, k), (k, k - 1)]
+    for c in range(loops):
+        i, j = c, N - 1 - c
+        if j - i > 1:
+            pairs.append((i, j))
+    E = len(pairs)
+    idx = np.zeros((E, HW), np.int32)
+    valid = np.zeros((E, HW), bool)
+    inv_perm = [np.argsort(p) for p in perms]
+    for e, (i, j) in enumerate(pairs):
+        idx[e] = perms[i][inv_perm[j]]
+        valid[e] = rng.uniform(size=HW) < valid_frac
+        bad = rng.uniform(size=HW) < outlier_frac
+        idx[e][bad] = rng.integers(0, HW, size=int(bad.sum()))
+    Q = rng.uniform(1.0, 5.0, size=(N, HW))
+    f32 = lambda a, shape: np.ascontiguousarray(a.reshape(shape), dtype=np.float32)
+    return BackendProblem(N, H, W, f32(Xc, (N, H, W, 3)), f32(Q, (N, H, W)), np.array(pairs, np.int32),
+                          idx.reshape(E, H, W), valid.reshape(E, H, W), T_true, T_init)

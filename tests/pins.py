@@ -738,6 +738,100 @@ def pin_fuse_degenerate(lib):
     assert np.abs(TX - fp.P).max() < 0.1
 
 
+def _sim3_rand(rng, deg=20.0, tmax=0.5, smin=0.7, smax=1.4):
+    s, R, t = synth.random_sim3(rng, deg, tmax, smin, smax)
+    return np.concatenate([s * R, t[:, None]], 1)
+
+
+def _pose_gap(A, B):
+    """Largest entry-wise difference of two 3x4 poses."""
+    return float(np.abs(np.asarray(A) - np.asarray(B)).max())
+
+
+def pin_backend_jacobians(lib):
+    """Central differences of the backend residuals under left perturbations
+    Exp(eps e_k) T of each world pose match the analytic Jacobians (Supp. A,
+    relative-to-global chain rule); the residuals depend on T_i^-1 T_j only."""
+    rng = np.random.Generator(np.random.PCG64(31))
+    for trial in range(4):
+        Ti, Tj = _sim3_rand(rng), _sim3_rand(rng)
+        Xj = rng.normal(size=3) + np.array([0.0, 0.0, 3.0])
+        Xi = rng.normal(size=3) + np.array([0.0, 0.0, 3.0])
+        r, Ji, Jj = oracle.backend_residual(Ti, Tj, Xj, Xi, lib=lib)
+        eps = 1e-6
+        for which, J in (("i", Ji), ("j", Jj)):
+            for k in range(7):
+                tau = np.zeros(7)
+                tau[k] = eps
+                Ep, Em = oracle.sim3_exp(tau, lib=lib), oracle.sim3_exp(-tau, lib=lib)
+                if which == "i":
+                    rp = oracle.backend_residual(_compose(Ep, Ti), Tj, Xj, Xi, lib=lib)[0]
+                    rm = oracle.backend_residual(_compose(Em, Ti), Tj, Xj, Xi, lib=lib)[0]
+                else:
+                    rp = oracle.backend_residual(Ti, _compose(Ep, Tj), Xj, Xi, lib=lib)[0]
+                    rm = oracle.backend_residual(Ti, _compose(Em, Tj), Xj, Xi, lib=lib)[0]
+                fd = (rp - rm) / (2 * eps)
+                assert np.abs(fd - J[:, k]).max() <= 1e-6 * max(1.0, np.abs(J).max()), \
+                    "backend J_%s column %d: fd %s analytic %s" % (which, k, fd, J[:, k])
+        # A common world transform G leaves the residuals unchanged.
+        G = _sim3_rand(rng)
+        r2 = oracle.backend_residual(_compose(G, Ti), _compose(G, Tj), Xj, Xi, lib=lib)[0]
+        assert np.abs(r2 - r).max() < 1e-12
+
+
+def pin_backend_two_keyframes_is_tracking(lib):
+    """Two keyframes with the first held at a pose G and pixel-aligned matches:
+    each backend step on T_WC1 is the tracking step on T_01 = G^-1 T_WC1
+    carried by Ad(G), so the backend ends at G times the tracking result."""
+    bp = synth.make_backend(2, 12, 16, 41, scramble=False, noise=1e-3, loops=0)
+    rng = np.random.Generator(np.random.PCG64(42))
+    G = _sim3_rand(rng)
+    T0 = np.stack([G, _compose(G, bp.T_init[1])])
+    edges = np.array([[0, 1]], np.int32)
+    idx = np.arange(12 * 16, dtype=np.int32).reshape(1, 12, 16)
+    valid = bp.valid[:1]
+    T_b, info = oracle.backend_gn(bp.Xc, bp.Q, edges, idx, valid, T0, iters=6, lib=lib)
+    T_t, tinfo = oracle.track_pose(bp.Xc[0], bp.Xc[1], idx[0], valid[0], bp.Q[1], bp.Q[0], bp.T_init[1],
+                                   iters=6, lib=lib)
+    assert np.array_equal(T_b[0], T0[0]), "the gauge keyframe moved"
+    assert _pose_gap(T_b[1], _compose(G, T_t)) < 1e-9, _pose_gap(T_b[1], _compose(G, T_t))
+    assert info["count"] == tinfo["count"] and abs(info["cost"] - tinfo["cost"]) <= 1e-9 * max(tinfo["cost"], 1.0)
+
+
+def pin_backend_recovers_poses(lib):
+    """Noise-free keyframe chain with a loop closure and scrambled pixel
+    correspondences: from perturbed poses, Gauss-Newton reaches the generating
+    poses; a world transform of the start transforms the result (gauge)."""
+    bp = synth.make_backend(5, 10, 12, 43, scramble=True, loops=1)
+    T, info = oracle.backend_gn(bp.Xc, bp.Q, bp.edges, bp.idx, bp.valid, bp.T_init, iters=12, lib=lib)
+    assert np.array_equal(T[0], bp.T_init[0])
+    for k in range(bp.N):
+        assert _pose_gap(T[k], bp.T_true[k]) < 2e-6, (k, _pose_gap(T[k], bp.T_true[k]))
+    assert info["last_step"] < 1e-6 and info["applied"] == 12
+    G = _sim3_rand(np.random.Generator(np.random.PCG64(44)))
+    TG = np.stack([_compose(G, t) for t in bp.T_init])
+    T2, _ = oracle.backend_gn(bp.Xc, bp.Q, bp.edges, bp.idx, bp.valid, TG, iters=12, lib=lib)
+    for k in range(bp.N):
+        assert _pose_gap(T2[k], _compose(G, T[k])) < 1e-8
+    # Early exit: a step tolerance stops the loop once the steps are small.
+    T3, info3 = oracle.backend_gn(bp.Xc, bp.Q, bp.edges, bp.idx, bp.valid, bp.T_init, iters=50, step_tol=1e-9,
+                                  lib=lib)
+    assert info3["applied"] < 50 and info3["last_step"] < 1e-9
+
+
+def pin_backend_robust(lib):
+    """Noise and 10 % gross outliers: the Huber-weighted solve stays close to
+    the generating poses, and the plain least-squares solve does worse."""
+    bp = synth.make_backend(4, 16, 20, 45, scramble=True, noise=1e-3, outlier_frac=0.1, loops=1)
+    T, _ = oracle.backend_gn(bp.Xc, bp.Q, bp.edges, bp.idx, bp.valid, bp.T_init, iters=10, lib=lib)
+    Tl, _ = oracle.backend_gn(bp.Xc, bp.Q, bp.edges, bp.idx, bp.valid, bp.T_init, iters=10, huber=float("inf"),
+                              lib=lib)
+    err = max(_pose_gap(T[k], bp.T_true[k]) for k in range(bp.N))
+    err_ls = max(_pose_gap(Tl[k], bp.T_true[k]) for k in range(bp.N))
+    assert err < 5e-3, err
+    assert err_ls > 2 * err, (err, err_ls)
+
+
 ALL_PINS = [
     pin_identity, pin_pinhole, pin_brute_force, pin_depth_invariance, pin_border_angle,
     pin_gradient_images, pin_convergence, pin_refine_planted, pin_refine_ties, pin_conf_gate,
@@ -745,4 +839,5 @@ ALL_PINS = [
     pin_bwd_fd, pin_bwd_unrolled, pin_bwd_orthogonal, pin_bwd_projection_jacobian, pin_bwd_held_border,
     pin_sim3_exp, pin_track_jacobians, pin_track_recovers_pose, pin_track_distance_term, pin_track_robust,
     pin_track_confidence_weight, pin_fuse_sequence_is_weighted_mean, pin_fuse_degenerate,
+    pin_backend_jacobians, pin_backend_two_keyframes_is_tracking, pin_backend_recovers_poses, pin_backend_robust,
 ]

@@ -91,6 +91,19 @@ TRACK_MUTANTS = {
     "fuse_no_normalisation": [(") / c_sum;", ") / (c_sum + 1.0);")],
 }
 
+BACKEND_MUTANTS = {
+    "backend_sign_of_i_jacobian": [("Ji[7 * a + b] = -s;", "Ji[7 * a + b] = s;")],
+    "backend_adjoint_of_pose_not_inverse": [("bk_adjoint(Tii, A);", "bk_adjoint(Ti, A);")],
+    "backend_relative_pose_order": [("bk_mul(Tii, Tj, Tij);", "bk_mul(Tj, Tii, Tij);")],
+    "backend_adjoint_missing_cross_term": [("A[7 * i + 3 + j] = tr;", "A[7 * i + 3 + j] = 0.0;")],
+    "backend_adjoint_scale_column_sign": [("A[7 * i + 6] = -t[i];", "A[7 * i + 6] = t[i];")],
+    "backend_gauge_fixes_wrong_block": [("b[r] = -sys.g[7 + r];", "b[r] = -sys.g[r];")],
+    "backend_no_cross_blocks": [("for (int c = 0; c < 2; ++c)", "for (int c = p; c <= p; ++c)")],
+    "backend_right_update": [("bk_mul(E7, T_WC + 12 * k, Tn);", "bk_mul(T_WC + 12 * k, E7, Tn);")],
+    "backend_inverse_scale": [("out[4 * i + j] = T[4 * j + i] / s2;", "out[4 * i + j] = T[4 * j + i] / s;")],
+    "backend_measured_point_swapped": [("Xc + 3 * ((long)i * HW + m), r, Ji, Jj))", "Xc + 3 * ((long)i * HW + n), r, Ji, Jj))")],
+}
+
 _BATTERY = r"""
 import sys
 sys.path.insert(0, %(root)r); sys.path.insert(0, %(tests)r)
@@ -106,7 +119,7 @@ print("SURVIVED"); sys.exit(3)
 
 
 def _build_and_run(name, edits, tmpdir, which="match"):
-    path = oracle._SRC if which == "match" else oracle._TRACK_SRC
+    path = {"match": oracle._SRC, "track": oracle._TRACK_SRC, "backend": oracle._BACKEND_SRC}[which]
     src = open(path).read()
     for old, new in edits:
         assert src.count(old) == 1, "mutant %s: snippet not found exactly once: %r" % (name, old)
@@ -114,10 +127,13 @@ def _build_and_run(name, edits, tmpdir, which="match"):
     cpath = os.path.join(tmpdir, name + ".c")
     with open(cpath, "w") as f:
         f.write(src)
+    out = os.path.join(tmpdir, "lib_" + name + ".so")
     if which == "match":
-        lib = oracle.compile_oracle(cpath, os.path.join(tmpdir, "lib_" + name + ".so"))
+        lib = oracle.compile_oracle(cpath, out)
+    elif which == "track":
+        lib = oracle.compile_oracle(oracle._SRC, out, track_src=cpath)
     else:
-        lib = oracle.compile_oracle(oracle._SRC, os.path.join(tmpdir, "lib_" + name + ".so"), track_src=cpath)
+        lib = oracle.compile_oracle(oracle._SRC, out, backend_src=cpath)
     code = _BATTERY % dict(root=ROOT, tests=os.path.join(ROOT, "tests"), lib=lib)
     env = dict(os.environ, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=600, env=env)
@@ -125,7 +141,8 @@ def _build_and_run(name, edits, tmpdir, which="match"):
 
 
 def test_every_mutant_is_caught(tmp_path):
-    jobs = [(k, v, "match") for k, v in MUTANTS.items()] + [(k, v, "track") for k, v in TRACK_MUTANTS.items()]
+    jobs = ([(k, v, "match") for k, v in MUTANTS.items()] + [(k, v, "track") for k, v in TRACK_MUTANTS.items()] +
+            [(k, v, "backend") for k, v in BACKEND_MUTANTS.items()])
     with cf.ThreadPoolExecutor(max_workers=4) as ex:
         results = list(ex.map(lambda j: _build_and_run(j[0], j[1], str(tmp_path), j[2]), jobs))
     survived = [(n, out) for n, rc, out in results if rc == 3]
