@@ -14,8 +14,10 @@
  * descriptor dot product in a small window (Sec. 3.2, feature refinement), and
  * gates it by residual angle, match confidence sqrt(Q^i_i[m] Q^j_i[n])
  * (Sec. 3.3) and 3D distance (Sec. 3.2, occlusion and outlier handling).
- * A backward pass gives the implicit adjoint of the converged match, and a
- * batched entry point matches many edges of a keyframe graph in one launch.
+ * A backward pass gives the implicit adjoint of the converged match, a
+ * batched entry point matches many edges of a keyframe graph in one launch,
+ * and the tracking entry point solves a frame's Sim(3) pose from its matches
+ * (Sec. 3.3).
  *
  * Conventions shared by every entry point:
  *   - All array arguments are caller-owned DEVICE memory (HBM of the current
@@ -171,6 +173,91 @@ size_t m3s_stats_workspace_bytes(int32_t H, int32_t W);
 m3s_status m3s_match_stats(const m3s_outputs *fwd, int32_t H, int32_t W, int32_t *counts,
                            void *ws, size_t ws_bytes, void *stream);
 
+/*
+ * Tracking pose solve (Sec. 3.3).  The current frame f is matched to the last
+ * keyframe k with the keyframe's pixels as queries (m3s_match_fwd with
+ * Xii = X^f_f and Xji = X^k_f), so idx[n] is the frame pixel m of keyframe
+ * pixel n.  The pose T_kf = [sR | t] (Sim(3), maps frame points into the
+ * keyframe) is refined by Gauss-Newton in an iteratively reweighted
+ * least-squares loop (Eq. gauss_newton) over every valid match with
+ * q = sqrt(Qf[m] Qk[n]) > q_min:
+ *   ray residual      psi(T Xf[m]) - psi(Xk[n])    weight q / sigma_ray^2
+ *   distance residual |T Xf[m]| - |Xk[n]|           weight q / sigma_dist^2
+ * each weight times the Huber weight of the block's whitened norm
+ * |r| sqrt(q) / sigma (width `huber`); Jacobians w.r.t. a left perturbation
+ * tau = (v, omega, sigma) (Supp. A); the 7x7 normal equations are summed,
+ * solved by Cholesky in fp64 (a step whose system is not positive definite
+ * is skipped) and applied as T <- Exp(tau) o T (Eq. 1).  Residuals and
+ * Jacobians are evaluated in fp32, the normal equations summed in fp32 per
+ * workgroup and in fp64 across workgroups; the confidence gate is decided in
+ * fp64.
+ */
+typedef struct {
+    int32_t iters;          /* Gauss-Newton iterations, run exactly, in [0, M3S_MAX_ITER] */
+    float   q_min;          /* confidence gate: a match needs q > q_min; finite */
+    float   sigma_ray;      /* ray residual sigma, > 0; +inf drops the ray residual */
+    float   sigma_dist;     /* distance residual sigma, > 0; +inf drops the distance residual */
+    float   huber;          /* Huber width on the whitened norm, > 0; +inf = plain least squares */
+} m3s_track_params;
+
+/* One tracking problem: keyframe k and current frame f, same H x W. */
+typedef struct {
+    int32_t H, W;
+    const float   *Xk;      /* [H*W*3] keyframe points X~^k_k (the measurements, required) */
+    const float   *Xf;      /* [H*W*3] frame points X^f_f (required) */
+    const int32_t *idx;     /* [H*W]   match of keyframe pixel n: frame pixel in [0, H*W), or < 0 (required) */
+    const uint8_t *valid;   /* [H*W]   match flags (required) */
+    const float   *Qf;      /* [H*W]   frame confidence Q^f_f (required) */
+    const float   *Qk;      /* [H*W]   keyframe confidence Q^k_k (required) */
+} m3s_track_problem;
+
+/* Fills *params with q_min 1.5, sigma_ray 0.003, sigma_dist 0.1, Huber 1.345, 10 iterations.  NULL is ignored. */
+void m3s_default_track_params(m3s_track_params *params);
+
+/* Workspace bytes m3s_track_pose needs for an H x W keyframe (0 on invalid shapes). */
+size_t m3s_track_workspace_bytes(int32_t H, int32_t W);
+
+/*
+ * m3s_track_pose -- `iters` Gauss-Newton iterations from the pose in T.
+ *   T     DEVICE float[12], row-major 3x4 [sR | t]: the initial pose on entry,
+ *         the refined pose when the stream reaches the end of the call.
+ *   info  DEVICE float[4] or NULL: {robust cost at the final pose, number of
+ *         matches used there, number of iterations whose system was solved,
+ *         norm of the last applied step}.
+ *   ws    256-byte aligned DEVICE memory of >= m3s_track_workspace_bytes();
+ *         calls that share a workspace must not overlap.
+ * Matches with idx outside [0, H*W), non-finite or zero points are skipped.
+ * One launch per iteration plus one, no host synchronisation: the call can be
+ * captured into a hipGraph.
+ */
+m3s_status m3s_track_pose(const m3s_track_problem *prob, const m3s_track_params *params, float *T, float *info,
+                          void *ws, size_t ws_bytes, void *stream);
+
+/*
+ * Canonical pointmap fusion (Sec. 3.3, Eq. 8): after the pose solve, every
+ * keyframe pixel n takes the running confidence-weighted average
+ *   Xc[n] <- (Cc[n] Xc[n] + C[n] (T X[n])) / (Cc[n] + C[n]),   Cc[n] <- Cc[n] + C[n]
+ * of its canonical point and the frame's prediction of it moved into the
+ * keyframe by T = T_kf.  A pixel whose summed confidence is not positive
+ * keeps its point.  fp32; Cc is the fp32 sum exactly rounded.
+ */
+typedef struct {
+    int32_t H, W;
+    float       *Xc;        /* [H*W*3] canonical pointmap X~^k_k, updated in place (required) */
+    float       *Cc;        /* [H*W]   its summed confidence C~^k_k, updated in place (required) */
+    const float *X;         /* [H*W*3] the frame's prediction X^k_f of the keyframe's points (required) */
+    const float *C;         /* [H*W]   its confidence C^k_f (required) */
+} m3s_fuse_problem;
+
+/*
+ * m3s_fuse_pointmap -- Eq. 8 over every pixel.  T is a DEVICE float[12]
+ * (row-major 3x4 [sR | t]), read when the stream reaches the call, so it may
+ * be the T that m3s_track_pose just wrote on the same stream.  Arrays must be
+ * 4-byte aligned; 16-byte aligned arrays take the vectorised path.  No
+ * workspace.
+ */
+m3s_status m3s_fuse_pointmap(const m3s_fuse_problem *prob, const float *T, void *stream);
+
 /* Flags of m3s_match_batched. */
 #define M3S_BATCH_GRAPH    0x1u  /* capture the launch sequence in a hipGraph and replay it */
 #define M3S_BATCH_AUTOTUNE 0x2u  /* time candidate launch shapes once per shape signature */
@@ -208,7 +295,8 @@ void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
  * hipEvents around every kernel it launches eagerly (and around each hipGraph
  * launch, as "batched_graph").  m3s_timing_read synchronises on the recorded
  * events and returns, for the kernel `name` ("prep", "fwd", "fill", "bwd",
- * "batched_counter", "batched_prep", "batched_fwd", "batched_graph"), the
+ * "batched_counter", "batched_prep", "batched_fwd", "batched_graph", and
+ * "track" for all launches of one m3s_track_pose call together, "fuse"), the
  * summed duration in milliseconds and the number of launches since the last
  * reset.  Meant for benchmarks: the events cost a little time per launch.
  */

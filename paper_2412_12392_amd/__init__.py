@@ -4,6 +4,6 @@ The matcher runs in libm3s.so: hand-written HIP kernels for gfx950 behind the C
 ABI of include/m3s.h.  This package is its thin Python binding over torch device
 tensors.  Build the library with ``python -m paper_2412_12392_amd.build``.
 """
-from .binding import (EdgeInput, MatchFunction, MatchResult, last_batched_config, make_edges, match,  # noqa: F401
-                    match_backward, match_batched, match_stats, params)
+from .binding import (EdgeInput, MatchFunction, MatchResult, fuse_pointmap, last_batched_config,  # noqa: F401
+                    make_edges, match, match_backward, match_batched, match_stats, params, track_params, track_pose)
 from ._lib import M3SError, load as load_library  # noqa: F401

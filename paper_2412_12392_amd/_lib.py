@@ -39,6 +39,22 @@ class Edge(ctypes.Structure):
                 ("refine_radius", ctypes.c_int32)]
 
 
+class TrackParams(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("q_min", ctypes.c_float), ("sigma_ray", ctypes.c_float),
+                ("sigma_dist", ctypes.c_float), ("huber", ctypes.c_float)]
+
+
+class TrackProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("Xk", ctypes.c_void_p), ("Xf", ctypes.c_void_p),
+                ("idx", ctypes.c_void_p), ("valid", ctypes.c_void_p), ("Qf", ctypes.c_void_p),
+                ("Qk", ctypes.c_void_p)]
+
+
+class FuseProblem(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("Xc", ctypes.c_void_p), ("Cc", ctypes.c_void_p),
+                ("X", ctypes.c_void_p), ("C", ctypes.c_void_p)]
+
+
 class M3SError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         self.status = status
@@ -50,7 +66,8 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_batched_workspace_bytes", "m3s_match_batched", "m3s_batched_last_config",
            "m3s_clear_caches", "m3s_status_string", "m3s_last_error", "m3s_version",
            "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
-           "m3s_match_stats"]
+           "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
+           "m3s_fuse_pointmap"]
 
 _lib = None
 
@@ -97,6 +114,15 @@ def load(path: str = LIB_PATH):
     lib.m3s_stats_workspace_bytes.restype = sz
     lib.m3s_match_stats.argtypes = [PO, i32, i32, vp, vp, sz, vp]
     lib.m3s_match_stats.restype = ctypes.c_int
+    TP, TPr = ctypes.POINTER(TrackParams), ctypes.POINTER(TrackProblem)
+    lib.m3s_default_track_params.argtypes = [TP]
+    lib.m3s_default_track_params.restype = None
+    lib.m3s_track_workspace_bytes.argtypes = [i32, i32]
+    lib.m3s_track_workspace_bytes.restype = sz
+    lib.m3s_track_pose.argtypes = [TPr, TP, vp, vp, vp, sz, vp]
+    lib.m3s_track_pose.restype = ctypes.c_int
+    lib.m3s_fuse_pointmap.argtypes = [ctypes.POINTER(FuseProblem), vp, vp]
+    lib.m3s_fuse_pointmap.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -111,6 +137,17 @@ def default_params(lib=None, **overrides) -> Params:
     lib = lib or load()
     p = Params()
     lib.m3s_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown parameter %s" % k)
+        setattr(p, k, v)
+    return p
+
+
+def default_track_params(lib=None, **overrides) -> TrackParams:
+    lib = lib or load()
+    p = TrackParams()
+    lib.m3s_default_track_params(ctypes.byref(p))
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise TypeError("unknown parameter %s" % k)

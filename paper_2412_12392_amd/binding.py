@@ -9,6 +9,8 @@ or a CPU tensor raises.
     gXii, gXji = match_backward(Xii, Xji, res.p, res.valid, grad_p, grad_xhat)
     outs = match_batched([EdgeInput(...), ...], graph=True)
     p, xhat, idx, valid, theta = MatchFunction.apply(Xii, Xji, Dii, Dji, Qii, Qji, None, params)
+    T, info = track_pose(Xk, Xf, idx, valid, Qf, Qk, T)   # Sec. 3.3, T updated in place
+    fuse_pointmap(Xc, Cc, X, C, T)                           # Eq. 8, in place
 """
 from __future__ import annotations
 
@@ -180,6 +182,43 @@ def match_stats(res: MatchResult, stream=None) -> torch.Tensor:
                              _stream(stream))
     _lib.check(lib, "m3s_match_stats", st)
     return counts
+
+
+def track_params(**overrides) -> _lib.TrackParams:
+    """Tracking parameters: library defaults (10 iterations, q_min 1.5, sigma_ray 0.003,
+    sigma_dist 0.1, Huber 1.345) with keyword overrides."""
+    return _lib.default_track_params(None, **overrides)
+
+
+def track_pose(Xk, Xf, idx, valid, Qf, Qk, T, prm: Optional[_lib.TrackParams] = None, stream=None):
+    """m3s_track_pose (Sec. 3.3): refines the Sim(3) pose T (device float32 (3, 4), updated in
+    place) from the matches idx/valid of the keyframe's pixels.  Returns (T, info) with info the
+    device float32 tensor [cost, matches used, iterations solved, last step norm]."""
+    lib = _lib.load()
+    H, W = Xk.shape[:2]
+    prob = _lib.TrackProblem(H, W, _ptr(Xk, shape=(H, W, 3)), _ptr(Xf, shape=(H, W, 3)),
+                             _ptr(idx, torch.int32, shape=(H, W)), _ptr(valid, torch.uint8, shape=(H, W)),
+                             _ptr(Qf, shape=(H, W)), _ptr(Qk, shape=(H, W)))
+    prm = prm if prm is not None else track_params()
+    info = torch.empty(4, dtype=torch.float32, device=Xk.device)
+    nbytes = lib.m3s_track_workspace_bytes(H, W)
+    ws = _workspace(nbytes, Xk.device)
+    st = lib.m3s_track_pose(ctypes.byref(prob), ctypes.byref(prm), _ptr(T, shape=(3, 4)), _ptr(info), ws.data_ptr(),
+                            ws.numel(), _stream(stream))
+    _lib.check(lib, "m3s_track_pose", st)
+    return T, info
+
+
+def fuse_pointmap(Xc, Cc, X, C, T, stream=None):
+    """m3s_fuse_pointmap (Sec. 3.3, Eq. 8): updates the canonical pointmap Xc (H, W, 3) and its
+    confidence Cc (H, W) in place from the frame's prediction X, C and the device pose T (3, 4)."""
+    lib = _lib.load()
+    H, W = Xc.shape[:2]
+    prob = _lib.FuseProblem(H, W, _ptr(Xc, shape=(H, W, 3)), _ptr(Cc, shape=(H, W)), _ptr(X, shape=(H, W, 3)),
+                            _ptr(C, shape=(H, W)))
+    st = lib.m3s_fuse_pointmap(ctypes.byref(prob), _ptr(T, shape=(3, 4)), _stream(stream))
+    _lib.check(lib, "m3s_fuse_pointmap", st)
+    return Xc, Cc
 
 
 def last_batched_config():

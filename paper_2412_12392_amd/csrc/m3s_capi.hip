@@ -435,6 +435,70 @@ m3s_status m3s_match_stats(const m3s_outputs* fwd, int32_t H, int32_t W, int32_t
     return M3S_OK;
 }
 
+void m3s_default_track_params(m3s_track_params* P) {
+    if (!P) return;
+    P->iters = 10;
+    P->q_min = 1.5f;
+    P->sigma_ray = 0.003f;
+    P->sigma_dist = 0.1f;
+    P->huber = 1.345f;
+}
+
+size_t m3s_track_workspace_bytes(int32_t H, int32_t W) {
+    if (H < 2 || W < 2 || (int64_t)H * W > M3S_MAX_PIXELS) return 0;
+    return align_up(m3s::track_workspace_bytes(H * W));
+}
+
+m3s_status m3s_track_pose(const m3s_track_problem* prob, const m3s_track_params* params, float* T, float* info,
+                          void* ws, size_t ws_bytes, void* stream) {
+    m3s_track_params defaults;
+    m3s_default_track_params(&defaults);
+    const m3s_track_params* P = params ? params : &defaults;
+    if (!prob) return fail(M3S_ERR_NULL, "problem is NULL");
+    m3s_status s = check_shape(prob->H, prob->W);
+    if (s != M3S_OK) return s;
+    if (!prob->Xk || !prob->Xf || !prob->idx || !prob->valid || !prob->Qf || !prob->Qk)
+        return fail(M3S_ERR_NULL, "Xk, Xf, idx, valid, Qf and Qk are required");
+    if (!T) return fail(M3S_ERR_NULL, "T is required");
+    if (!aligned(prob->Xk, 4) || !aligned(prob->Xf, 4) || !aligned(prob->idx, 4) || !aligned(prob->Qf, 4) ||
+        !aligned(prob->Qk, 4) || !aligned(T, 4) || (info && !aligned(info, 4)))
+        return fail(M3S_ERR_PARAM, "arrays must be 4-byte aligned");
+    if (P->iters < 0 || P->iters > M3S_MAX_ITER) return fail(M3S_ERR_PARAM, "iters %d outside [0, %d]", P->iters, M3S_MAX_ITER);
+    if (!std::isfinite(P->q_min)) return fail(M3S_ERR_PARAM, "q_min must be finite");
+    if (std::isnan(P->sigma_ray) || !(P->sigma_ray > 0.f)) return fail(M3S_ERR_PARAM, "sigma_ray must be > 0");
+    if (std::isnan(P->sigma_dist) || !(P->sigma_dist > 0.f)) return fail(M3S_ERR_PARAM, "sigma_dist must be > 0");
+    if (std::isnan(P->huber) || !(P->huber > 0.f)) return fail(M3S_ERR_PARAM, "huber must be > 0");
+    const size_t need = m3s_track_workspace_bytes(prob->H, prob->W);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need, ws_bytes);
+    int dev;
+    DeviceInfo info_dev;
+    if ((s = current_device(&dev, &info_dev)) != M3S_OK) return s;
+    hipError_t e = m3s::launch_track(prob->H * prob->W, prob->Xk, prob->Xf, prob->idx, prob->valid, prob->Qf, prob->Qk,
+                                     P->q_min, P->sigma_ray, P->sigma_dist, P->huber, P->iters, T, info, ws,
+                                     reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "tracking launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+m3s_status m3s_fuse_pointmap(const m3s_fuse_problem* prob, const float* T, void* stream) {
+    if (!prob) return fail(M3S_ERR_NULL, "problem is NULL");
+    m3s_status s = check_shape(prob->H, prob->W);
+    if (s != M3S_OK) return s;
+    if (!prob->Xc || !prob->Cc || !prob->X || !prob->C || !T) return fail(M3S_ERR_NULL, "Xc, Cc, X, C and T are required");
+    if (!aligned(prob->Xc, 4) || !aligned(prob->Cc, 4) || !aligned(prob->X, 4) || !aligned(prob->C, 4) || !aligned(T, 4))
+        return fail(M3S_ERR_PARAM, "arrays must be 4-byte aligned");
+    int dev;
+    DeviceInfo info_dev;
+    if ((s = current_device(&dev, &info_dev)) != M3S_OK) return s;
+    hipError_t e = m3s::launch_fuse(prob->H * prob->W, T, prob->Xc, prob->Cc, prob->X, prob->C,
+                                    reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "fusion launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
 size_t m3s_batched_workspace_bytes(const m3s_edge* edges, int32_t n_edges, const m3s_params* common) {
     m3s_params defaults;
     m3s_default_params(&defaults);

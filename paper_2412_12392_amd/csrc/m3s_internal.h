@@ -33,4 +33,14 @@ hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, 
 hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
                       const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s);
 
+// Tracking pose solve (m3s_track.hip): workgroups of one iteration launch,
+// workspace bytes, and the launch sequence (init + iters + 1 launches).
+int track_blocks(int N);
+size_t track_workspace_bytes(int N);
+hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* idx, const uint8_t* valid,
+                        const float* Qf, const float* Qk, float q_min, float sigma_ray, float sigma_dist, float huber,
+                        int iters, float* T, float* info, void* ws, hipStream_t s);
+// Canonical pointmap fusion (Eq. 8) with the pose T read from device memory.
+hipError_t launch_fuse(int N, const float* T, float* Xc, float* Cc, const float* X, const float* C, hipStream_t s);
+
 }  // namespace m3s

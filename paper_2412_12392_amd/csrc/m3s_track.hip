@@ -1,0 +1,422 @@
+// gfx950 kernels of the tracking pose solve and of the canonical pointmap
+// fusion that follows it (MASt3R-SLAM, Sec. 3.3).
+//
+// Gauss-Newton in an iteratively reweighted least-squares loop (Eq.
+// gauss_newton) for the Sim(3) pose T_kf that maps frame points X^f_f into the
+// keyframe, over the matches of the keyframe's pixels found by the matcher.
+// One launch per iteration; in it
+//
+//   every lane takes matches n (grid-stride): x = T Xf[m] with m = idx[n];
+//     ray residual psi(x) - psi(Xk[n]) (Eq. track_ray) and distance residual
+//     |x| - |Xk[n]| (the small-weight distance term); Jacobians w.r.t. a left
+//     perturbation (Supp. A: [N(x), -[x]_x / |x|, 0] and [x^T / |x|, 0, |x|]);
+//     weights q / sigma^2 (match confidence q = sqrt(Qf[m] Qk[n]) gated at
+//     q_min, Sec. 3.3) times the Huber weight of the whitened block norm;
+//   every block writes its partial sums of J^T W J (upper triangle), J^T W r,
+//     robust cost and count;
+//   the block that finishes last (agent-scope ticket counter) sums the
+//     partials in fp64 in a fixed order, solves the 7x7 system by Cholesky
+//     and applies T <- Exp(tau) o T (Eq. 1, left plus on Sim(3)) in fp64.
+//
+// The pose lives in the workspace in fp64 between launches; the last launch
+// evaluates the cost at the final pose and writes the fp32 pose and the
+// statistics.  Tangent order (v, omega, sigma), as in the point Jacobian
+// [I, -[x]_x, x].  Launches are stream-ordered with no host synchronisation,
+// so the whole solve can be captured into a graph.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "m3s_internal.h"
+
+namespace m3s {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kVals = 28 + 7 + 2;   // H upper triangle, g, cost, count
+constexpr int kStride = 40;         // floats per block partial
+constexpr int kChunks = 6;          // fp64 reduction: kStride * kChunks <= kThreads
+constexpr int kMaxBlocks = 1024;
+
+// Workspace layout (bytes): pose, statistics, counters, then the partials.
+constexpr size_t kOffT = 0;         // double[12]
+constexpr size_t kOffStat = 96;     // double[2]: last step norm, reserved
+constexpr size_t kOffCnt = 128;     // int32[2]: ticket counter, solved iterations
+constexpr size_t kOffPart = 256;    // float[nblocks * kStride]
+
+struct TrackArgs {
+    int N;
+    const float* Xk;
+    const float* Xf;
+    const int32_t* idx;
+    const uint8_t* valid;
+    const float* Qf;
+    const float* Qk;
+    double q_min;
+    float w_ray, w_dist;    // 1 / sigma^2 (0 drops the residual)
+    float is_ray, is_dist;  // 1 / sigma
+    float huber;
+    double* T64;
+    double* stat;
+    int32_t* counter;
+    int32_t* solved;
+    float* partials;
+    float* T_out;
+    float* info;
+};
+
+__device__ __forceinline__ float huber_weight(float a, float width) { return a <= width ? 1.f : width / a; }
+__device__ __forceinline__ float huber_cost(float a, float width) {
+    return a <= width ? 0.5f * a * a : width * (a - 0.5f * width);
+}
+
+__global__ void __launch_bounds__(64) track_init_kernel(const float* __restrict__ T_in, double* __restrict__ T64,
+                                                        int32_t* __restrict__ cnt, double* __restrict__ stat) {
+    const int i = threadIdx.x;
+    if (i < 12) T64[i] = (double)T_in[i];
+    if (i < 2) { cnt[i] = 0; stat[i] = 0.0; }
+}
+
+// Exp of sim(3): tau = (v, omega, sigma) -> [e^sigma R | V v], R by Rodrigues
+// and V = a0 I + a1 [omega]_x + a2 [omega]_x^2 with a0 = int e^{sigma s},
+// a1 = int e^{sigma s} sin(theta s) / theta and
+// a2 = int e^{sigma s} (1 - cos(theta s)) / theta^2 over s in [0, 1]; their
+// series near theta = 0 and sigma = 0.
+__device__ void sim3_exp(const double* tau, double* E) {
+    const double sg = tau[6];
+    const double w0 = tau[3], w1 = tau[4], w2 = tau[5];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    const double S[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+    double S2[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S2[i][j] = S[i][0] * S[0][j] + S[i][1] * S[1][j] + S[i][2] * S[2][j];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const bool small = th < 1e-4;
+    const double ka = small ? 1.0 - th2 / 6.0 : sn / th;
+    const double kb = small ? 0.5 - th2 / 24.0 : (1.0 - cs) / th2;
+    const double es = exp(sg);
+    const double a0 = sg == 0.0 ? 1.0 : expm1(sg) / sg;
+    double a1, a2;
+    if (small) {
+        const double s2 = sg * sg;
+        if (fabs(sg) < 1e-3) {
+            a1 = 0.5 + sg / 3.0 + s2 / 8.0 + s2 * sg / 30.0;
+            a2 = 1.0 / 6.0 + sg / 8.0 + s2 / 20.0 + s2 * sg / 72.0;
+        } else {
+            a1 = (es * (sg - 1.0) + 1.0) / s2;
+            a2 = (es * (s2 - 2.0 * sg + 2.0) - 2.0) / (2.0 * s2 * sg);
+        }
+    } else {
+        const double den = sg * sg + th2;
+        const double is = (es * (sg * sn - th * cs) + th) / den;
+        const double ic = (es * (sg * cs + th * sn) - sg) / den;
+        a1 = is / th;
+        a2 = (a0 - ic) / th2;
+    }
+    for (int i = 0; i < 3; ++i) {
+        double tv = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double I = i == j ? 1.0 : 0.0;
+            E[4 * i + j] = es * (I + ka * S[i][j] + kb * S2[i][j]);
+            tv += (I * a0 + a1 * S[i][j] + a2 * S2[i][j]) * tau[j];
+        }
+        E[4 * i + 3] = tv;
+    }
+}
+
+// Entry (a, b), a <= b, of the packed upper triangle (rows of 7, 6, ..., 1).
+__device__ __forceinline__ int upper_index(int a, int b) { return a * 7 - a * (a - 1) / 2 + (b - a); }
+
+// Solve H tau = -g (7x7 SPD) and apply T <- Exp(tau) o T.  Returns false
+// (pose unchanged) when H is not positive definite.
+__device__ bool solve_and_update(const double* sum, double* T, double* step_norm) {
+    double L[7][7];
+    for (int r = 0; r < 7; ++r)
+        for (int c = 0; c < 7; ++c) L[r][c] = 0.0;
+    for (int r = 0; r < 7; ++r) {
+        for (int c = 0; c <= r; ++c) {
+            double s = sum[upper_index(c, r)];
+            for (int q = 0; q < c; ++q) s -= L[r][q] * L[c][q];
+            if (r == c) {
+                if (!(s > 0.0) || !isfinite(s)) return false;
+                L[r][r] = sqrt(s);
+            } else {
+                L[r][c] = s / L[c][c];
+            }
+        }
+    }
+    double y[7], tau[7];
+    for (int r = 0; r < 7; ++r) {
+        double s = -sum[28 + r];
+        for (int q = 0; q < r; ++q) s -= L[r][q] * y[q];
+        y[r] = s / L[r][r];
+    }
+    for (int r = 6; r >= 0; --r) {
+        double s = y[r];
+        for (int q = r + 1; q < 7; ++q) s -= L[q][r] * tau[q];
+        tau[r] = s / L[r][r];
+    }
+    double E[12], Tn[12];
+    sim3_exp(tau, E);
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 4; ++c)
+            Tn[4 * r + c] = E[4 * r] * T[c] + E[4 * r + 1] * T[4 + c] + E[4 * r + 2] * T[8 + c] +
+                            (c == 3 ? E[4 * r + 3] : 0.0);
+    for (int j = 0; j < 12; ++j) T[j] = Tn[j];
+    double tn = 0.0;
+    for (int j = 0; j < 7; ++j) tn += tau[j] * tau[j];
+    *step_norm = sqrt(tn);
+    return true;
+}
+
+// mode 0: accumulate and update the pose; mode 1: accumulate at the final
+// pose and write the outputs.
+__global__ void __launch_bounds__(kThreads) track_iter_kernel(TrackArgs A, int mode) {
+    __shared__ float red[kThreads / 64][kVals];
+    __shared__ double dsum[kChunks][kStride];
+    __shared__ int last;
+
+    float T[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) T[i] = (float)A.T64[i];
+    float acc[kVals];
+#pragma unroll
+    for (int i = 0; i < kVals; ++i) acc[i] = 0.f;
+
+    for (int n = blockIdx.x * kThreads + threadIdx.x; n < A.N; n += gridDim.x * kThreads) {
+        if (!A.valid[n]) continue;
+        const int m = A.idx[n];
+        if (m < 0 || m >= A.N) continue;
+        // The confidence gate decides in fp64, from the exact product of the
+        // two fp32 confidences.
+        const double q64 = sqrt((double)A.Qf[m] * (double)A.Qk[n]);
+        if (!(q64 > A.q_min)) continue;
+        const float q = (float)q64;
+        const float X0 = A.Xf[3 * m], X1 = A.Xf[3 * m + 1], X2 = A.Xf[3 * m + 2];
+        const float Y0 = A.Xk[3 * n], Y1 = A.Xk[3 * n + 1], Y2 = A.Xk[3 * n + 2];
+        const float x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[3];
+        const float x1 = T[4] * X0 + T[5] * X1 + T[6] * X2 + T[7];
+        const float x2 = T[8] * X0 + T[9] * X1 + T[10] * X2 + T[11];
+        const float d = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
+        const float dy = sqrtf(Y0 * Y0 + Y1 * Y1 + Y2 * Y2);
+        if (!(d > 0.f) || !(dy > 0.f) || !isfinite(d) || !isfinite(dy)) continue;
+        const float id = 1.f / d, idy = 1.f / dy;
+        const float u[3] = {x0 * id, x1 * id, x2 * id};
+        const float x[3] = {x0, x1, x2};
+        const float res[4] = {u[0] - Y0 * idy, u[1] - Y1 * idy, u[2] - Y2 * idy, d - dy};
+        float J[4][7];
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) J[i][j] = ((i == j ? 1.f : 0.f) - u[i] * u[j]) * id;
+            J[i][6] = 0.f;
+        }
+        // -[x]_x / d
+        J[0][3] = 0.f;         J[0][4] = x[2] * id;   J[0][5] = -x[1] * id;
+        J[1][3] = -x[2] * id;  J[1][4] = 0.f;         J[1][5] = x[0] * id;
+        J[2][3] = x[1] * id;   J[2][4] = -x[0] * id;  J[2][5] = 0.f;
+        J[3][0] = u[0]; J[3][1] = u[1]; J[3][2] = u[2];
+        J[3][3] = 0.f;  J[3][4] = 0.f;  J[3][5] = 0.f;  J[3][6] = d;
+        const float sq = sqrtf(q);
+        const float a_ray = sqrtf(res[0] * res[0] + res[1] * res[1] + res[2] * res[2]) * sq * A.is_ray;
+        const float a_dist = fabsf(res[3]) * sq * A.is_dist;
+        const float wr = q * A.w_ray * huber_weight(a_ray, A.huber);
+        const float wd = q * A.w_dist * huber_weight(a_dist, A.huber);
+        const float w[4] = {wr, wr, wr, wd};
+        int k = 0;
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+#pragma unroll
+            for (int b = a; b < 7; ++b) {
+                float h = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) h = fmaf(J[r][a] * w[r], J[r][b], h);
+                acc[k++] += h;
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < 7; ++a) {
+            float g = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) g = fmaf(J[r][a] * w[r], res[r], g);
+            acc[28 + a] += g;
+        }
+        acc[35] += huber_cost(a_ray, A.huber) + huber_cost(a_dist, A.huber);
+        acc[36] += 1.f;
+    }
+
+    // Block partial: wave butterflies, then the four waves through LDS.
+#pragma unroll
+    for (int i = 0; i < kVals; ++i) {
+        float v = acc[i];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[i] = v;
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int i = 0; i < kVals; ++i) red[threadIdx.x >> 6][i] = acc[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < kVals) {
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
+        A.partials[(size_t)blockIdx.x * kStride + threadIdx.x] = v;
+    }
+
+    // Ticket: the last block to finish owns the reduction and the solve.
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int t = __hip_atomic_fetch_add(A.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = t == (int)gridDim.x - 1;
+    }
+    __syncthreads();
+    if (!last) return;
+    __threadfence();
+
+    // Fixed-order fp64 sum of the block partials: chunk c takes blocks
+    // c, c + kChunks, ...; the chunks are then added in order.
+    const int vi = threadIdx.x % kStride, ch = threadIdx.x / kStride;
+    if (ch < kChunks) {
+        double s = 0.0;
+        if (vi < kVals) {
+            for (int b = ch; b < (int)gridDim.x; b += kChunks)
+                s += (double)__builtin_nontemporal_load(&A.partials[(size_t)b * kStride + vi]);
+        }
+        dsum[ch][vi] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double sum[kVals];
+    for (int i = 0; i < kVals; ++i) {
+        double s = 0.0;
+        for (int c = 0; c < kChunks; ++c) s += dsum[c][i];
+        sum[i] = s;
+    }
+    A.counter[0] = 0;  // ready for the next launch on the stream
+    if (mode == 0) {
+        double step;
+        if (solve_and_update(sum, A.T64, &step)) {
+            A.solved[0] += 1;
+            A.stat[0] = step;
+        }
+    } else {
+        for (int j = 0; j < 12; ++j) A.T_out[j] = (float)A.T64[j];
+        if (A.info) {
+            A.info[0] = (float)sum[35];
+            A.info[1] = (float)sum[36];
+            A.info[2] = (float)A.solved[0];
+            A.info[3] = (float)A.stat[0];
+        }
+    }
+}
+
+// Canonical pointmap update (Sec. 3.3, Eq. 8), per keyframe pixel n:
+//   Xc[n] <- (Cc[n] Xc[n] + C[n] (T X[n])) / (Cc[n] + C[n]),  Cc[n] <- Cc[n] + C[n];
+// a pixel whose summed confidence is not positive keeps its point.  VEC
+// pixels per lane: with VEC = 4 every array is read and written as float4
+// (3 per point quad, 1 per confidence quad); VEC = 1 handles any alignment
+// and the tail.
+__device__ __forceinline__ void fuse_one(const float* T, float& x0, float& x1, float& x2, float& cc, float X0, float X1,
+                                         float X2, float c) {
+    const float t0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[3];
+    const float t1 = T[4] * X0 + T[5] * X1 + T[6] * X2 + T[7];
+    const float t2 = T[8] * X0 + T[9] * X1 + T[10] * X2 + T[11];
+    const float cs = cc + c;
+    if (cs > 0.f) {
+        const float inv = 1.f / cs;
+        x0 = (cc * x0 + c * t0) * inv;
+        x1 = (cc * x1 + c * t1) * inv;
+        x2 = (cc * x2 + c * t2) * inv;
+    }
+    cc = cs;
+}
+
+template <int VEC>
+__global__ void __launch_bounds__(256) fuse_kernel(int N, int first, const float* __restrict__ Tg, float* __restrict__ Xc,
+                                                   float* __restrict__ Cc, const float* __restrict__ X,
+                                                   const float* __restrict__ C) {
+    float T[12];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) T[i] = Tg[i];
+    const long g = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (VEC == 4) {
+        const long n0 = first + 4 * g;
+        if (n0 + 4 > N) return;
+        float4* xc4 = reinterpret_cast<float4*>(Xc + 3 * n0);
+        const float4* x4 = reinterpret_cast<const float4*>(X + 3 * n0);
+        float4 a = xc4[0], b = xc4[1], d = xc4[2];
+        const float4 p = x4[0], q = x4[1], r = x4[2];
+        float4 cc = *reinterpret_cast<const float4*>(Cc + n0);
+        const float4 c = *reinterpret_cast<const float4*>(C + n0);
+        fuse_one(T, a.x, a.y, a.z, cc.x, p.x, p.y, p.z, c.x);
+        fuse_one(T, a.w, b.x, b.y, cc.y, p.w, q.x, q.y, c.y);
+        fuse_one(T, b.z, b.w, d.x, cc.z, q.z, q.w, r.x, c.z);
+        fuse_one(T, d.y, d.z, d.w, cc.w, r.y, r.z, r.w, c.w);
+        xc4[0] = a; xc4[1] = b; xc4[2] = d;
+        *reinterpret_cast<float4*>(Cc + n0) = cc;
+    } else {
+        const long n = first + g;
+        if (n >= N) return;
+        float x0 = Xc[3 * n], x1 = Xc[3 * n + 1], x2 = Xc[3 * n + 2], cc = Cc[n];
+        fuse_one(T, x0, x1, x2, cc, X[3 * n], X[3 * n + 1], X[3 * n + 2], C[n]);
+        Xc[3 * n] = x0; Xc[3 * n + 1] = x1; Xc[3 * n + 2] = x2;
+        Cc[n] = cc;
+    }
+}
+
+}  // namespace
+
+int track_blocks(int N) {
+    const int nb = (N + kThreads * 4 - 1) / (kThreads * 4);
+    return nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb);
+}
+
+size_t track_workspace_bytes(int N) { return kOffPart + (size_t)track_blocks(N) * kStride * sizeof(float); }
+
+hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* idx, const uint8_t* valid,
+                        const float* Qf, const float* Qk, float q_min, float sigma_ray, float sigma_dist, float huber,
+                        int iters, float* T, float* info, void* ws, hipStream_t s) {
+    char* w = reinterpret_cast<char*>(ws);
+    TrackArgs A;
+    A.N = N;
+    A.Xk = Xk; A.Xf = Xf; A.idx = idx; A.valid = valid; A.Qf = Qf; A.Qk = Qk;
+    A.q_min = (double)q_min;
+    // An infinite sigma drops its residual from the system and the cost.
+    A.w_ray = isinf(sigma_ray) ? 0.f : 1.f / (sigma_ray * sigma_ray);
+    A.w_dist = isinf(sigma_dist) ? 0.f : 1.f / (sigma_dist * sigma_dist);
+    A.is_ray = isinf(sigma_ray) ? 0.f : 1.f / sigma_ray;
+    A.is_dist = isinf(sigma_dist) ? 0.f : 1.f / sigma_dist;
+    A.huber = huber;
+    A.T64 = reinterpret_cast<double*>(w + kOffT);
+    A.stat = reinterpret_cast<double*>(w + kOffStat);
+    A.counter = reinterpret_cast<int32_t*>(w + kOffCnt);
+    A.solved = A.counter + 1;
+    A.partials = reinterpret_cast<float*>(w + kOffPart);
+    A.T_out = T;
+    A.info = info;
+    const int nb = track_blocks(N);
+    timer_begin("track", s);
+    track_init_kernel<<<1, 64, 0, s>>>(T, A.T64, A.counter, A.stat);
+    for (int it = 0; it <= iters; ++it) track_iter_kernel<<<nb, kThreads, 0, s>>>(A, it < iters ? 0 : 1);
+    timer_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_fuse(int N, const float* T, float* Xc, float* Cc, const float* X, const float* C, hipStream_t s) {
+    auto al16 = [](const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; };
+    const bool vec = al16(Xc) && al16(Cc) && al16(X) && al16(C);
+    const int quads = vec ? N / 4 : 0;
+    const int tail = N - 4 * quads;
+    timer_begin("fuse", s);
+    if (quads > 0) fuse_kernel<4><<<(quads + 255) / 256, 256, 0, s>>>(N, 0, T, Xc, Cc, X, C);
+    if (tail > 0) fuse_kernel<1><<<(tail + 255) / 256, 256, 0, s>>>(N, 4 * quads, T, Xc, Cc, X, C);
+    timer_end(s);
+    return hipGetLastError();
+}
+
+}  // namespace m3s

@@ -193,3 +193,81 @@ def test_batched_validation(lib):
     edges[1].in_ = _pair(W=1)
     assert lib.m3s_match_batched(edges, 2, ctypes.byref(prm), 0, 0, 0, None) == 2
     assert b"edge 1" in lib.m3s_last_error()
+
+
+def test_track_struct_layout(tmp_path):
+    prog = tmp_path / "tlayout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "m3s.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(m3s_track_params), sizeof(m3s_track_problem),
+         offsetof(m3s_track_params, huber), offsetof(m3s_track_problem, Xk), offsetof(m3s_track_problem, Qk));
+  return 0;
+}''')
+    exe = tmp_path / "tlayout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(_lib.TrackParams), ctypes.sizeof(_lib.TrackProblem), _lib.TrackParams.huber.offset,
+                    _lib.TrackProblem.Xk.offset, _lib.TrackProblem.Qk.offset]
+
+
+def test_track_defaults_and_workspace(lib):
+    p = _lib.default_track_params(lib)
+    assert p.iters == 10 and abs(p.q_min - 1.5) < 1e-7 and abs(p.sigma_ray - 0.003) < 1e-9
+    assert abs(p.sigma_dist - 0.1) < 1e-8 and abs(p.huber - 1.345) < 1e-6
+    assert lib.m3s_track_workspace_bytes(384, 512) >= 256 + 192 * 37 * 4
+    assert lib.m3s_track_workspace_bytes(384, 512) % 256 == 0
+    assert lib.m3s_track_workspace_bytes(1, 512) == 0
+
+
+def _track_prob(H=4, W=4, **kw):
+    args = dict(Xk=_addr, Xf=_addr, idx=_addr, valid=_addr, Qf=_addr, Qk=_addr)
+    args.update(kw)
+    return _lib.TrackProblem(H, W, args["Xk"], args["Xf"], args["idx"], args["valid"], args["Qf"], args["Qk"])
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(prob=None), 1),
+    (dict(prob=dict(H=1)), 2),
+    (dict(prob=dict(W=70000, H=70000)), 2),
+    (dict(prob=dict(Xk=0)), 1),
+    (dict(prob=dict(valid=0)), 1),
+    (dict(prob=dict(Qk=0)), 1),
+    (dict(T=0), 1),
+    (dict(prob=dict(Xf=_addr + 2)), 3),
+    (dict(T=_addr + 1), 3),
+    (dict(prm=dict(iters=-1)), 3),
+    (dict(prm=dict(iters=1001)), 3),
+    (dict(prm=dict(q_min=float("nan"))), 3),
+    (dict(prm=dict(sigma_ray=0.0)), 3),
+    (dict(prm=dict(sigma_dist=float("nan"))), 3),
+    (dict(prm=dict(huber=-1.0)), 3),
+    (dict(ws=0), 4),
+    (dict(ws="misaligned"), 4),
+    (dict(ws="small"), 4),
+])
+def test_track_validation(lib, case, expect):
+    prob = None if case.get("prob", {}) is None else _track_prob(**case.get("prob", {}))
+    prm = _lib.default_track_params(lib, **case.get("prm", {}))
+    need = lib.m3s_track_workspace_bytes(4, 4)
+    base = (ctypes.addressof(_ws) + 255) // 256 * 256
+    ws, nbytes = {"none": (0, 0), 0: (0, 0), "misaligned": (base + 4, 1024), "small": (base, need - 1)}[
+        case.get("ws", "none")]
+    T = case.get("T", _addr)
+    st = lib.m3s_track_pose(ctypes.byref(prob) if prob is not None else None, ctypes.byref(prm), T, 0, ws, nbytes,
+                            None)
+    assert st == expect, (st, lib.m3s_last_error())
+    assert lib.m3s_last_error()
+
+
+def test_fuse_validation(lib):
+    ok = _lib.FuseProblem(4, 4, _addr, _addr, _addr, _addr)
+    assert lib.m3s_fuse_pointmap(None, _addr, None) == 1
+    assert lib.m3s_fuse_pointmap(ctypes.byref(ok), 0, None) == 1
+    assert lib.m3s_fuse_pointmap(ctypes.byref(_lib.FuseProblem(1, 4, _addr, _addr, _addr, _addr)), _addr, None) == 2
+    assert lib.m3s_fuse_pointmap(ctypes.byref(_lib.FuseProblem(4, 4, 0, _addr, _addr, _addr)), _addr, None) == 1
+    assert lib.m3s_fuse_pointmap(ctypes.byref(_lib.FuseProblem(4, 4, _addr, _addr, _addr + 2, _addr)), _addr, None) == 3
+    assert lib.m3s_fuse_pointmap(ctypes.byref(ok), _addr + 1, None) == 3
+    assert lib.m3s_last_error()
