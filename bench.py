@@ -51,6 +51,35 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_kernels_512x384_hbm_counters.md")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("m3s_kernels.hip", "m3s_device.h"):
+        with open(os.path.join(ROOT, "paper_2412_12392_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a plain copy), or None when
+    the summary is missing or was taken from different kernel sources."""
+    try:
+        text = open(COUNTERS_FILE).read()
+    except OSError:
+        return None
+    src = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("source_sha256_16:")]
+    if not src or src[0] != kernel_source_hash():
+        return None
+    for l in text.splitlines():
+        if l.startswith("traffic_bytes ") and l.split("=")[0].split(" ", 1)[1].strip() == kernel:
+            return int(l.split("=")[1])
+    return None
+
+
 class PreparedPair:
     """Device tensors and pre-built ctypes argument blocks of one pair."""
 
@@ -144,9 +173,12 @@ def main():
         kt[name] = tot.value / max(cnt.value, 1)
     alg_bytes = FWD_BYTES_PER_QUERY * N
     achieved = alg_bytes / (kt["fwd"] * 1e-3) / 1e9
+    traffic_bytes = measured_traffic("fwd_f16_kernel<16, 16>")
+    traffic = None if traffic_bytes is None else round(traffic_bytes / (kt["fwd"] * 1e-3) / 1e9, 1)
     roofline = {"bound": "hbm", "kernel": "fwd_f16_kernel<16,16>", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "algorithmic_bytes_per_launch": alg_bytes,
+                "traffic": traffic, "traffic_bytes_per_launch": traffic_bytes,
+                "algorithmic_bytes_per_launch": alg_bytes,
                 "kernel_avg_us": round(kt["fwd"] * 1e3, 2), "prep_avg_us": round(kt["prep"] * 1e3, 2),
                 "path_achieved_GBs": round(alg_bytes / ((kt["fwd"] + kt["prep"]) * 1e-3) / 1e9, 1)}
     log("kernel timing: fwd %.2f us, prep %.2f us" % (kt["fwd"] * 1e3, kt["prep"] * 1e3))
