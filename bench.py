@@ -18,6 +18,10 @@ Further legs, reported in the same JSON line:
                  K in 5..15 and r in 2..4 per edge, same comparison;
   roofline       the forward kernel's algorithmic bytes over its average
                  duration, timed live with hipEvents around each launch;
+  track_fuse     the tracking pose solve (10 Gauss-Newton iterations) and the
+                 canonical pointmap fusion of one 512x384 keyframe (Sec. 3.3);
+  backend        Gauss-Newton over 32 keyframe poses at 512x384 with 65 edges
+                 (Sec. 3.5), 10 iterations;
   cpu_baseline   the FP64 oracle on the host cores, on a bounded sample.
 """
 from __future__ import annotations
@@ -45,6 +49,12 @@ FWD_BYTES_PER_QUERY = 12 + 12 + 8 * 24 + 8 + 8 + 4 + 1 + 4
 # Backward per query: grad_p 8 + grad_xhat 12 + p 8 + valid 1 + X^j_i 12 + X^i_i 12
 # + dX^j_i 12 + dX^i_i 12 + its zero fill 12; forward with xhat adds 12.
 BWD_BYTES_PER_QUERY = 8 + 12 + 8 + 1 + 12 + 12 + 12 + 12 + 12
+# Pose-solve accumulation per match: moving point 12 + measured point 12 + idx 4
+# + valid 1 + two confidences 8.
+POSE_BYTES_PER_MATCH = 12 + 12 + 4 + 1 + 4 + 4
+# Fusion per pixel: read canonical point 12, confidence 4, frame point 12,
+# confidence 4; write point 12, confidence 4.
+FUSE_BYTES_PER_PIXEL = 12 + 4 + 12 + 4 + 12 + 4
 
 
 def log(*a):
@@ -106,6 +116,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--pool", type=int, default=8, help="distinct 512x384 pairs cycled through")
     ap.add_argument("--only-main", action="store_true", help="time only the single-pair forward leg")
+    ap.add_argument("--legs", default="fwd_bwd,batched,track_fuse,backend",
+                    help="comma-separated further legs to run after the single-pair forward")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -213,10 +225,18 @@ def main():
            "roofline": roofline}
 
     if not args.only_main:
-        out["fwd_bwd"] = fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
-        out["batched"] = batched_leg(m3s, lib, _lib, synth.batched_uniform, dev, args, "64 edges 512x384, K=10, r=3")
-        out["batched_uneven"] = batched_leg(m3s, lib, _lib, synth.batched_uneven, dev, args,
-                                            "96 edges: 40x 512x384, 32x 384x512, 24x 512x288; K 5..15, r 2..4")
+        legs = set(args.legs.split(","))
+        if "fwd_bwd" in legs:
+            out["fwd_bwd"] = fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
+        if "batched" in legs:
+            out["batched"] = batched_leg(m3s, lib, _lib, synth.batched_uniform, dev, args,
+                                         "64 edges 512x384, K=10, r=3")
+            out["batched_uneven"] = batched_leg(m3s, lib, _lib, synth.batched_uneven, dev, args,
+                                                "96 edges: 40x 512x384, 32x 384x512, 24x 512x288; K 5..15, r 2..4")
+        if "track_fuse" in legs:
+            out["track_fuse"] = track_fuse_leg(m3s, lib, dev, args)
+        if "backend" in legs:
+            out["backend"] = backend_leg(m3s, lib, dev, args)
     if args.copy_calibration:
         out["copy_calibration"] = copy_calibration(torch, dev)
     if not args.skip_cpu:
@@ -348,6 +368,115 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
     del ws, pw, outs, edges
     torch.cuda.empty_cache()
     return res
+
+
+def _timer(lib, name):
+    tot, cnt = ctypes.c_double(), ctypes.c_int64()
+    lib.m3s_timing_read(name.encode(), ctypes.byref(tot), ctypes.byref(cnt))
+    return tot.value / max(cnt.value, 1), cnt.value
+
+
+def track_fuse_leg(m3s, lib, dev, args):
+    """Tracking pose solve + fusion of one 512x384 keyframe (Sec. 3.3)."""
+    import torch
+    H, W = 384, 512
+    tp = synth.make_tracking(H, W, 5000, noise=1e-3, outlier_frac=0.05)
+    fp = synth.make_fusion(H, W, 5001)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    prob = (t(tp.Xk), t(tp.Xf), t(tp.idx.astype(np.int32)), t(tp.valid.astype(np.uint8)), t(tp.Qf), t(tp.Qk))
+    Xc, Cc, X, C = t(fp.Xc), t(fp.Cc), t(fp.X), t(fp.C)
+    I34 = torch.tensor(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), dtype=torch.float32, device=dev)
+    T = I34.clone()
+    prm = m3s.track_params()
+
+    def step():
+        T.copy_(I34)
+        m3s.track_pose(*prob, T, prm)
+        m3s.fuse_pointmap(Xc, Cc, X, C, T)
+
+    steps = max(5, args.steps // 5)
+    for _ in range(3):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    lib.m3s_timing_enable(0)
+    ac_ms, _ = _timer(lib, "track_accum")
+    so_ms, _ = _timer(lib, "track_solve")
+    fu_ms, _ = _timer(lib, "fuse")
+    n_match = int(tp.valid.sum())
+    iters = prm.iters + 1
+    out = {"workload": "512x384 keyframe: tracking pose solve (10 Gauss-Newton iterations + final cost) then "
+                       "pointmap fusion; noise 1e-3, 5% outliers",
+           "ms_per_frame": round(el * 1e3, 4),
+           "track_accum_avg_us": round(ac_ms * 1e3, 2), "track_solve_avg_us": round(so_ms * 1e3, 2),
+           "launch_pairs_per_frame": iters,
+           "match_evaluations_per_s": round(n_match * iters / el, 1),
+           "track_accum_algorithmic_GBs": round(POSE_BYTES_PER_MATCH * H * W / (ac_ms * 1e-3) / 1e9, 1),
+           "fuse_avg_us": round(fu_ms * 1e3, 2),
+           "fuse_algorithmic_GBs": round(FUSE_BYTES_PER_PIXEL * H * W / (fu_ms * 1e-3) / 1e9, 1),
+           "fuse_frac_of_hbm_peak": round(FUSE_BYTES_PER_PIXEL * H * W / (fu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log("track_fuse:", out)
+    return out
+
+
+def backend_leg(m3s, lib, dev, args):
+    """Backend Gauss-Newton over 32 keyframes at 512x384 with 65 edges (Sec. 3.5)."""
+    import torch
+    N, H, W = 32, 384, 512
+    t0 = time.time()
+    bp = synth.make_backend(N, H, W, 6000, loops=3, scramble=False, noise=1e-3, outlier_frac=0.05)
+    log("backend leg: %d keyframes, %d edges generated in %.1fs" % (N, len(bp.edges), time.time() - t0))
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    prob = (t(bp.Xc), t(bp.Q), t(bp.edges), t(bp.idx), t(bp.valid.astype(np.uint8)))
+    T0 = t(np.asarray(bp.T_init, np.float32))
+    T = T0.clone()
+    prm = m3s.backend_params()
+
+    def step():
+        T.copy_(T0)
+        m3s.backend_gn(*prob, T, prm)
+
+    steps = max(3, args.steps // 10)
+    for _ in range(2):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    lib.m3s_timing_enable(0)
+    acc_ms, _ = _timer(lib, "backend_accum")
+    edg_ms, _ = _timer(lib, "backend_edge")
+    sol_ms, _ = _timer(lib, "backend_solve")
+    E = len(bp.edges)
+    matches = E * H * W
+    alg = POSE_BYTES_PER_MATCH * matches
+    out = {"workload": "%d keyframes 512x384, %d edges (neighbours both ways + loop closures), 10 Gauss-Newton "
+                       "iterations, noise 1e-3, 5%% outliers" % (N, E),
+           "ms_per_solve": round(el * 1e3, 4),
+           "match_evaluations_per_s": round(matches * (prm.iters + 1) / el, 1),
+           "accum_avg_us": round(acc_ms * 1e3, 2), "edge_avg_us": round(edg_ms * 1e3, 2),
+           "solve_avg_us": round(sol_ms * 1e3, 2),
+           "accum_algorithmic_bytes": alg,
+           "accum_algorithmic_GBs": round(alg / (acc_ms * 1e-3) / 1e9, 1),
+           "accum_frac_of_hbm_peak": round(alg / (acc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log("backend:", out)
+    return out
 
 
 def copy_calibration(torch, dev):

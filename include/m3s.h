@@ -16,8 +16,9 @@
  * (Sec. 3.3) and 3D distance (Sec. 3.2, occlusion and outlier handling).
  * A backward pass gives the implicit adjoint of the converged match, a
  * batched entry point matches many edges of a keyframe graph in one launch,
- * and the tracking entry point solves a frame's Sim(3) pose from its matches
- * (Sec. 3.3).
+ * the tracking entry point solves a frame's Sim(3) pose from its matches and
+ * fuses its pointmap into the keyframe's (Sec. 3.3), and the backend entry
+ * point solves the keyframe poses over the whole graph (Sec. 3.5).
  *
  * Conventions shared by every entry point:
  *   - All array arguments are caller-owned DEVICE memory (HBM of the current
@@ -53,6 +54,8 @@ extern "C" {
 #define M3S_MAX_DESC 64       /* largest descriptor dimension D */
 #define M3S_MAX_PIXELS (1 << 26)  /* largest H * W of one frame (67,108,864 pixels) */
 #define M3S_MAX_LEVELS 4      /* largest number of coarse-to-fine refine levels */
+#define M3S_MAX_KEYFRAMES 128 /* largest number of keyframes of one backend solve */
+#define M3S_MAX_EDGES 65535   /* largest number of edges of one backend solve */
 
 typedef enum {
     M3S_OK = 0,
@@ -227,8 +230,8 @@ size_t m3s_track_workspace_bytes(int32_t H, int32_t W);
  *   ws    256-byte aligned DEVICE memory of >= m3s_track_workspace_bytes();
  *         calls that share a workspace must not overlap.
  * Matches with idx outside [0, H*W), non-finite or zero points are skipped.
- * One launch per iteration plus one, no host synchronisation: the call can be
- * captured into a hipGraph.
+ * Two launches per iteration plus three, no host synchronisation: the call can
+ * be captured into a hipGraph.
  */
 m3s_status m3s_track_pose(const m3s_track_problem *prob, const m3s_track_params *params, float *T, float *info,
                           void *ws, size_t ws_bytes, void *stream);
@@ -257,6 +260,69 @@ typedef struct {
  * workspace.
  */
 m3s_status m3s_fuse_pointmap(const m3s_fuse_problem *prob, const float *T, void *stream);
+
+/*
+ * Backend optimisation (Sec. 3.5).  N keyframes of one H x W resolution with
+ * world poses T_WC[k] (Sim(3), 3x4 [sR | t]) and canonical pointmaps; E edges
+ * (i, j), each with the matches of keyframe j's pixels into keyframe i
+ * (m3s_match_fwd with Xii = X~^i_i and Xji = T_ij X~^j_j, so idx[n] is a pixel
+ * of i).  Gauss-Newton on the global ray objective (Eq. backend_ray) plus the
+ * small-weight distance term, over every valid match with
+ * q = sqrt(Q[i][m] Q[j][n]) > q_min:
+ *   ray residual      psi(T_ij Xc[j][n]) - psi(Xc[i][m])   weight q / sigma_ray^2
+ *   distance residual |T_ij Xc[j][n]| - |Xc[i][m]|         weight q / sigma_dist^2
+ * with T_ij = T_WC[i]^-1 T_WC[j], Huber weights as in m3s_track_pose, and the
+ * world-pose Jacobians -J Ad(T_WC[i]^-1), J Ad(T_WC[i]^-1) (Supp. A).  Keyframe 0
+ * holds the gauge.  The reduced 7(N-1) system is solved by a dense Cholesky
+ * factorisation in fp64 (the same solution as the paper's sparse one) and every
+ * other pose takes T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  The loop ends after
+ * `iters` steps, once a step norm |tau| falls below step_tol (that step is
+ * applied), or when the system is not positive definite (no step applied).
+ * Residuals are evaluated in fp32 and summed per workgroup in fp32, per edge
+ * and across edges in fp64; the confidence gate is decided in fp64.
+ */
+typedef struct {
+    int32_t iters;          /* at most this many Gauss-Newton steps, in [0, M3S_MAX_ITER] */
+    float   q_min;          /* confidence gate, finite */
+    float   sigma_ray;      /* > 0; +inf drops the ray residual */
+    float   sigma_dist;     /* > 0; +inf drops the distance residual */
+    float   huber;          /* Huber width on the whitened norm, > 0; +inf = plain least squares */
+    double  step_tol;       /* >= 0: stop once |tau| < step_tol (0: run all iterations); steps do not
+                               fall below about 1e-7 (1 + |t|), the fp32 rounding of the relative poses */
+} m3s_backend_params;
+
+typedef struct {
+    int32_t N, H, W;        /* keyframes (2 .. M3S_MAX_KEYFRAMES) and their common resolution */
+    int32_t E;              /* edges, 1 .. M3S_MAX_EDGES */
+    const float   *Xc;      /* [N*H*W*3] canonical pointmaps, keyframe-major (required) */
+    const float   *Q;       /* [N*H*W]   per-keyframe confidences (required) */
+    const int32_t *edges;   /* [E*2]     DEVICE (i, j) per edge; edges outside [0, N) are skipped (required) */
+    const int32_t *idx;     /* [E*H*W]   per edge, the pixel of i matched to pixel n of j, or < 0 (required) */
+    const uint8_t *valid;   /* [E*H*W]   per edge, match flags (required) */
+} m3s_backend_problem;
+
+/* Fills *params with the tracking defaults, 10 iterations and step_tol 0.  NULL is ignored. */
+void m3s_default_backend_params(m3s_backend_params *params);
+
+/* Workspace bytes m3s_backend_gn needs (0 on invalid sizes). */
+size_t m3s_backend_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t E);
+
+/*
+ * m3s_backend_gn -- the Gauss-Newton loop above.
+ *   T_WC  DEVICE float[N*12], the initial world poses on entry and the solved
+ *         ones when the stream reaches the end of the call (keyframe 0 is
+ *         written back unchanged).
+ *   info  DEVICE float[4] or NULL: {robust cost at the final poses, matches
+ *         used there, steps applied, norm of the last applied step}.
+ *   ws    256-byte aligned DEVICE memory of >= m3s_backend_workspace_bytes();
+ *         calls that share a workspace must not overlap.
+ * 4 + 3 * iters launches on `stream`, no host synchronisation (a graph can
+ * capture the call); after the loop has ended, the remaining launches return
+ * at once.  The solve runs in one workgroup: a blocked Cholesky factorisation
+ * of the dense reduced system (32 x 32 tiles).
+ */
+m3s_status m3s_backend_gn(const m3s_backend_problem *prob, const m3s_backend_params *params, float *T_WC,
+                          float *info, void *ws, size_t ws_bytes, void *stream);
 
 /* Flags of m3s_match_batched. */
 #define M3S_BATCH_GRAPH    0x1u  /* capture the launch sequence in a hipGraph and replay it */
@@ -295,8 +361,9 @@ void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
  * hipEvents around every kernel it launches eagerly (and around each hipGraph
  * launch, as "batched_graph").  m3s_timing_read synchronises on the recorded
  * events and returns, for the kernel `name` ("prep", "fwd", "fill", "bwd",
- * "batched_counter", "batched_prep", "batched_fwd", "batched_graph", and
- * "track" for all launches of one m3s_track_pose call together, "fuse"), the
+ * "batched_counter", "batched_prep", "batched_fwd", "batched_graph",
+ * "track_accum", "track_solve", "fuse" (the vectorised launch),
+ * "backend_accum", "backend_edge", "backend_solve"), the
  * summed duration in milliseconds and the number of launches since the last
  * reset.  Meant for benchmarks: the events cost a little time per launch.
  */

@@ -1,9 +1,12 @@
-"""MI355X-native projective pointmap matching (MASt3R-SLAM, arXiv 2412.12392, Sec. 3.2).
+"""MI355X-native projective pointmap matching (MASt3R-SLAM, arXiv 2412.12392, Sec. 3.2)
+and the consumers of its matches: tracking pose solve and pointmap fusion (Sec. 3.3),
+backend pose-graph Gauss-Newton (Sec. 3.5).
 
-The matcher runs in libm3s.so: hand-written HIP kernels for gfx950 behind the C
+Everything runs in libm3s.so: hand-written HIP kernels for gfx950 behind the C
 ABI of include/m3s.h.  This package is its thin Python binding over torch device
 tensors.  Build the library with ``python -m paper_2412_12392_amd.build``.
 """
-from .binding import (EdgeInput, MatchFunction, MatchResult, fuse_pointmap, last_batched_config,  # noqa: F401
+from .binding import (EdgeInput, MatchFunction, MatchResult, backend_gn, backend_params,  # noqa: F401
+                    fuse_pointmap, last_batched_config,
                     make_edges, match, match_backward, match_batched, match_stats, params, track_params, track_pose)
 from ._lib import M3SError, load as load_library  # noqa: F401

@@ -55,6 +55,17 @@ class FuseProblem(ctypes.Structure):
                 ("X", ctypes.c_void_p), ("C", ctypes.c_void_p)]
 
 
+class BackendParams(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("q_min", ctypes.c_float), ("sigma_ray", ctypes.c_float),
+                ("sigma_dist", ctypes.c_float), ("huber", ctypes.c_float), ("step_tol", ctypes.c_double)]
+
+
+class BackendProblem(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_int32), ("H", ctypes.c_int32), ("W", ctypes.c_int32), ("E", ctypes.c_int32),
+                ("Xc", ctypes.c_void_p), ("Q", ctypes.c_void_p), ("edges", ctypes.c_void_p),
+                ("idx", ctypes.c_void_p), ("valid", ctypes.c_void_p)]
+
+
 class M3SError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         self.status = status
@@ -67,7 +78,7 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_clear_caches", "m3s_status_string", "m3s_last_error", "m3s_version",
            "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
            "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
-           "m3s_fuse_pointmap"]
+           "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn"]
 
 _lib = None
 
@@ -123,6 +134,13 @@ def load(path: str = LIB_PATH):
     lib.m3s_track_pose.restype = ctypes.c_int
     lib.m3s_fuse_pointmap.argtypes = [ctypes.POINTER(FuseProblem), vp, vp]
     lib.m3s_fuse_pointmap.restype = ctypes.c_int
+    BP, BPr = ctypes.POINTER(BackendParams), ctypes.POINTER(BackendProblem)
+    lib.m3s_default_backend_params.argtypes = [BP]
+    lib.m3s_default_backend_params.restype = None
+    lib.m3s_backend_workspace_bytes.argtypes = [i32, i32, i32, i32]
+    lib.m3s_backend_workspace_bytes.restype = sz
+    lib.m3s_backend_gn.argtypes = [BPr, BP, vp, vp, vp, sz, vp]
+    lib.m3s_backend_gn.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib
@@ -148,6 +166,17 @@ def default_track_params(lib=None, **overrides) -> TrackParams:
     lib = lib or load()
     p = TrackParams()
     lib.m3s_default_track_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        if not hasattr(p, k):
+            raise TypeError("unknown parameter %s" % k)
+        setattr(p, k, v)
+    return p
+
+
+def default_backend_params(lib=None, **overrides) -> BackendParams:
+    lib = lib or load()
+    p = BackendParams()
+    lib.m3s_default_backend_params(ctypes.byref(p))
     for k, v in overrides.items():
         if not hasattr(p, k):
             raise TypeError("unknown parameter %s" % k)

@@ -11,6 +11,7 @@ or a CPU tensor raises.
     p, xhat, idx, valid, theta = MatchFunction.apply(Xii, Xji, Dii, Dji, Qii, Qji, None, params)
     T, info = track_pose(Xk, Xf, idx, valid, Qf, Qk, T)   # Sec. 3.3, T updated in place
     fuse_pointmap(Xc, Cc, X, C, T)                           # Eq. 8, in place
+    T_WC, info = backend_gn(Xc_all, Q_all, edges, idx_all, valid_all, T_WC)   # Sec. 3.5
 """
 from __future__ import annotations
 
@@ -219,6 +220,33 @@ def fuse_pointmap(Xc, Cc, X, C, T, stream=None):
     st = lib.m3s_fuse_pointmap(ctypes.byref(prob), _ptr(T, shape=(3, 4)), _stream(stream))
     _lib.check(lib, "m3s_fuse_pointmap", st)
     return Xc, Cc
+
+
+def backend_params(**overrides) -> _lib.BackendParams:
+    """Backend parameters: library defaults (10 iterations, q_min 1.5, sigma_ray 0.003,
+    sigma_dist 0.1, Huber 1.345, step_tol 0) with keyword overrides."""
+    return _lib.default_backend_params(None, **overrides)
+
+
+def backend_gn(Xc, Q, edges, idx, valid, T_WC, prm: Optional[_lib.BackendParams] = None, stream=None):
+    """m3s_backend_gn (Sec. 3.5): refines the world poses T_WC (device float32 (N, 3, 4), updated in
+    place, keyframe 0 held) over the edges (device int32 (E, 2)) with matches idx/valid (E, H, W).
+    Returns (T_WC, info) with info the device float32 tensor [cost, matches used, steps applied,
+    last step norm]."""
+    lib = _lib.load()
+    N, H, W = Xc.shape[:3]
+    E = edges.shape[0]
+    prob = _lib.BackendProblem(N, H, W, E, _ptr(Xc, shape=(N, H, W, 3)), _ptr(Q, shape=(N, H, W)),
+                               _ptr(edges, torch.int32, shape=(E, 2)), _ptr(idx, torch.int32, shape=(E, H, W)),
+                               _ptr(valid, torch.uint8, shape=(E, H, W)))
+    prm = prm if prm is not None else backend_params()
+    info = torch.empty(4, dtype=torch.float32, device=Xc.device)
+    nbytes = lib.m3s_backend_workspace_bytes(N, H, W, E)
+    ws = _workspace(nbytes, Xc.device)
+    st = lib.m3s_backend_gn(ctypes.byref(prob), ctypes.byref(prm), _ptr(T_WC, shape=(N, 3, 4)), _ptr(info),
+                            ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(lib, "m3s_backend_gn", st)
+    return T_WC, info
 
 
 def last_batched_config():

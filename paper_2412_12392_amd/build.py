@@ -19,7 +19,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libm3s.so")
-SOURCES = ["m3s_kernels.hip", "m3s_track.hip", "m3s_capi.hip"]
+SOURCES = ["m3s_kernels.hip", "m3s_track.hip", "m3s_backend.hip", "m3s_capi.hip"]
 
 
 def hipcc() -> str:

@@ -1,0 +1,541 @@
+// gfx950 kernels of the backend optimisation (MASt3R-SLAM, Sec. 3.5).
+//
+// Gauss-Newton over the world poses T_WC of N keyframes on the global ray
+// objective (Eq. backend_ray) plus the small-weight distance term, summed over
+// every edge (i, j) and every valid match (n of keyframe j, m = idx[n] of
+// keyframe i) with confidence q = sqrt(Q_i[m] Q_j[n]) > q_min.  The residuals
+// of an edge depend on the relative pose T_ij = T_WC[i]^-1 T_WC[j] only, and
+// the world-pose Jacobians are -J Ad(T_WC[i]^-1) and J Ad(T_WC[i]^-1) (Supp. A,
+// relative to global pose), so with A = Ad(T_WC[i]^-1) an edge contributes
+//   H_ii += A^T H_e A,  H_jj += A^T H_e A,  H_ij = H_ji^T -= A^T H_e A,
+//   g_i  -= A^T g_e,    g_j  += A^T g_e
+// where (H_e, g_e) are the edge's 7x7 normal equations w.r.t. a left
+// perturbation of T_ij.  Per iteration:
+//
+//   accum   grid (blocks, edges): every lane sums the relative normal
+//           equations of its matches in fp32 (the tracking residuals with
+//           x = T_ij X_j[n] transformed and X_i[m] measured); one partial per
+//           workgroup.
+//   edge    one workgroup per edge: the edge's partials summed in fp64 in a
+//           fixed order; A^T H_e A and A^T g_e.
+//   solve   one workgroup: the edges' blocks scattered in edge order into the
+//           reduced 7(N-1) system (keyframe 0 holds the gauge) by one wave
+//           whose lanes own fixed block offsets (so every address has one
+//           writer); blocked right-looking Cholesky in fp64 with 32 x 32
+//           tiles, the diagonal tile factored in LDS and the panel kept in
+//           LDS; blocked substitutions; T_WC[k] <- Exp(tau_k) o T_WC[k]
+//           (Eq. 1).  A system that is not positive definite, or a step norm
+//           below step_tol, ends the loop: later launches of the call return
+//           at once.
+//
+// Kernel boundaries order every hand-off, so no workgroup needs a
+// device-scope fence.  A final accumulation at the last poses gives the cost
+// and match count.  Launches are stream-ordered with no host synchronisation.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "m3s.h"
+#include "m3s_internal.h"
+#include "m3s_sim3.h"
+
+namespace m3s {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kSolveThreads = 512;
+constexpr int kVals = kPoseVals;
+constexpr int kStride = 40;         // floats per block partial, doubles per edge system
+constexpr int kMaxDim = 7 * (M3S_MAX_KEYFRAMES - 1);  // largest reduced system
+
+struct BackendArgs {
+    int N, HW, E, blocks_per_edge;
+    int n, np;                // reduced system size 7(N-1) and its padding to whole tiles
+    const float* Xc;          // [N*HW*3]
+    const float* Q;           // [N*HW]
+    const int32_t* edges;     // [E*2] (i, j)
+    const int32_t* idx;       // [E*HW]
+    const uint8_t* valid;     // [E*HW]
+    double q_min;
+    RobustWeights rw;
+    double step_tol;
+    double* T64;              // [N*12] world poses
+    double* edge_sys;         // [E*kStride] fp64 relative normal equations per edge
+    double* edge_blk;         // [E*kBlk] A^T H_e A (49) and A^T g_e (7) per edge
+    float* partials;          // [E*blocks_per_edge*kStride]
+    int32_t* state;           // [0] done flag, [1] applied steps
+    double* stat;             // [0] last step norm
+    double* M;                // [np*np] reduced Hessian, factored in place (lower triangle)
+    double* rhs;              // [np]
+    double* dinv;             // [nt*kTile*kTile] inverses of the diagonal tiles
+    float* T_out;             // [N*12]
+    float* info;              // [4] or null
+};
+
+constexpr int kBlk = 56;      // 49 + 7 doubles per edge
+constexpr int kTile = 32;     // tile of the blocked Cholesky
+constexpr int kPanelRows = 416;  // panel rows kept in LDS (larger systems read the panel from memory)
+constexpr int kStageRows = 64;   // raw panel rows staged per step of the panel product
+constexpr int kPanelStride = kTile + 1;  // odd stride in doubles: rows of a wave fall in different banks
+
+__global__ void __launch_bounds__(256) backend_init_kernel(const float* __restrict__ T_in, double* __restrict__ T64,
+                                                           int N, int32_t* __restrict__ state,
+                                                           double* __restrict__ stat) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < 12 * N) T64[t] = (double)T_in[t];
+    if (t < 2) { state[t] = 0; stat[t] = 0.0; }
+}
+
+__device__ __forceinline__ bool edge_in_range(int ei, int ej, int N) {
+    return ei >= 0 && ei < N && ej >= 0 && ej < N;
+}
+
+// final: 0 = an iteration's accumulation (skipped once the loop has ended), 1 = the final one.
+__global__ void __launch_bounds__(kThreads) backend_accum_kernel(BackendArgs A, int final_pass) {
+    __shared__ float red[kThreads / 64][kVals];
+    __shared__ float Ts[12];
+    if (!final_pass && A.state[0]) return;
+    const int e = blockIdx.y;
+    const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+    const bool edge_ok = edge_in_range(ei, ej, A.N);
+    if (threadIdx.x == 0) {
+        double Ti[12], Tij[12];
+        if (edge_ok) {
+            sim3_inverse(A.T64 + 12 * ei, Ti);
+            sim3_mul(Ti, A.T64 + 12 * ej, Tij);
+        } else {
+            for (int k = 0; k < 12; ++k) Tij[k] = 0.0;
+        }
+        for (int k = 0; k < 12; ++k) Ts[k] = (float)Tij[k];
+    }
+    __syncthreads();
+    float T[12];
+#pragma unroll
+    for (int k = 0; k < 12; ++k) T[k] = Ts[k];
+    float acc[kVals];
+#pragma unroll
+    for (int k = 0; k < kVals; ++k) acc[k] = 0.f;
+
+    const long ebase = (long)e * A.HW;
+    const float* Xi = A.Xc + (long)(edge_ok ? ei : 0) * A.HW * 3;
+    const float* Xj = A.Xc + (long)(edge_ok ? ej : 0) * A.HW * 3;
+    const float* Qi = A.Q + (long)(edge_ok ? ei : 0) * A.HW;
+    const float* Qj = A.Q + (long)(edge_ok ? ej : 0) * A.HW;
+    const int stride = A.blocks_per_edge * kThreads;
+    for (int n = edge_ok ? blockIdx.x * kThreads + threadIdx.x : A.HW; n < A.HW; n += stride) {
+        if (!A.valid[ebase + n]) continue;
+        const int m = A.idx[ebase + n];
+        if (m < 0 || m >= A.HW) continue;
+        const double q64 = sqrt((double)Qi[m] * (double)Qj[n]);
+        if (!(q64 > A.q_min)) continue;
+        accumulate_match(T, Xj[3 * n], Xj[3 * n + 1], Xj[3 * n + 2], Xi[3 * m], Xi[3 * m + 1], Xi[3 * m + 2],
+                         (float)q64, A.rw, acc);
+    }
+
+#pragma unroll
+    for (int k = 0; k < kVals; ++k) {
+        float v = acc[k];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[k] = v;
+    }
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < kVals; ++k) red[threadIdx.x >> 6][k] = acc[k];
+    }
+    __syncthreads();
+    if (threadIdx.x < kVals) {
+        float v = 0.f;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
+        A.partials[((size_t)e * A.blocks_per_edge + blockIdx.x) * kStride + threadIdx.x] = v;
+    }
+}
+
+// One workgroup per edge: fixed-order fp64 sum of the edge's partials; then
+// (iterations only) A = Ad(T_WC[i]^-1), A^T H_e A and A^T g_e.
+__global__ void __launch_bounds__(kThreads) backend_edge_kernel(BackendArgs A, int final_pass) {
+    __shared__ double tree[kVals * kThreads];
+    __shared__ double sys[kStride];
+    __shared__ double Ad[49];
+    if (!final_pass && A.state[0]) return;
+    const int e = blockIdx.x;
+    sum_partials<kThreads>(A.partials + (size_t)e * A.blocks_per_edge * kStride, A.blocks_per_edge, kStride, tree,
+                           sys);
+    if (threadIdx.x < kVals) A.edge_sys[(size_t)e * kStride + threadIdx.x] = sys[threadIdx.x];
+    if (final_pass) return;
+    const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+    if (!edge_in_range(ei, ej, A.N)) return;
+    if (threadIdx.x == 0) {
+        double Ti[12];
+        sim3_inverse(A.T64 + 12 * ei, Ti);
+        sim3_adjoint(Ti, Ad);
+    }
+    __syncthreads();
+    double* out = A.edge_blk + (size_t)e * kBlk;
+    if (threadIdx.x < 49) {
+        const int a = threadIdx.x / 7, b = threadIdx.x % 7;
+        double s = 0.0;
+        for (int k = 0; k < 7; ++k) {
+            double hk = 0.0;
+            for (int l = 0; l < 7; ++l) hk += sys[upper_index(k < l ? k : l, k < l ? l : k)] * Ad[7 * l + b];
+            s += Ad[7 * k + a] * hk;
+        }
+        out[threadIdx.x] = s;
+    } else if (threadIdx.x >= 64 && threadIdx.x < 71) {
+        const int a = threadIdx.x - 64;
+        double s = 0.0;
+        for (int k = 0; k < 7; ++k) s += Ad[7 * k + a] * sys[28 + k];
+        out[49 + a] = s;
+    }
+}
+
+// Tile (ti, tj) of M as kTile x kTile, row-major with leading dimension np.
+__device__ __forceinline__ double* tile_ptr(const BackendArgs& A, int ti, int tj) {
+    return A.M + (long)ti * kTile * A.np + (long)tj * kTile;
+}
+
+// Trailing update of one 32 x 32 tile (ti, tj), tj <= ti, of the lower
+// triangle below tile column k: M[R][C] -= L[R] . L[C], a 4 x 4 block per lane
+// of one wave.  P points at the panel rows (stride ps doubles): LDS or M.
+template <typename PanelPtr>
+__device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, int ps, int R0, int ti, int tj,
+                                              int lane) {
+    const int np = A.np;
+    const int r0 = (lane >> 3) * 4, c0 = (lane & 7) * 4;
+    const int ra = ti * kTile + r0, ca = tj * kTile + c0;
+    double acc[4][4] = {};
+    for (int t = 0; t < kTile; ++t) {
+        double va[4], vb[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            va[u] = P[(long)(ra + u) * ps + t];
+            vb[u] = P[(long)(ca + u) * ps + t];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[u][v] += va[u] * vb[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (ti != tj || c0 + v <= r0 + u) A.M[(long)(R0 + ra + u) * np + R0 + ca + v] -= acc[u][v];
+}
+
+// One workgroup: assemble the reduced system, factor it (blocked Cholesky),
+// solve and update the poses.
+__global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArgs A) {
+    __shared__ double D[kTile][kTile + 1];        // diagonal tile being factored
+    __shared__ double Dinv[kTile][kTile + 1];     // its inverse
+    __shared__ double panel[kPanelRows * kPanelStride];  // the factored panel below it
+    __shared__ double x[kMaxDim + kTile];          // right-hand side, then the solution
+    __shared__ double red[kSolveThreads / 64];
+    __shared__ double part[kTile];
+    __shared__ double stage[kStageRows * kPanelStride];  // raw panel rows
+    if (A.state[0]) return;
+    const int tid = threadIdx.x;
+    const int n = A.n, np = A.np, nt = np / kTile;
+
+    // Zero M and the right-hand side; padding rows get a unit diagonal.
+    for (int r = 0; r < np; ++r)
+        for (int c = tid; c < np; c += kSolveThreads) A.M[(long)r * np + c] = (r == c && r >= n) ? 1.0 : 0.0;
+    for (int k = tid; k < np; k += kSolveThreads) x[k] = 0.0;
+    __syncthreads();
+
+    // Scatter the edges' blocks in edge order.  Wave w owns the block rows p
+    // with (p - 1) % waves == w; within it lane (a, b) owns the entries whose
+    // offsets in their 7x7 block are (a, b) and lane 49 + a the right-hand side
+    // entries with offset a, so every address has one writer, which visits
+    // the edges in order.
+    {
+        const int wave = tid >> 6, lane = tid & 63;
+        const int a = lane / 7, b = lane % 7;
+        constexpr int kWaves = kSolveThreads / 64;
+        const double* __restrict__ blks = A.edge_blk;
+        for (int e = 0; e < A.E; ++e) {
+            const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+            // A self edge has T_ij = I whatever the poses: its blocks cancel.
+            if (!edge_in_range(ei, ej, A.N) || ei == ej) continue;
+            const bool own_i = ei > 0 && (ei - 1) % kWaves == wave;
+            const bool own_j = ej > 0 && (ej - 1) % kWaves == wave;
+            if (!own_i && !own_j) continue;
+            const double* blk = blks + (size_t)e * kBlk;
+            const int I = 7 * (ei - 1), J = 7 * (ej - 1);
+            if (lane < 49) {
+                const double v = blk[7 * a + b];
+                if (own_i) {
+                    A.M[(long)(I + a) * np + I + b] += v;
+                    if (ej > 0) A.M[(long)(I + a) * np + J + b] -= v;
+                }
+                if (own_j) {
+                    A.M[(long)(J + a) * np + J + b] += v;
+                    if (ei > 0) A.M[(long)(J + a) * np + I + b] -= blk[7 * b + a];
+                }
+            } else if (lane < 56) {
+                const int o = lane - 49;
+                // right-hand side -g: g_i -= A^T g_e, g_j += A^T g_e
+                if (own_i) x[I + o] += blk[49 + o];
+                if (own_j) x[J + o] -= blk[49 + o];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Blocked right-looking Cholesky, lower triangle, kTile x kTile tiles.
+    // Per tile column k: the diagonal tile is factored in LDS by the whole
+    // workgroup (one column per step), its inverse Dinv = L_kk^-1 is formed and
+    // kept for the substitutions, the panel below becomes A_ik Dinv^T (a
+    // product, no sequential chain) and the trailing lower triangle takes
+    // -= L_ik L_jk^T from the panel (in LDS when it fits).
+    bool failed = false;  // the same in every thread: decided from LDS values read after a barrier
+    for (int k = 0; k < nt; ++k) {
+        double* Mk = tile_ptr(A, k, k);
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) D[q / kTile][q % kTile] = Mk[(long)(q / kTile) * np + q % kTile];
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = (q / kTile == q % kTile) ? 1.0 : 0.0;
+        __syncthreads();
+        // Factor the tile, one column at a time, with the whole workgroup:
+        // scale L[.][c] and row c of Dinv by 1/sqrt(D[c][c]); then the
+        // trailing update of D and the row operations of Dinv = L_kk^-1.
+        // Every thread reads the same pivot after a barrier, so the decision
+        // to stop is the same in every thread.
+        for (int c = 0; c < kTile; ++c) {
+            const double dg = D[c][c];
+            if (!(dg > 0.0) || !isfinite(dg)) {
+                failed = true;
+                break;
+            }
+            const double sd = sqrt(dg);
+            if (tid > c && tid < kTile) D[tid][c] /= sd;
+            if (tid >= 64 && tid < 64 + kTile && tid - 64 <= c) Dinv[c][tid - 64] /= sd;
+            __syncthreads();
+            if (tid == 0) D[c][c] = sd;
+            for (int e2 = tid; e2 < kTile * kTile; e2 += kSolveThreads) {
+                const int r = e2 / kTile, q = e2 % kTile;
+                if (q > c && q <= r) D[r][q] -= D[r][c] * D[q][c];
+                if (r > c && q <= c) Dinv[r][q] -= D[r][c] * Dinv[c][q];
+            }
+            __syncthreads();
+        }
+        if (failed) break;
+        double* inv = A.dinv + (size_t)k * kTile * kTile;
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) {
+            const int r = q / kTile, c = q % kTile;
+            if (c <= r) Mk[(long)r * np + c] = D[r][c];
+            inv[q] = Dinv[r][c];
+        }
+        // Panel: L_ik = A_ik Dinv^T, kStageRows rows at a time staged in LDS,
+        // four elements per thread.
+        const int R0 = (k + 1) * kTile;
+        const int m = np - R0;
+        const bool in_lds = m <= kPanelRows;
+        for (int r0 = 0; r0 < m; r0 += kStageRows) {
+            for (int q = tid; q < kStageRows * kTile; q += kSolveThreads) {
+                const int rr = r0 + q / kTile, t = q % kTile;
+                if (rr < m) stage[(q / kTile) * kPanelStride + t] = A.M[(long)(R0 + rr) * np + k * kTile + t];
+            }
+            __syncthreads();
+            const int c = tid % kTile;
+#pragma unroll
+            for (int u = 0; u < kStageRows * kTile / kSolveThreads; ++u) {
+                const int sr = tid / kTile + u * (kSolveThreads / kTile);
+                const int rr = r0 + sr;
+                if (rr < m) {
+                    double acc = 0.0;
+                    for (int t = 0; t <= c; ++t) acc += stage[sr * kPanelStride + t] * Dinv[c][t];
+                    A.M[(long)(R0 + rr) * np + k * kTile + c] = acc;
+                    if (in_lds) panel[rr * kPanelStride + c] = acc;
+                }
+            }
+            __syncthreads();
+        }
+        // Trailing update of the lower triangle, M[R][C] -= L[R] . L[C] for
+        // R >= C >= R0: one wave per 32 x 32 tile.
+        {
+            const int tt = m / kTile;
+            const int ntiles = tt * (tt + 1) / 2;
+            const int wave = tid >> 6, lane = tid & 63;
+            for (int tix = wave; tix < ntiles; tix += kSolveThreads / 64) {
+                int ti = 0;
+                while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
+                const int tj = tix - ti * (ti + 1) / 2;
+                if (in_lds)
+                    trailing_tile(A, (const double*)panel, kPanelStride, R0, ti, tj, lane);
+                else
+                    trailing_tile(A, (const double*)(A.M + (long)R0 * np + k * kTile), np, R0, ti, tj, lane);
+            }
+        }
+        __syncthreads();
+    }
+    if (failed) {
+        if (tid == 0) A.state[0] = 1;
+        return;
+    }
+
+    // Forward substitution L y = rhs, tile by tile: the rows of tile k first
+    // subtract L[k][0..k) y (32 threads per row), then y_k = Dinv_k b_k.
+    const int lane = tid & 31;
+    for (int k = 0; k < nt; ++k) {
+        for (int row = tid >> 5; row < kTile; row += kSolveThreads / 32) {
+            const int R = k * kTile + row;
+            double s = 0.0;
+            for (int c = lane; c < k * kTile; c += 32) s += A.M[(long)R * np + c] * x[c];
+            for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+            if (lane == 0) x[R] -= s;
+        }
+        const double* inv = A.dinv + (size_t)k * kTile * kTile;
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = inv[q];
+        __syncthreads();
+        double y = 0.0;
+        if (tid < kTile) {
+            for (int t = 0; t <= tid; ++t) y += Dinv[tid][t] * x[k * kTile + t];
+        }
+        __syncthreads();
+        if (tid < kTile) x[k * kTile + tid] = y;
+        __syncthreads();
+    }
+    // Backward substitution L^T tau = y: column c of tile k first subtracts
+    // the rows below the tile, sum of L[R][c] tau[R]; then tau_k = Dinv_k^T b_k.
+    for (int k = nt - 1; k >= 0; --k) {
+        for (int row = tid >> 5; row < kTile; row += kSolveThreads / 32) {
+            const int C = k * kTile + row;
+            double s = 0.0;
+            for (int r = (k + 1) * kTile + lane; r < np; r += 32) s += A.M[(long)r * np + C] * x[r];
+            for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
+            if (lane == 0) part[row] = s;
+        }
+        const double* inv = A.dinv + (size_t)k * kTile * kTile;
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = inv[q];
+        __syncthreads();
+        if (tid < kTile) x[k * kTile + tid] -= part[tid];
+        __syncthreads();
+        double y = 0.0;
+        if (tid < kTile) {
+            for (int t = tid; t < kTile; ++t) y += Dinv[t][tid] * x[k * kTile + t];
+        }
+        __syncthreads();
+        if (tid < kTile) x[k * kTile + tid] = y;
+        __syncthreads();
+    }
+
+    // Pose updates, keyframes 1..N-1, and the step norm.
+    for (int k = 1 + tid; k < A.N; k += kSolveThreads) {
+        double E[12], Tn[12];
+        sim3_exp(x + 7 * (k - 1), E);
+        sim3_mul(E, A.T64 + 12 * k, Tn);
+        for (int j = 0; j < 12; ++j) A.T64[12 * k + j] = Tn[j];
+    }
+    double sq = 0.0;
+    for (int k = tid; k < n; k += kSolveThreads) sq += x[k] * x[k];
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kSolveThreads / 64; ++w) t += red[w];
+        const double step = sqrt(t);
+        A.stat[0] = step;
+        A.state[1] += 1;
+        if (step < A.step_tol) A.state[0] = 1;
+    }
+}
+
+__global__ void __launch_bounds__(256) backend_finish_kernel(BackendArgs A) {
+    const int t = threadIdx.x + blockIdx.x * blockDim.x;
+    if (t < 12 * A.N) A.T_out[t] = (float)A.T64[t];
+    if (t == 0 && A.info) {
+        double cost = 0.0, count = 0.0;
+        for (int e = 0; e < A.E; ++e) {
+            if (!edge_in_range(A.edges[2 * e], A.edges[2 * e + 1], A.N)) continue;
+            cost += A.edge_sys[(size_t)e * kStride + 35];
+            count += A.edge_sys[(size_t)e * kStride + 36];
+        }
+        A.info[0] = (float)cost;
+        A.info[1] = (float)count;
+        A.info[2] = (float)A.state[1];
+        A.info[3] = (float)A.stat[0];
+    }
+}
+
+// Workspace layout.
+struct BackendLayout {
+    size_t T64, edge_sys, edge_blk, partials, state, stat, M, rhs, dinv, total;
+};
+
+int padded_dim(int N) { return (7 * (N - 1) + kTile - 1) / kTile * kTile; }
+
+BackendLayout backend_layout(int N, int HW, int E) {
+    auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+    const int bpe = backend_blocks_per_edge(HW);
+    const size_t np = padded_dim(N);
+    BackendLayout L;
+    size_t o = 0;
+    L.T64 = o;      o = al(o + sizeof(double) * 12 * N);
+    L.edge_sys = o; o = al(o + sizeof(double) * kStride * E);
+    L.edge_blk = o; o = al(o + sizeof(double) * kBlk * E);
+    L.partials = o; o = al(o + sizeof(float) * kStride * (size_t)bpe * E);
+    L.state = o;    o = al(o + sizeof(int32_t) * 2);
+    L.stat = o;     o = al(o + sizeof(double) * 2);
+    L.M = o;        o = al(o + sizeof(double) * np * np);
+    L.rhs = o;      o = al(o + sizeof(double) * np);
+    L.dinv = o;     o = al(o + sizeof(double) * np * kTile);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+int backend_blocks_per_edge(int HW) {
+    const int b = (HW + kThreads * 4 - 1) / (kThreads * 4);
+    return b < 1 ? 1 : (b > 1024 ? 1024 : b);
+}
+
+size_t backend_workspace_bytes(int N, int HW, int E) { return backend_layout(N, HW, E).total; }
+
+hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q, const int32_t* edges,
+                          const int32_t* idx, const uint8_t* valid, float q_min, float sigma_ray, float sigma_dist,
+                          float huber, int iters, double step_tol, float* T, float* info, void* ws, hipStream_t s) {
+    const BackendLayout L = backend_layout(N, HW, E);
+    char* w = reinterpret_cast<char*>(ws);
+    BackendArgs A;
+    A.N = N; A.HW = HW; A.E = E;
+    A.blocks_per_edge = backend_blocks_per_edge(HW);
+    A.n = 7 * (N - 1);
+    A.np = padded_dim(N);
+    A.Xc = Xc; A.Q = Q; A.edges = edges; A.idx = idx; A.valid = valid;
+    A.q_min = (double)q_min;
+    A.rw = robust_weights(sigma_ray, sigma_dist, huber);
+    A.step_tol = step_tol;
+    A.T64 = reinterpret_cast<double*>(w + L.T64);
+    A.edge_sys = reinterpret_cast<double*>(w + L.edge_sys);
+    A.edge_blk = reinterpret_cast<double*>(w + L.edge_blk);
+    A.partials = reinterpret_cast<float*>(w + L.partials);
+    A.state = reinterpret_cast<int32_t*>(w + L.state);
+    A.stat = reinterpret_cast<double*>(w + L.stat);
+    A.M = reinterpret_cast<double*>(w + L.M);
+    A.rhs = reinterpret_cast<double*>(w + L.rhs);
+    A.dinv = reinterpret_cast<double*>(w + L.dinv);
+    A.T_out = T;
+    A.info = info;
+    const dim3 grid(A.blocks_per_edge, E);
+    backend_init_kernel<<<(12 * N + 255) / 256, 256, 0, s>>>(T, A.T64, N, A.state, A.stat);
+    for (int it = 0; it <= iters; ++it) {
+        const int final_pass = it == iters ? 1 : 0;
+        timer_begin("backend_accum", s);
+        backend_accum_kernel<<<grid, kThreads, 0, s>>>(A, final_pass);
+        timer_end(s);
+        timer_begin("backend_edge", s);
+        backend_edge_kernel<<<E, kThreads, 0, s>>>(A, final_pass);
+        timer_end(s);
+        if (final_pass) break;
+        timer_begin("backend_solve", s);
+        backend_solve_kernel<<<1, kSolveThreads, 0, s>>>(A);
+        timer_end(s);
+    }
+    backend_finish_kernel<<<(12 * N + 255) / 256, 256, 0, s>>>(A);
+    return hipGetLastError();
+}
+
+}  // namespace m3s

@@ -270,6 +270,7 @@ hipEvent_t pooled_event() {
 }
 
 bool capturing(hipStream_t s) {
+    if (s == nullptr) return false;  // the null stream is never captured
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(s, &st) != hipSuccess) return true;
     return st != hipStreamCaptureStatusNone;
@@ -495,6 +496,61 @@ m3s_status m3s_fuse_pointmap(const m3s_fuse_problem* prob, const float* T, void*
     hipError_t e = m3s::launch_fuse(prob->H * prob->W, T, prob->Xc, prob->Cc, prob->X, prob->C,
                                     reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "fusion launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+void m3s_default_backend_params(m3s_backend_params* P) {
+    if (!P) return;
+    P->iters = 10;
+    P->q_min = 1.5f;
+    P->sigma_ray = 0.003f;
+    P->sigma_dist = 0.1f;
+    P->huber = 1.345f;
+    P->step_tol = 0.0;
+}
+
+size_t m3s_backend_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t E) {
+    if (N < 2 || N > M3S_MAX_KEYFRAMES || E < 1 || E > M3S_MAX_EDGES || H < 2 || W < 2 ||
+        (int64_t)H * W > M3S_MAX_PIXELS)
+        return 0;
+    return align_up(m3s::backend_workspace_bytes(N, H * W, E));
+}
+
+m3s_status m3s_backend_gn(const m3s_backend_problem* prob, const m3s_backend_params* params, float* T_WC,
+                          float* info, void* ws, size_t ws_bytes, void* stream) {
+    m3s_backend_params defaults;
+    m3s_default_backend_params(&defaults);
+    const m3s_backend_params* P = params ? params : &defaults;
+    if (!prob) return fail(M3S_ERR_NULL, "problem is NULL");
+    m3s_status s = check_shape(prob->H, prob->W);
+    if (s != M3S_OK) return s;
+    if (prob->N < 2 || prob->N > M3S_MAX_KEYFRAMES)
+        return fail(M3S_ERR_SHAPE, "N %d outside [2, %d]", prob->N, M3S_MAX_KEYFRAMES);
+    if (prob->E < 1 || prob->E > M3S_MAX_EDGES) return fail(M3S_ERR_SHAPE, "E %d outside [1, %d]", prob->E, M3S_MAX_EDGES);
+    if ((int64_t)prob->N * prob->H * prob->W * 3 > INT32_MAX || (int64_t)prob->E * prob->H * prob->W > INT32_MAX)
+        return fail(M3S_ERR_SHAPE, "N * H * W * 3 and E * H * W must stay below 2^31");
+    if (!prob->Xc || !prob->Q || !prob->edges || !prob->idx || !prob->valid || !T_WC)
+        return fail(M3S_ERR_NULL, "Xc, Q, edges, idx, valid and T_WC are required");
+    if (!aligned(prob->Xc, 4) || !aligned(prob->Q, 4) || !aligned(prob->edges, 4) || !aligned(prob->idx, 4) ||
+        !aligned(T_WC, 4) || (info && !aligned(info, 4)))
+        return fail(M3S_ERR_PARAM, "arrays must be 4-byte aligned");
+    if (P->iters < 0 || P->iters > M3S_MAX_ITER) return fail(M3S_ERR_PARAM, "iters %d outside [0, %d]", P->iters, M3S_MAX_ITER);
+    if (!std::isfinite(P->q_min)) return fail(M3S_ERR_PARAM, "q_min must be finite");
+    if (std::isnan(P->sigma_ray) || !(P->sigma_ray > 0.f)) return fail(M3S_ERR_PARAM, "sigma_ray must be > 0");
+    if (std::isnan(P->sigma_dist) || !(P->sigma_dist > 0.f)) return fail(M3S_ERR_PARAM, "sigma_dist must be > 0");
+    if (std::isnan(P->huber) || !(P->huber > 0.f)) return fail(M3S_ERR_PARAM, "huber must be > 0");
+    if (std::isnan(P->step_tol) || P->step_tol < 0.0) return fail(M3S_ERR_PARAM, "step_tol must be >= 0");
+    const size_t need = m3s_backend_workspace_bytes(prob->N, prob->H, prob->W, prob->E);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need, ws_bytes);
+    int dev;
+    DeviceInfo info_dev;
+    if ((s = current_device(&dev, &info_dev)) != M3S_OK) return s;
+    hipError_t e = m3s::launch_backend(prob->N, prob->H * prob->W, prob->E, prob->Xc, prob->Q, prob->edges, prob->idx,
+                                       prob->valid, P->q_min, P->sigma_ray, P->sigma_dist, P->huber, P->iters,
+                                       P->step_tol, T_WC, info, ws, reinterpret_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "backend launch");
     g_last_error.clear();
     return M3S_OK;
 }

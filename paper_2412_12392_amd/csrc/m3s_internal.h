@@ -43,4 +43,11 @@ hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* 
 // Canonical pointmap fusion (Eq. 8) with the pose T read from device memory.
 hipError_t launch_fuse(int N, const float* T, float* Xc, float* Cc, const float* X, const float* C, hipStream_t s);
 
+// Backend Gauss-Newton (m3s_backend.hip).
+int backend_blocks_per_edge(int HW);
+size_t backend_workspace_bytes(int N, int HW, int E);
+hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q, const int32_t* edges,
+                          const int32_t* idx, const uint8_t* valid, float q_min, float sigma_ray, float sigma_dist,
+                          float huber, int iters, double step_tol, float* T, float* info, void* ws, hipStream_t s);
+
 }  // namespace m3s

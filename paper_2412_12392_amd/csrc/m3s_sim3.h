@@ -1,0 +1,227 @@
+// Device helpers shared by the pose solves (MASt3R-SLAM, Sec. 3.3 and 3.5):
+// Sim(3) algebra in fp64 and the per-match accumulation of the ray and
+// distance normal equations in fp32.
+//
+// Pose layout: row-major 3x4 [sR | t].  Tangent order tau = (v, omega, sigma),
+// matching the point Jacobian [I, -[x]_x, x] of Supp. A; updates are left plus,
+// T <- Exp(tau) o T (Eq. 1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+namespace m3s {
+
+// Number of accumulated values per match set: the upper triangle of the 7x7
+// J^T W J (28, rows of 7, 6, ..., 1), J^T W r (7), robust cost, match count.
+constexpr int kPoseVals = 28 + 7 + 2;
+
+__device__ __forceinline__ int upper_index(int a, int b) { return a * 7 - a * (a - 1) / 2 + (b - a); }
+
+// Huber weight and cost of a whitened norm a with the given width.
+__device__ __forceinline__ float huber_weight(float a, float width) { return a <= width ? 1.f : width / a; }
+__device__ __forceinline__ float huber_cost(float a, float width) {
+    return a <= width ? 0.5f * a * a : width * (a - 0.5f * width);
+}
+
+// Weights of the two residual blocks: 1 / sigma^2 and 1 / sigma (0 drops the
+// residual), and the Huber width.
+struct RobustWeights {
+    float w_ray, w_dist, is_ray, is_dist, huber;
+};
+
+inline RobustWeights robust_weights(float sigma_ray, float sigma_dist, float huber) {
+    RobustWeights w;
+    w.w_ray = isinf(sigma_ray) ? 0.f : 1.f / (sigma_ray * sigma_ray);
+    w.w_dist = isinf(sigma_dist) ? 0.f : 1.f / (sigma_dist * sigma_dist);
+    w.is_ray = isinf(sigma_ray) ? 0.f : 1.f / sigma_ray;
+    w.is_dist = isinf(sigma_dist) ? 0.f : 1.f / sigma_dist;
+    w.huber = huber;
+    return w;
+}
+
+// One match: x = T X (X the point that moves with the pose), Y the measured
+// point, q its confidence.  Ray residual psi(x) - psi(Y) and distance residual
+// |x| - |Y| (Sec. 3.3), Jacobians w.r.t. a left perturbation of T (Supp. A:
+// [N(x), -[x]_x / |x|, 0] and [x^T / |x|, 0, |x|]), weights q / sigma^2 times
+// the Huber weight of the whitened block norm |r| sqrt(q) / sigma.  Adds to
+// acc and returns true, or returns false for a point at the origin or
+// non-finite.
+__device__ __forceinline__ bool accumulate_match(const float* T, float X0, float X1, float X2, float Y0, float Y1,
+                                                 float Y2, float q, const RobustWeights& rw, float* acc) {
+    const float x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[3];
+    const float x1 = T[4] * X0 + T[5] * X1 + T[6] * X2 + T[7];
+    const float x2 = T[8] * X0 + T[9] * X1 + T[10] * X2 + T[11];
+    const float d = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
+    const float dy = sqrtf(Y0 * Y0 + Y1 * Y1 + Y2 * Y2);
+    if (!(d > 0.f) || !(dy > 0.f) || !isfinite(d) || !isfinite(dy)) return false;
+    const float id = 1.f / d, idy = 1.f / dy;
+    const float u[3] = {x0 * id, x1 * id, x2 * id};
+    const float x[3] = {x0, x1, x2};
+    const float res[4] = {u[0] - Y0 * idy, u[1] - Y1 * idy, u[2] - Y2 * idy, d - dy};
+    float J[4][7];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) J[r][c] = ((r == c ? 1.f : 0.f) - u[r] * u[c]) * id;
+        J[r][6] = 0.f;
+    }
+    // -[x]_x / d
+    J[0][3] = 0.f;         J[0][4] = x[2] * id;   J[0][5] = -x[1] * id;
+    J[1][3] = -x[2] * id;  J[1][4] = 0.f;         J[1][5] = x[0] * id;
+    J[2][3] = x[1] * id;   J[2][4] = -x[0] * id;  J[2][5] = 0.f;
+    J[3][0] = u[0]; J[3][1] = u[1]; J[3][2] = u[2];
+    J[3][3] = 0.f;  J[3][4] = 0.f;  J[3][5] = 0.f;  J[3][6] = d;
+    const float sq = sqrtf(q);
+    const float a_ray = sqrtf(res[0] * res[0] + res[1] * res[1] + res[2] * res[2]) * sq * rw.is_ray;
+    const float a_dist = fabsf(res[3]) * sq * rw.is_dist;
+    const float wr = q * rw.w_ray * huber_weight(a_ray, rw.huber);
+    const float wd = q * rw.w_dist * huber_weight(a_dist, rw.huber);
+    const float w[4] = {wr, wr, wr, wd};
+    int k = 0;
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+#pragma unroll
+        for (int b = a; b < 7; ++b) {
+            float h = 0.f;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) h = fmaf(J[r][a] * w[r], J[r][b], h);
+            acc[k++] += h;
+        }
+    }
+#pragma unroll
+    for (int a = 0; a < 7; ++a) {
+        float g = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) g = fmaf(J[r][a] * w[r], res[r], g);
+        acc[28 + a] += g;
+    }
+    acc[35] += huber_cost(a_ray, rw.huber) + huber_cost(a_dist, rw.huber);
+    acc[36] += 1.f;
+    return true;
+}
+
+// Fixed-order fp64 sum of nparts fp32 partials of kPoseVals values each
+// (stride `stride` floats) by a workgroup of NT threads: thread t adds the
+// partials t, t + NT, ... for every value (all loads independent), then a
+// pairwise tree over the threads in LDS.  The order depends on NT and nparts
+// only.  `tree` is LDS of kPoseVals * NT doubles; the sums land in out[0 ..
+// kPoseVals) (LDS), visible to the whole workgroup on return.
+template <int NT>
+__device__ void sum_partials(const float* __restrict__ parts, int nparts, int stride, double* tree, double* out) {
+    const int t = threadIdx.x;
+    double acc[kPoseVals];
+#pragma unroll
+    for (int v = 0; v < kPoseVals; ++v) acc[v] = 0.0;
+    for (int b = t; b < nparts; b += NT) {
+        const float* p = parts + (size_t)b * stride;
+#pragma unroll
+        for (int v = 0; v < kPoseVals; ++v) acc[v] += (double)p[v];
+    }
+#pragma unroll
+    for (int v = 0; v < kPoseVals; ++v) tree[v * NT + t] = acc[v];
+    __syncthreads();
+    for (int h = NT / 2; h > 0; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int v = 0; v < kPoseVals; ++v) tree[v * NT + t] += tree[v * NT + t + h];
+        }
+        __syncthreads();
+    }
+    if (t < kPoseVals) out[t] = tree[t * NT];
+    __syncthreads();
+}
+
+// Scale of a similarity [sR | t]: the cube root of det(sR).
+__device__ inline double sim3_scale(const double* T) {
+    const double det = T[0] * (T[5] * T[10] - T[6] * T[9]) - T[1] * (T[4] * T[10] - T[6] * T[8]) +
+                       T[2] * (T[4] * T[9] - T[5] * T[8]);
+    return cbrt(det);
+}
+
+// out = T^-1 = [R^T / s | -R^T t / s].
+__device__ inline void sim3_inverse(const double* T, double* out) {
+    const double s = sim3_scale(T), s2 = s * s;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) out[4 * i + j] = T[4 * j + i] / s2;
+    for (int i = 0; i < 3; ++i)
+        out[4 * i + 3] = -(out[4 * i] * T[3] + out[4 * i + 1] * T[7] + out[4 * i + 2] * T[11]);
+}
+
+// out = A B (out must not alias A or B).
+__device__ inline void sim3_mul(const double* A, const double* B, double* out) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 4; ++j)
+            out[4 * i + j] = A[4 * i] * B[j] + A[4 * i + 1] * B[4 + j] + A[4 * i + 2] * B[8 + j] +
+                             (j == 3 ? A[4 * i + 3] : 0.0);
+}
+
+// Ad(T) on (v, omega, sigma): [[sR, [t]_x R, -t], [0, R, 0], [0, 0, 1]], row-major 7x7.
+__device__ inline void sim3_adjoint(const double* T, double* A) {
+    const double s = sim3_scale(T);
+    double R[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) R[i][j] = T[4 * i + j] / s;
+    const double t[3] = {T[3], T[7], T[11]};
+    const double S[3][3] = {{0.0, -t[2], t[1]}, {t[2], 0.0, -t[0]}, {-t[1], t[0], 0.0}};
+    for (int k = 0; k < 49; ++k) A[k] = 0.0;
+    for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) {
+            A[7 * i + j] = s * R[i][j];
+            A[7 * i + 3 + j] = S[i][0] * R[0][j] + S[i][1] * R[1][j] + S[i][2] * R[2][j];
+            A[7 * (3 + i) + 3 + j] = R[i][j];
+        }
+        A[7 * i + 6] = -t[i];
+    }
+    A[48] = 1.0;
+}
+
+// Exp of sim(3): tau = (v, omega, sigma) -> [e^sigma R | V v], R by Rodrigues
+// and V = a0 I + a1 [omega]_x + a2 [omega]_x^2 with a0 = int e^{sigma s},
+// a1 = int e^{sigma s} sin(theta s) / theta and
+// a2 = int e^{sigma s} (1 - cos(theta s)) / theta^2 over s in [0, 1]; their
+// series near theta = 0 and sigma = 0.
+__device__ inline void sim3_exp(const double* tau, double* E) {
+    const double sg = tau[6];
+    const double w0 = tau[3], w1 = tau[4], w2 = tau[5];
+    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
+    const double S[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
+    double S2[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) S2[i][j] = S[i][0] * S[0][j] + S[i][1] * S[1][j] + S[i][2] * S[2][j];
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    const bool small = th < 1e-4;
+    const double ka = small ? 1.0 - th2 / 6.0 : sn / th;
+    const double kb = small ? 0.5 - th2 / 24.0 : (1.0 - cs) / th2;
+    const double es = exp(sg);
+    const double a0 = sg == 0.0 ? 1.0 : expm1(sg) / sg;
+    double a1, a2;
+    if (small) {
+        const double s2 = sg * sg;
+        if (fabs(sg) < 1e-3) {
+            a1 = 0.5 + sg / 3.0 + s2 / 8.0 + s2 * sg / 30.0;
+            a2 = 1.0 / 6.0 + sg / 8.0 + s2 / 20.0 + s2 * sg / 72.0;
+        } else {
+            a1 = (es * (sg - 1.0) + 1.0) / s2;
+            a2 = (es * (s2 - 2.0 * sg + 2.0) - 2.0) / (2.0 * s2 * sg);
+        }
+    } else {
+        const double den = sg * sg + th2;
+        const double is = (es * (sg * sn - th * cs) + th) / den;
+        const double ic = (es * (sg * cs + th * sn) - sg) / den;
+        a1 = is / th;
+        a2 = (a0 - ic) / th2;
+    }
+    for (int i = 0; i < 3; ++i) {
+        double tv = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double I = i == j ? 1.0 : 0.0;
+            E[4 * i + j] = es * (I + ka * S[i][j] + kb * S2[i][j]);
+            tv += (I * a0 + a1 * S[i][j] + a2 * S2[i][j]) * tau[j];
+        }
+        E[4 * i + 3] = tv;
+    }
+}
+
+}  // namespace m3s

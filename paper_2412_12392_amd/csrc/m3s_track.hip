@@ -4,45 +4,45 @@
 // Gauss-Newton in an iteratively reweighted least-squares loop (Eq.
 // gauss_newton) for the Sim(3) pose T_kf that maps frame points X^f_f into the
 // keyframe, over the matches of the keyframe's pixels found by the matcher.
-// One launch per iteration; in it
+// Two launches per iteration:
 //
-//   every lane takes matches n (grid-stride): x = T Xf[m] with m = idx[n];
-//     ray residual psi(x) - psi(Xk[n]) (Eq. track_ray) and distance residual
-//     |x| - |Xk[n]| (the small-weight distance term); Jacobians w.r.t. a left
-//     perturbation (Supp. A: [N(x), -[x]_x / |x|, 0] and [x^T / |x|, 0, |x|]);
-//     weights q / sigma^2 (match confidence q = sqrt(Qf[m] Qk[n]) gated at
-//     q_min, Sec. 3.3) times the Huber weight of the whitened block norm;
-//   every block writes its partial sums of J^T W J (upper triangle), J^T W r,
-//     robust cost and count;
-//   the block that finishes last (agent-scope ticket counter) sums the
-//     partials in fp64 in a fixed order, solves the 7x7 system by Cholesky
-//     and applies T <- Exp(tau) o T (Eq. 1, left plus on Sim(3)) in fp64.
+//   accum   one lane per match n: x = T Xf[m] with m = idx[n]; ray residual
+//           psi(x) - psi(Xk[n]) (Eq. track_ray) and distance residual
+//           |x| - |Xk[n]| (the small-weight distance term); Jacobians w.r.t. a
+//           left perturbation (Supp. A); weights q / sigma^2 (match confidence
+//           q = sqrt(Qf[m] Qk[n]) gated at q_min, Sec. 3.3) times the Huber
+//           weight of the whitened block norm; one fp32 partial of J^T W J
+//           (upper triangle), J^T W r, robust cost and count per workgroup.
+//   solve   one workgroup: the partials summed in fp64 in a fixed order, the
+//           7x7 system solved by Cholesky and T <- Exp(tau) o T applied
+//           (Eq. 1, left plus on Sim(3)) in fp64.
 //
-// The pose lives in the workspace in fp64 between launches; the last launch
-// evaluates the cost at the final pose and writes the fp32 pose and the
-// statistics.  Tangent order (v, omega, sigma), as in the point Jacobian
-// [I, -[x]_x, x].  Launches are stream-ordered with no host synchronisation,
-// so the whole solve can be captured into a graph.
+// The kernel boundary orders the partials before their sum, so no workgroup
+// needs a device-scope fence (on this part a device-scope release writes back
+// the XCD's L2).  The pose lives in the workspace in fp64 between launches;
+// the last pair evaluates the cost at the final pose and writes the fp32 pose
+// and the statistics.  Launches are stream-ordered with no host
+// synchronisation, so the whole solve can be captured into a graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
 
 #include "m3s_internal.h"
+#include "m3s_sim3.h"
 
 namespace m3s {
 
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kVals = 28 + 7 + 2;   // H upper triangle, g, cost, count
+constexpr int kVals = kPoseVals;
 constexpr int kStride = 40;         // floats per block partial
-constexpr int kChunks = 6;          // fp64 reduction: kStride * kChunks <= kThreads
-constexpr int kMaxBlocks = 1024;
+constexpr int kMaxBlocks = 2048;
 
 // Workspace layout (bytes): pose, statistics, counters, then the partials.
 constexpr size_t kOffT = 0;         // double[12]
 constexpr size_t kOffStat = 96;     // double[2]: last step norm, reserved
-constexpr size_t kOffCnt = 128;     // int32[2]: ticket counter, solved iterations
+constexpr size_t kOffCnt = 128;     // int32[2]: reserved, solved iterations
 constexpr size_t kOffPart = 256;    // float[nblocks * kStride]
 
 struct TrackArgs {
@@ -54,22 +54,15 @@ struct TrackArgs {
     const float* Qf;
     const float* Qk;
     double q_min;
-    float w_ray, w_dist;    // 1 / sigma^2 (0 drops the residual)
-    float is_ray, is_dist;  // 1 / sigma
-    float huber;
+    RobustWeights rw;
     double* T64;
     double* stat;
-    int32_t* counter;
+    int32_t* counter;       // [0] reserved, [1] solved iterations
     int32_t* solved;
     float* partials;
     float* T_out;
     float* info;
 };
-
-__device__ __forceinline__ float huber_weight(float a, float width) { return a <= width ? 1.f : width / a; }
-__device__ __forceinline__ float huber_cost(float a, float width) {
-    return a <= width ? 0.5f * a * a : width * (a - 0.5f * width);
-}
 
 __global__ void __launch_bounds__(64) track_init_kernel(const float* __restrict__ T_in, double* __restrict__ T64,
                                                         int32_t* __restrict__ cnt, double* __restrict__ stat) {
@@ -77,57 +70,6 @@ __global__ void __launch_bounds__(64) track_init_kernel(const float* __restrict_
     if (i < 12) T64[i] = (double)T_in[i];
     if (i < 2) { cnt[i] = 0; stat[i] = 0.0; }
 }
-
-// Exp of sim(3): tau = (v, omega, sigma) -> [e^sigma R | V v], R by Rodrigues
-// and V = a0 I + a1 [omega]_x + a2 [omega]_x^2 with a0 = int e^{sigma s},
-// a1 = int e^{sigma s} sin(theta s) / theta and
-// a2 = int e^{sigma s} (1 - cos(theta s)) / theta^2 over s in [0, 1]; their
-// series near theta = 0 and sigma = 0.
-__device__ void sim3_exp(const double* tau, double* E) {
-    const double sg = tau[6];
-    const double w0 = tau[3], w1 = tau[4], w2 = tau[5];
-    const double th2 = w0 * w0 + w1 * w1 + w2 * w2, th = sqrt(th2);
-    const double S[3][3] = {{0.0, -w2, w1}, {w2, 0.0, -w0}, {-w1, w0, 0.0}};
-    double S2[3][3];
-    for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) S2[i][j] = S[i][0] * S[0][j] + S[i][1] * S[1][j] + S[i][2] * S[2][j];
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    const bool small = th < 1e-4;
-    const double ka = small ? 1.0 - th2 / 6.0 : sn / th;
-    const double kb = small ? 0.5 - th2 / 24.0 : (1.0 - cs) / th2;
-    const double es = exp(sg);
-    const double a0 = sg == 0.0 ? 1.0 : expm1(sg) / sg;
-    double a1, a2;
-    if (small) {
-        const double s2 = sg * sg;
-        if (fabs(sg) < 1e-3) {
-            a1 = 0.5 + sg / 3.0 + s2 / 8.0 + s2 * sg / 30.0;
-            a2 = 1.0 / 6.0 + sg / 8.0 + s2 / 20.0 + s2 * sg / 72.0;
-        } else {
-            a1 = (es * (sg - 1.0) + 1.0) / s2;
-            a2 = (es * (s2 - 2.0 * sg + 2.0) - 2.0) / (2.0 * s2 * sg);
-        }
-    } else {
-        const double den = sg * sg + th2;
-        const double is = (es * (sg * sn - th * cs) + th) / den;
-        const double ic = (es * (sg * cs + th * sn) - sg) / den;
-        a1 = is / th;
-        a2 = (a0 - ic) / th2;
-    }
-    for (int i = 0; i < 3; ++i) {
-        double tv = 0.0;
-        for (int j = 0; j < 3; ++j) {
-            const double I = i == j ? 1.0 : 0.0;
-            E[4 * i + j] = es * (I + ka * S[i][j] + kb * S2[i][j]);
-            tv += (I * a0 + a1 * S[i][j] + a2 * S2[i][j]) * tau[j];
-        }
-        E[4 * i + 3] = tv;
-    }
-}
-
-// Entry (a, b), a <= b, of the packed upper triangle (rows of 7, 6, ..., 1).
-__device__ __forceinline__ int upper_index(int a, int b) { return a * 7 - a * (a - 1) / 2 + (b - a); }
 
 // Solve H tau = -g (7x7 SPD) and apply T <- Exp(tau) o T.  Returns false
 // (pose unchanged) when H is not positive definite.
@@ -171,13 +113,10 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
     return true;
 }
 
-// mode 0: accumulate and update the pose; mode 1: accumulate at the final
-// pose and write the outputs.
-__global__ void __launch_bounds__(kThreads) track_iter_kernel(TrackArgs A, int mode) {
+// Normal equations of the matches of this workgroup at the current pose: one
+// fp32 partial of kVals values per workgroup.
+__global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
     __shared__ float red[kThreads / 64][kVals];
-    __shared__ double dsum[kChunks][kStride];
-    __shared__ int last;
-
     float T[12];
 #pragma unroll
     for (int i = 0; i < 12; ++i) T[i] = (float)A.T64[i];
@@ -194,57 +133,8 @@ __global__ void __launch_bounds__(kThreads) track_iter_kernel(TrackArgs A, int m
         const double q64 = sqrt((double)A.Qf[m] * (double)A.Qk[n]);
         if (!(q64 > A.q_min)) continue;
         const float q = (float)q64;
-        const float X0 = A.Xf[3 * m], X1 = A.Xf[3 * m + 1], X2 = A.Xf[3 * m + 2];
-        const float Y0 = A.Xk[3 * n], Y1 = A.Xk[3 * n + 1], Y2 = A.Xk[3 * n + 2];
-        const float x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[3];
-        const float x1 = T[4] * X0 + T[5] * X1 + T[6] * X2 + T[7];
-        const float x2 = T[8] * X0 + T[9] * X1 + T[10] * X2 + T[11];
-        const float d = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
-        const float dy = sqrtf(Y0 * Y0 + Y1 * Y1 + Y2 * Y2);
-        if (!(d > 0.f) || !(dy > 0.f) || !isfinite(d) || !isfinite(dy)) continue;
-        const float id = 1.f / d, idy = 1.f / dy;
-        const float u[3] = {x0 * id, x1 * id, x2 * id};
-        const float x[3] = {x0, x1, x2};
-        const float res[4] = {u[0] - Y0 * idy, u[1] - Y1 * idy, u[2] - Y2 * idy, d - dy};
-        float J[4][7];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-#pragma unroll
-            for (int j = 0; j < 3; ++j) J[i][j] = ((i == j ? 1.f : 0.f) - u[i] * u[j]) * id;
-            J[i][6] = 0.f;
-        }
-        // -[x]_x / d
-        J[0][3] = 0.f;         J[0][4] = x[2] * id;   J[0][5] = -x[1] * id;
-        J[1][3] = -x[2] * id;  J[1][4] = 0.f;         J[1][5] = x[0] * id;
-        J[2][3] = x[1] * id;   J[2][4] = -x[0] * id;  J[2][5] = 0.f;
-        J[3][0] = u[0]; J[3][1] = u[1]; J[3][2] = u[2];
-        J[3][3] = 0.f;  J[3][4] = 0.f;  J[3][5] = 0.f;  J[3][6] = d;
-        const float sq = sqrtf(q);
-        const float a_ray = sqrtf(res[0] * res[0] + res[1] * res[1] + res[2] * res[2]) * sq * A.is_ray;
-        const float a_dist = fabsf(res[3]) * sq * A.is_dist;
-        const float wr = q * A.w_ray * huber_weight(a_ray, A.huber);
-        const float wd = q * A.w_dist * huber_weight(a_dist, A.huber);
-        const float w[4] = {wr, wr, wr, wd};
-        int k = 0;
-#pragma unroll
-        for (int a = 0; a < 7; ++a) {
-#pragma unroll
-            for (int b = a; b < 7; ++b) {
-                float h = 0.f;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) h = fmaf(J[r][a] * w[r], J[r][b], h);
-                acc[k++] += h;
-            }
-        }
-#pragma unroll
-        for (int a = 0; a < 7; ++a) {
-            float g = 0.f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) g = fmaf(J[r][a] * w[r], res[r], g);
-            acc[28 + a] += g;
-        }
-        acc[35] += huber_cost(a_ray, A.huber) + huber_cost(a_dist, A.huber);
-        acc[36] += 1.f;
+        accumulate_match(T, A.Xf[3 * m], A.Xf[3 * m + 1], A.Xf[3 * m + 2], A.Xk[3 * n], A.Xk[3 * n + 1],
+                         A.Xk[3 * n + 2], q, A.rw, acc);
     }
 
     // Block partial: wave butterflies, then the four waves through LDS.
@@ -266,38 +156,15 @@ __global__ void __launch_bounds__(kThreads) track_iter_kernel(TrackArgs A, int m
         for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
         A.partials[(size_t)blockIdx.x * kStride + threadIdx.x] = v;
     }
+}
 
-    // Ticket: the last block to finish owns the reduction and the solve.
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int t = __hip_atomic_fetch_add(A.counter, 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = t == (int)gridDim.x - 1;
-    }
-    __syncthreads();
-    if (!last) return;
-    __threadfence();
-
-    // Fixed-order fp64 sum of the block partials: chunk c takes blocks
-    // c, c + kChunks, ...; the chunks are then added in order.
-    const int vi = threadIdx.x % kStride, ch = threadIdx.x / kStride;
-    if (ch < kChunks) {
-        double s = 0.0;
-        if (vi < kVals) {
-            for (int b = ch; b < (int)gridDim.x; b += kChunks)
-                s += (double)__builtin_nontemporal_load(&A.partials[(size_t)b * kStride + vi]);
-        }
-        dsum[ch][vi] = s;
-    }
-    __syncthreads();
+// One workgroup: fixed-order fp64 sum of the nb partials; mode 0 solves and
+// updates the pose, mode 1 writes the outputs at the final pose.
+__global__ void __launch_bounds__(kThreads) track_solve_kernel(TrackArgs A, int nb, int mode) {
+    __shared__ double tree[kVals * kThreads];
+    __shared__ double sum[kVals];
+    sum_partials<kThreads>(A.partials, nb, kStride, tree, sum);
     if (threadIdx.x != 0) return;
-    double sum[kVals];
-    for (int i = 0; i < kVals; ++i) {
-        double s = 0.0;
-        for (int c = 0; c < kChunks; ++c) s += dsum[c][i];
-        sum[i] = s;
-    }
-    A.counter[0] = 0;  // ready for the next launch on the stream
     if (mode == 0) {
         double step;
         if (solve_and_update(sum, A.T64, &step)) {
@@ -372,7 +239,7 @@ __global__ void __launch_bounds__(256) fuse_kernel(int N, int first, const float
 }  // namespace
 
 int track_blocks(int N) {
-    const int nb = (N + kThreads * 4 - 1) / (kThreads * 4);
+    const int nb = (N + kThreads - 1) / kThreads;
     return nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb);
 }
 
@@ -387,11 +254,7 @@ hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* 
     A.Xk = Xk; A.Xf = Xf; A.idx = idx; A.valid = valid; A.Qf = Qf; A.Qk = Qk;
     A.q_min = (double)q_min;
     // An infinite sigma drops its residual from the system and the cost.
-    A.w_ray = isinf(sigma_ray) ? 0.f : 1.f / (sigma_ray * sigma_ray);
-    A.w_dist = isinf(sigma_dist) ? 0.f : 1.f / (sigma_dist * sigma_dist);
-    A.is_ray = isinf(sigma_ray) ? 0.f : 1.f / sigma_ray;
-    A.is_dist = isinf(sigma_dist) ? 0.f : 1.f / sigma_dist;
-    A.huber = huber;
+    A.rw = robust_weights(sigma_ray, sigma_dist, huber);
     A.T64 = reinterpret_cast<double*>(w + kOffT);
     A.stat = reinterpret_cast<double*>(w + kOffStat);
     A.counter = reinterpret_cast<int32_t*>(w + kOffCnt);
@@ -400,10 +263,15 @@ hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* 
     A.T_out = T;
     A.info = info;
     const int nb = track_blocks(N);
-    timer_begin("track", s);
     track_init_kernel<<<1, 64, 0, s>>>(T, A.T64, A.counter, A.stat);
-    for (int it = 0; it <= iters; ++it) track_iter_kernel<<<nb, kThreads, 0, s>>>(A, it < iters ? 0 : 1);
-    timer_end(s);
+    for (int it = 0; it <= iters; ++it) {
+        timer_begin("track_accum", s);
+        track_accum_kernel<<<nb, kThreads, 0, s>>>(A);
+        timer_end(s);
+        timer_begin("track_solve", s);
+        track_solve_kernel<<<1, kThreads, 0, s>>>(A, nb, it < iters ? 0 : 1);
+        timer_end(s);
+    }
     return hipGetLastError();
 }
 
@@ -412,10 +280,12 @@ hipError_t launch_fuse(int N, const float* T, float* Xc, float* Cc, const float*
     const bool vec = al16(Xc) && al16(Cc) && al16(X) && al16(C);
     const int quads = vec ? N / 4 : 0;
     const int tail = N - 4 * quads;
-    timer_begin("fuse", s);
-    if (quads > 0) fuse_kernel<4><<<(quads + 255) / 256, 256, 0, s>>>(N, 0, T, Xc, Cc, X, C);
+    if (quads > 0) {
+        timer_begin("fuse", s);
+        fuse_kernel<4><<<(quads + 255) / 256, 256, 0, s>>>(N, 0, T, Xc, Cc, X, C);
+        timer_end(s);
+    }
     if (tail > 0) fuse_kernel<1><<<(tail + 255) / 256, 256, 0, s>>>(N, 4 * quads, T, Xc, Cc, X, C);
-    timer_end(s);
     return hipGetLastError();
 }
 

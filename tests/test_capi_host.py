@@ -271,3 +271,73 @@ def test_fuse_validation(lib):
     assert lib.m3s_fuse_pointmap(ctypes.byref(_lib.FuseProblem(4, 4, _addr, _addr, _addr + 2, _addr)), _addr, None) == 3
     assert lib.m3s_fuse_pointmap(ctypes.byref(ok), _addr + 1, None) == 3
     assert lib.m3s_last_error()
+
+
+def test_backend_struct_layout(tmp_path):
+    prog = tmp_path / "blayout.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "m3s.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(m3s_backend_params), sizeof(m3s_backend_problem),
+         offsetof(m3s_backend_params, step_tol), offsetof(m3s_backend_problem, Xc), offsetof(m3s_backend_problem, valid));
+  return 0;
+}''')
+    exe = tmp_path / "blayout"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(_lib.BackendParams), ctypes.sizeof(_lib.BackendProblem),
+                    _lib.BackendParams.step_tol.offset, _lib.BackendProblem.Xc.offset, _lib.BackendProblem.valid.offset]
+
+
+def test_backend_workspace(lib):
+    p = _lib.default_backend_params(lib)
+    assert p.iters == 10 and p.step_tol == 0.0 and abs(p.sigma_ray - 0.003) < 1e-9
+    n = 7 * 31
+    assert lib.m3s_backend_workspace_bytes(32, 384, 512, 64) >= n * n * 8 + 64 * 192 * 40 * 4
+    assert lib.m3s_backend_workspace_bytes(32, 384, 512, 64) % 256 == 0
+    assert lib.m3s_backend_workspace_bytes(1, 384, 512, 64) == 0
+    assert lib.m3s_backend_workspace_bytes(129, 384, 512, 64) == 0
+    assert lib.m3s_backend_workspace_bytes(4, 384, 512, 0) == 0
+
+
+def _backend_prob(N=3, H=4, W=4, E=2, **kw):
+    args = dict(Xc=_addr, Q=_addr, edges=_addr, idx=_addr, valid=_addr)
+    args.update(kw)
+    return _lib.BackendProblem(N, H, W, E, args["Xc"], args["Q"], args["edges"], args["idx"], args["valid"])
+
+
+@pytest.mark.parametrize("case,expect", [
+    (dict(prob=None), 1),
+    (dict(prob=dict(H=1)), 2),
+    (dict(prob=dict(N=1)), 2),
+    (dict(prob=dict(N=129)), 2),
+    (dict(prob=dict(E=0)), 2),
+    (dict(prob=dict(E=65536)), 2),
+    (dict(prob=dict(edges=0)), 1),
+    (dict(prob=dict(valid=0)), 1),
+    (dict(T=0), 1),
+    (dict(prob=dict(idx=_addr + 2)), 3),
+    (dict(prm=dict(iters=-1)), 3),
+    (dict(prm=dict(step_tol=-1.0)), 3),
+    (dict(prm=dict(step_tol=float("nan"))), 3),
+    (dict(prm=dict(sigma_dist=0.0)), 3),
+    (dict(prm=dict(huber=float("nan"))), 3),
+    (dict(ws=0), 4),
+    (dict(ws="misaligned"), 4),
+    (dict(ws="small"), 4),
+])
+def test_backend_validation(lib, case, expect):
+    prob = None if case.get("prob", {}) is None else _backend_prob(**case.get("prob", {}))
+    prm = _lib.default_backend_params(lib, **case.get("prm", {}))
+    need = lib.m3s_backend_workspace_bytes(3, 4, 4, 2)
+    big = (ctypes.c_char * (need + 512))()
+    base = (ctypes.addressof(big) + 255) // 256 * 256
+    ws, nbytes = {"none": (0, 0), 0: (0, 0), "misaligned": (base + 4, need), "small": (base, need - 1)}[
+        case.get("ws", "none")]
+    T = case.get("T", _addr)
+    st = lib.m3s_backend_gn(ctypes.byref(prob) if prob is not None else None, ctypes.byref(prm), T, 0, ws, nbytes,
+                            None)
+    assert st == expect, (st, lib.m3s_last_error())
+    assert lib.m3s_last_error()
