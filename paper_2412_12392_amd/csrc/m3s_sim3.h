@@ -16,7 +16,7 @@ namespace m3s {
 // J^T W J (28, rows of 7, 6, ..., 1), J^T W r (7), robust cost, match count.
 constexpr int kPoseVals = 28 + 7 + 2;
 
-__device__ __forceinline__ int upper_index(int a, int b) { return a * 7 - a * (a - 1) / 2 + (b - a); }
+__device__ __forceinline__ constexpr int upper_index(int a, int b) { return a * 7 - a * (a - 1) / 2 + (b - a); }
 
 // Huber weight and cost of a whitened norm a with the given width.
 __device__ __forceinline__ float huber_weight(float a, float width) { return a <= width ? 1.f : width / a; }
@@ -41,12 +41,20 @@ inline RobustWeights robust_weights(float sigma_ray, float sigma_dist, float hub
 }
 
 // One match: x = T X (X the point that moves with the pose), Y the measured
-// point, q its confidence.  Ray residual psi(x) - psi(Y) and distance residual
-// |x| - |Y| (Sec. 3.3), Jacobians w.r.t. a left perturbation of T (Supp. A:
-// [N(x), -[x]_x / |x|, 0] and [x^T / |x|, 0, |x|]), weights q / sigma^2 times
-// the Huber weight of the whitened block norm |r| sqrt(q) / sigma.  Adds to
-// acc and returns true, or returns false for a point at the origin or
-// non-finite.
+// point, q its confidence.  Ray residual e = psi(x) - psi(Y) and distance
+// residual rd = |x| - |Y| (Sec. 3.3); their Jacobians w.r.t. a left
+// perturbation of T (Supp. A) are J_ray = [P/d, -[x]_x/d, 0] and
+// J_dist = [u^T, 0, d] with d = |x|, u = x/d and the projector P = I - u u^T;
+// weights wr = q/sigma_ray^2 and wd = q/sigma_dist^2, each times the Huber
+// weight of its whitened block norm |r| sqrt(q)/sigma.  Since P^T P = P,
+// P [x]_x = [x]_x and [x]_x^T [x]_x = d^2 P, the weighted normal equations
+// have the closed form (ar = wr/d^2)
+//   H_vv = ar I + (wd - ar) u u^T   H_vw = -ar [x]_x   H_vs = wd d u
+//   H_ww = wr P                     H_ws = 0           H_ss = wd d^2
+//   g_v  = wr P e / d + wd rd u     g_w = wr u x e     g_s  = wd rd d
+// which is what is added to acc (upper triangle of H by rows, then g, the
+// robust cost and the count).  Returns false, adding nothing, for a point at
+// the origin or non-finite.
 __device__ __forceinline__ bool accumulate_match(const float* T, float X0, float X1, float X2, float Y0, float Y1,
                                                  float Y2, float q, const RobustWeights& rw, float* acc) {
     const float x0 = T[0] * X0 + T[1] * X1 + T[2] * X2 + T[3];
@@ -55,47 +63,53 @@ __device__ __forceinline__ bool accumulate_match(const float* T, float X0, float
     const float d = sqrtf(x0 * x0 + x1 * x1 + x2 * x2);
     const float dy = sqrtf(Y0 * Y0 + Y1 * Y1 + Y2 * Y2);
     if (!(d > 0.f) || !(dy > 0.f) || !isfinite(d) || !isfinite(dy)) return false;
-    const float id = 1.f / d, idy = 1.f / dy;
-    const float u[3] = {x0 * id, x1 * id, x2 * id};
-    const float x[3] = {x0, x1, x2};
-    const float res[4] = {u[0] - Y0 * idy, u[1] - Y1 * idy, u[2] - Y2 * idy, d - dy};
-    float J[4][7];
-#pragma unroll
-    for (int r = 0; r < 3; ++r) {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) J[r][c] = ((r == c ? 1.f : 0.f) - u[r] * u[c]) * id;
-        J[r][6] = 0.f;
-    }
-    // -[x]_x / d
-    J[0][3] = 0.f;         J[0][4] = x[2] * id;   J[0][5] = -x[1] * id;
-    J[1][3] = -x[2] * id;  J[1][4] = 0.f;         J[1][5] = x[0] * id;
-    J[2][3] = x[1] * id;   J[2][4] = -x[0] * id;  J[2][5] = 0.f;
-    J[3][0] = u[0]; J[3][1] = u[1]; J[3][2] = u[2];
-    J[3][3] = 0.f;  J[3][4] = 0.f;  J[3][5] = 0.f;  J[3][6] = d;
+    const float id = __builtin_amdgcn_rcpf(d), idy = __builtin_amdgcn_rcpf(dy);
+    const float u0 = x0 * id, u1 = x1 * id, u2 = x2 * id;
+    const float e0 = u0 - Y0 * idy, e1 = u1 - Y1 * idy, e2 = u2 - Y2 * idy, rd = d - dy;
     const float sq = sqrtf(q);
-    const float a_ray = sqrtf(res[0] * res[0] + res[1] * res[1] + res[2] * res[2]) * sq * rw.is_ray;
-    const float a_dist = fabsf(res[3]) * sq * rw.is_dist;
-    const float wr = q * rw.w_ray * huber_weight(a_ray, rw.huber);
-    const float wd = q * rw.w_dist * huber_weight(a_dist, rw.huber);
-    const float w[4] = {wr, wr, wr, wd};
-    int k = 0;
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-#pragma unroll
-        for (int b = a; b < 7; ++b) {
-            float h = 0.f;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) h = fmaf(J[r][a] * w[r], J[r][b], h);
-            acc[k++] += h;
-        }
-    }
-#pragma unroll
-    for (int a = 0; a < 7; ++a) {
-        float g = 0.f;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) g = fmaf(J[r][a] * w[r], res[r], g);
-        acc[28 + a] += g;
-    }
+    const float a_ray = sqrtf(e0 * e0 + e1 * e1 + e2 * e2) * sq * rw.is_ray;
+    const float a_dist = fabsf(rd) * sq * rw.is_dist;
+    const float hr = a_ray <= rw.huber ? 1.f : rw.huber * __builtin_amdgcn_rcpf(a_ray);
+    const float hd = a_dist <= rw.huber ? 1.f : rw.huber * __builtin_amdgcn_rcpf(a_dist);
+    const float wr = q * rw.w_ray * hr;
+    const float wd = q * rw.w_dist * hd;
+    const float ar = wr * id * id;
+    const float cv = wd - ar;
+    const float wdd = wd * d;
+    // H_vv, H_vw, H_vs (rows 0..2)
+    acc[upper_index(0, 0)] += ar + cv * u0 * u0;
+    acc[upper_index(0, 1)] += cv * u0 * u1;
+    acc[upper_index(0, 2)] += cv * u0 * u2;
+    acc[upper_index(0, 4)] += ar * x2;
+    acc[upper_index(0, 5)] -= ar * x1;
+    acc[upper_index(0, 6)] += wdd * u0;
+    acc[upper_index(1, 1)] += ar + cv * u1 * u1;
+    acc[upper_index(1, 2)] += cv * u1 * u2;
+    acc[upper_index(1, 3)] -= ar * x2;
+    acc[upper_index(1, 5)] += ar * x0;
+    acc[upper_index(1, 6)] += wdd * u1;
+    acc[upper_index(2, 2)] += ar + cv * u2 * u2;
+    acc[upper_index(2, 3)] += ar * x1;
+    acc[upper_index(2, 4)] -= ar * x0;
+    acc[upper_index(2, 6)] += wdd * u2;
+    // H_ww (rows 3..5), H_ss
+    acc[upper_index(3, 3)] += wr - wr * u0 * u0;
+    acc[upper_index(3, 4)] -= wr * u0 * u1;
+    acc[upper_index(3, 5)] -= wr * u0 * u2;
+    acc[upper_index(4, 4)] += wr - wr * u1 * u1;
+    acc[upper_index(4, 5)] -= wr * u1 * u2;
+    acc[upper_index(5, 5)] += wr - wr * u2 * u2;
+    acc[upper_index(6, 6)] += wdd * d;
+    // g
+    const float ue = u0 * e0 + u1 * e1 + u2 * e2;
+    const float wri = wr * id, wdr = wd * rd;
+    acc[28] += wri * (e0 - u0 * ue) + wdr * u0;
+    acc[29] += wri * (e1 - u1 * ue) + wdr * u1;
+    acc[30] += wri * (e2 - u2 * ue) + wdr * u2;
+    acc[31] += wr * (u1 * e2 - u2 * e1);
+    acc[32] += wr * (u2 * e0 - u0 * e2);
+    acc[33] += wr * (u0 * e1 - u1 * e0);
+    acc[34] += wdr * d;
     acc[35] += huber_cost(a_ray, rw.huber) + huber_cost(a_dist, rw.huber);
     acc[36] += 1.f;
     return true;
