@@ -465,14 +465,17 @@ def backend_leg(m3s, lib, dev, args):
     sol_ms, _ = _timer(lib, "backend_solve")
     E = len(bp.edges)
     matches = E * H * W
-    alg = POSE_BYTES_PER_MATCH * matches
+    # Bytes an iteration has to read at least: every edge's idx and valid, and
+    # every keyframe's points and confidences once (keyframes are shared by
+    # several edges).
+    alg = E * H * W * (4 + 1) + N * H * W * (12 + 4)
     out = {"workload": "%d keyframes 512x384, %d edges (neighbours both ways + loop closures), 10 Gauss-Newton "
                        "iterations, noise 1e-3, 5%% outliers" % (N, E),
            "ms_per_solve": round(el * 1e3, 4),
            "match_evaluations_per_s": round(matches * (prm.iters + 1) / el, 1),
            "accum_avg_us": round(acc_ms * 1e3, 2), "edge_avg_us": round(edg_ms * 1e3, 2),
            "solve_avg_us": round(sol_ms * 1e3, 2),
-           "accum_algorithmic_bytes": alg,
+           "accum_algorithmic_bytes": alg, "accum_match_bytes": POSE_BYTES_PER_MATCH * matches,
            "accum_algorithmic_GBs": round(alg / (acc_ms * 1e-3) / 1e9, 1),
            "accum_frac_of_hbm_peak": round(alg / (acc_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     log("backend:", out)
