@@ -58,6 +58,7 @@ struct BackendArgs {
     const int32_t* idx;       // [E*HW]
     const uint8_t* valid;     // [E*HW]
     double q_min;
+    float q_minf;
     RobustWeights rw;
     double step_tol;
     double* T64;              // [N*12] world poses
@@ -74,6 +75,7 @@ struct BackendArgs {
 };
 
 constexpr int kBlk = 56;      // 49 + 7 doubles per edge
+constexpr int kMatchesPerLane = 16;  // amortises the workgroup reduction of the 37 sums
 constexpr int kTile = 32;     // tile of the blocked Cholesky
 constexpr int kPanelRows = 416;  // panel rows kept in LDS (larger systems read the panel from memory)
 constexpr int kStageRows = 64;   // raw panel rows staged per step of the panel product
@@ -122,15 +124,21 @@ __global__ void __launch_bounds__(kThreads) backend_accum_kernel(BackendArgs A, 
     const float* Xj = A.Xc + (long)(edge_ok ? ej : 0) * A.HW * 3;
     const float* Qi = A.Q + (long)(edge_ok ? ei : 0) * A.HW;
     const float* Qj = A.Q + (long)(edge_ok ? ej : 0) * A.HW;
-    const int stride = A.blocks_per_edge * kThreads;
-    for (int n = edge_ok ? blockIdx.x * kThreads + threadIdx.x : A.HW; n < A.HW; n += stride) {
+    // Workgroups are dealt to the 8 XCDs round-robin (b % 8 with the edge's
+    // workgroups consecutive); chunk c(b) gives XCD j the j-th contiguous
+    // eighth of the chunks, so each XCD's L2 sees one slice of every keyframe
+    // and the edges that share a keyframe reuse it there.
+    const int bpe = A.blocks_per_edge;
+    const int chunk = (bpe % 8 == 0) ? (int)(blockIdx.x % 8) * (bpe / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
+    const int stride = bpe * kThreads;
+    for (int n = edge_ok ? chunk * kThreads + threadIdx.x : A.HW; n < A.HW; n += stride) {
         if (!A.valid[ebase + n]) continue;
         const int m = A.idx[ebase + n];
         if (m < 0 || m >= A.HW) continue;
-        const double q64 = sqrt((double)Qi[m] * (double)Qj[n]);
-        if (!(q64 > A.q_min)) continue;
-        accumulate_match(T, Xj[3 * n], Xj[3 * n + 1], Xj[3 * n + 2], Xi[3 * m], Xi[3 * m + 1], Xi[3 * m + 2],
-                         (float)q64, A.rw, acc);
+        float q;
+        if (!confidence_gate(Qi[m], Qj[n], A.q_min, A.q_minf, q)) continue;
+        accumulate_match(T, Xj[3 * n], Xj[3 * n + 1], Xj[3 * n + 2], Xi[3 * m], Xi[3 * m + 1], Xi[3 * m + 2], q,
+                         A.rw, acc);
     }
 
 #pragma unroll
@@ -488,7 +496,7 @@ BackendLayout backend_layout(int N, int HW, int E) {
 }  // namespace
 
 int backend_blocks_per_edge(int HW) {
-    const int b = (HW + kThreads * 4 - 1) / (kThreads * 4);
+    const int b = (HW + kThreads * kMatchesPerLane - 1) / (kThreads * kMatchesPerLane);
     return b < 1 ? 1 : (b > 1024 ? 1024 : b);
 }
 
@@ -506,6 +514,7 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
     A.np = padded_dim(N);
     A.Xc = Xc; A.Q = Q; A.edges = edges; A.idx = idx; A.valid = valid;
     A.q_min = (double)q_min;
+    A.q_minf = q_min;
     A.rw = robust_weights(sigma_ray, sigma_dist, huber);
     A.step_tol = step_tol;
     A.T64 = reinterpret_cast<double*>(w + L.T64);

@@ -40,6 +40,17 @@ inline RobustWeights robust_weights(float sigma_ray, float sigma_dist, float hub
     return w;
 }
 
+// Confidence gate of a match (Sec. 3.3): q = sqrt(Qa Qb) > q_min, decided
+// exactly as in fp64 (the product of two fp32 values is exact there).  The
+// fp32 root is within 2 ulp of the exact one, so outside a relative band of
+// 1e-5 around q_min its comparison gives the fp64 answer; inside the band the
+// fp64 root decides.  Writes the fp32 confidence to q.
+__device__ __forceinline__ bool confidence_gate(float Qa, float Qb, double q_min, float q_minf, float& q) {
+    q = sqrtf(Qa * Qb);
+    if (fabsf(q - q_minf) > 1e-5f * q_minf) return q > q_minf;
+    return sqrt((double)Qa * (double)Qb) > q_min;
+}
+
 // One match: x = T X (X the point that moves with the pose), Y the measured
 // point, q its confidence.  Ray residual e = psi(x) - psi(Y) and distance
 // residual rd = |x| - |Y| (Sec. 3.3); their Jacobians w.r.t. a left

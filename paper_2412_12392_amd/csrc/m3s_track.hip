@@ -54,6 +54,7 @@ struct TrackArgs {
     const float* Qf;
     const float* Qk;
     double q_min;
+    float q_minf;
     RobustWeights rw;
     double* T64;
     double* stat;
@@ -128,11 +129,8 @@ __global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
         if (!A.valid[n]) continue;
         const int m = A.idx[n];
         if (m < 0 || m >= A.N) continue;
-        // The confidence gate decides in fp64, from the exact product of the
-        // two fp32 confidences.
-        const double q64 = sqrt((double)A.Qf[m] * (double)A.Qk[n]);
-        if (!(q64 > A.q_min)) continue;
-        const float q = (float)q64;
+        float q;
+        if (!confidence_gate(A.Qf[m], A.Qk[n], A.q_min, A.q_minf, q)) continue;
         accumulate_match(T, A.Xf[3 * m], A.Xf[3 * m + 1], A.Xf[3 * m + 2], A.Xk[3 * n], A.Xk[3 * n + 1],
                          A.Xk[3 * n + 2], q, A.rw, acc);
     }
@@ -253,6 +251,7 @@ hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* 
     A.N = N;
     A.Xk = Xk; A.Xf = Xf; A.idx = idx; A.valid = valid; A.Qf = Qf; A.Qk = Qk;
     A.q_min = (double)q_min;
+    A.q_minf = q_min;
     // An infinite sigma drops its residual from the system and the cost.
     A.rw = robust_weights(sigma_ray, sigma_dist, huber);
     A.T64 = reinterpret_cast<double*>(w + kOffT);
