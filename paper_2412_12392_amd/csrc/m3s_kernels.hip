@@ -761,25 +761,21 @@ __device__ __forceinline__ float3 norm_jac_apply(float3 X, float3 v) {
     return f3((v.x - u.x * uv) * inv, (v.y - u.y * uv) * inv, (v.z - u.z * uv) * inv);
 }
 
-__global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __restrict__ Xii, const float* __restrict__ Xji,
-                                                  const float* __restrict__ p, const uint8_t* __restrict__ valid,
-                                                  const float* __restrict__ grad_p, const float* __restrict__ grad_xhat,
-                                                  float* __restrict__ dXii, float* __restrict__ dXji) {
-    long n = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= (long)H * W) return;
-    if (!valid[n]) {
-        dXji[3 * n] = 0.f; dXji[3 * n + 1] = 0.f; dXji[3 * n + 2] = 0.f;
-        return;
-    }
+// Adjoint of one valid query n: writes dXji[n] and returns the four corner
+// pixels of p* with the gradient each receives in dXii (zero weight: none).
+__device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict__ Xii, const float* __restrict__ Xji,
+                                          const float* __restrict__ p, const float* __restrict__ grad_p,
+                                          const float* __restrict__ grad_xhat, float* __restrict__ dXji, long n,
+                                          long cm[4], float3 gc[4], int& cx0, int& cy0) {
     float px = p[2 * n], py = p[2 * n + 1];
     int x0 = min(max((int)floorf(px), 0), W - 2), y0 = min(max((int)floorf(py), 0), H - 2);
     float a = px - (float)x0, b = py - (float)y0;
-    long cm[4] = {(long)y0 * W + x0, (long)y0 * W + x0 + 1, (long)(y0 + 1) * W + x0, (long)(y0 + 1) * W + x0 + 1};
+    const long cm_[4] = {(long)y0 * W + x0, (long)y0 * W + x0 + 1, (long)(y0 + 1) * W + x0, (long)(y0 + 1) * W + x0 + 1};
     float w[4] = {(1.f - a) * (1.f - b), a * (1.f - b), (1.f - a) * b, a * b};
     float3 X[4], R[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        X[c] = load_point(Xii, cm[c]);
+        X[c] = load_point(Xii, cm_[c]);
         R[c] = unit_ray(X[c]);
     }
     float3 r = f3(w[0] * R[0].x + w[1] * R[1].x + w[2] * R[2].x + w[3] * R[3].x,
@@ -840,17 +836,82 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     float irn = rsq(r.x * r.x + r.y * r.y + r.z * r.z);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        if (w[c] == 0.f) continue;
         float3 g = f3(w[c] * gx.x, w[c] * gx.y, w[c] * gx.z);
         bool has_ray = R[c].x != 0.f || R[c].y != 0.f || R[c].z != 0.f;
-        if (solve && has_ray) {
+        if (w[c] != 0.f && solve && has_ray) {
             float3 nv = norm_jac_apply(X[c], v);
             float s = w[c] * irn;
             g.x -= s * nv.x; g.y -= s * nv.y; g.z -= s * nv.z;
         }
-        unsafeAtomicAdd(dXii + 3 * cm[c] + 0, g.x);
-        unsafeAtomicAdd(dXii + 3 * cm[c] + 1, g.y);
-        unsafeAtomicAdd(dXii + 3 * cm[c] + 2, g.z);
+        cm[c] = w[c] == 0.f ? -1 : cm_[c];
+        gc[c] = g;
+    }
+    cx0 = x0;
+    cy0 = y0;
+}
+
+// Largest box of corner pixels a tile accumulates in LDS (12 B per pixel).
+constexpr int kBwdLdsPx = 1536;
+
+// One 16 x 16 tile of queries.  The tile's scatter into dXii is summed in an
+// LDS window covering every corner its queries touch (LDS float atomics) and
+// then added to global memory once per window entry, in row order; a tile
+// whose window exceeds kBwdLdsPx adds each corner to global memory directly.
+__global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __restrict__ Xii,
+                                                  const float* __restrict__ Xji, const float* __restrict__ p,
+                                                  const uint8_t* __restrict__ valid, const float* __restrict__ grad_p,
+                                                  const float* __restrict__ grad_xhat, float* __restrict__ dXii,
+                                                  float* __restrict__ dXji, int tiles_x) {
+    __shared__ float acc[3 * kBwdLdsPx];
+    __shared__ int box[4 * 4];
+    const int tid = threadIdx.x;
+    const int x = (blockIdx.x % tiles_x) * 16 + (tid & 15), y = (blockIdx.x / tiles_x) * 16 + (tid >> 4);
+    const bool inside = x < W && y < H;
+    const long n = (long)y * W + x;
+    long cm[4] = {-1, -1, -1, -1};
+    float3 gc[4];
+    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    if (inside) {
+        if (!valid[n]) {
+            dXji[3 * n] = 0.f; dXji[3 * n + 1] = 0.f; dXji[3 * n + 2] = 0.f;
+        } else {
+            int cx0, cy0;
+            bwd_query(H, W, Xii, Xji, p, grad_p, grad_xhat, dXji, n, cm, gc, cx0, cy0);
+            lx = cx0; hx = cx0 + 1; ly = cy0; hy = cy0 + 1;
+        }
+    }
+    block_box<256>(lx, hx, ly, hy, box);
+    const int bw = hx - lx + 1, bh = hy - ly + 1;
+    const bool any = hx >= lx;
+    if (any && bw * bh <= kBwdLdsPx) {
+        const int cnt = 3 * bw * bh;
+        for (int i = tid; i < cnt; i += 256) acc[i] = 0.f;
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (cm[c] < 0) continue;
+            const int cy = (int)(cm[c] / W), cx = (int)(cm[c] - (long)cy * W);
+            float* a = acc + 3 * ((cy - ly) * bw + (cx - lx));
+            atomicAdd(a, gc[c].x);
+            atomicAdd(a + 1, gc[c].y);
+            atomicAdd(a + 2, gc[c].z);
+        }
+        __syncthreads();
+        const uint32_t magic = div_magic(3 * bw);
+        for (int i = tid; i < cnt; i += 256) {
+            const float v = acc[i];
+            if (v == 0.f) continue;
+            const int row = (int)__umulhi((uint32_t)i, magic), col = i - row * 3 * bw;
+            unsafeAtomicAdd(dXii + 3 * ((long)(ly + row) * W + lx) + col, v);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            if (cm[c] < 0) continue;
+            unsafeAtomicAdd(dXii + 3 * cm[c] + 0, gc[c].x);
+            unsafeAtomicAdd(dXii + 3 * cm[c] + 1, gc[c].y);
+            unsafeAtomicAdd(dXii + 3 * cm[c] + 2, gc[c].z);
+        }
     }
 }
 
@@ -990,8 +1051,9 @@ hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const fl
     timer_begin("fill", s);
     fill_zero_kernel<<<min(blocks_for(3 * N, 256), 4096u), 256, 0, s>>>(dXii, 3 * N);
     timer_end(s);
+    const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
     timer_begin("bwd", s);
-    bwd_kernel<<<blocks_for(N, 256), 256, 0, s>>>(H, W, Xii, Xji, p, valid, grad_p, grad_xhat, dXii, dXji);
+    bwd_kernel<<<tiles_x * tiles_y, 256, 0, s>>>(H, W, Xii, Xji, p, valid, grad_p, grad_xhat, dXii, dXji, tiles_x);
     timer_end(s);
     return hipGetLastError();
 }
