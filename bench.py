@@ -409,6 +409,24 @@ def track_fuse_leg(m3s, lib, dev, args):
         step()
     torch.cuda.synchronize()
     lib.m3s_timing_enable(0)
+    # The same frame captured once into a graph and replayed.
+    g = torch.cuda.CUDAGraph()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(gs):
+        step()
+    torch.cuda.current_stream().wait_stream(gs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el_graph = (time.perf_counter() - t0) / steps
     ac_ms, _ = _timer(lib, "track_accum")
     so_ms, _ = _timer(lib, "track_solve")
     fu_ms, _ = _timer(lib, "fuse")
@@ -416,7 +434,7 @@ def track_fuse_leg(m3s, lib, dev, args):
     iters = prm.iters + 1
     out = {"workload": "512x384 keyframe: tracking pose solve (10 Gauss-Newton iterations + final cost) then "
                        "pointmap fusion; noise 1e-3, 5% outliers",
-           "ms_per_frame": round(el * 1e3, 4),
+           "ms_per_frame": round(el * 1e3, 4), "ms_per_frame_graph": round(el_graph * 1e3, 4),
            "track_accum_avg_us": round(ac_ms * 1e3, 2), "track_solve_avg_us": round(so_ms * 1e3, 2),
            "launch_pairs_per_frame": iters,
            "match_evaluations_per_s": round(n_match * iters / el, 1),
@@ -460,6 +478,23 @@ def backend_leg(m3s, lib, dev, args):
         step()
     torch.cuda.synchronize()
     lib.m3s_timing_enable(0)
+    g = torch.cuda.CUDAGraph()
+    gs = torch.cuda.Stream()
+    gs.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(gs):
+        step()
+    torch.cuda.current_stream().wait_stream(gs)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        step()
+    for _ in range(2):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    el_graph = (time.perf_counter() - t0) / steps
     acc_ms, _ = _timer(lib, "backend_accum")
     edg_ms, _ = _timer(lib, "backend_edge")
     sol_ms, _ = _timer(lib, "backend_solve")
@@ -471,7 +506,7 @@ def backend_leg(m3s, lib, dev, args):
     alg = E * H * W * (4 + 1) + N * H * W * (12 + 4)
     out = {"workload": "%d keyframes 512x384, %d edges (neighbours both ways + loop closures), 10 Gauss-Newton "
                        "iterations, noise 1e-3, 5%% outliers" % (N, E),
-           "ms_per_solve": round(el * 1e3, 4),
+           "ms_per_solve": round(el * 1e3, 4), "ms_per_solve_graph": round(el_graph * 1e3, 4),
            "match_evaluations_per_s": round(matches * (prm.iters + 1) / el, 1),
            "accum_avg_us": round(acc_ms * 1e3, 2), "edge_avg_us": round(edg_ms * 1e3, 2),
            "solve_avg_us": round(sol_ms * 1e3, 2),
