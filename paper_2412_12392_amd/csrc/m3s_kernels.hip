@@ -539,21 +539,20 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     const float eps32 = kU32x24 * qn * dnorm;
     const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
 
-    // Pass 1: fp16 scores; seed the running maximum with the window centre.
+    // Pass 1: fp16 scores in row-major window order over the part of the
+    // window inside the image; the running maximum is seeded with the window
+    // centre (v_med3 against +inf is the maximum of two non-NaN scores).
     const uint4* c0 = sd + (my0 - ry0) * rw + (mx0 - rx0);
     float run = dot16(q16, c0[0], c0[kRegionPx16], c0[2 * kRegionPx16]);
     uint64_t mask0 = 0, mask1 = 0;
-    int k = 0;
-    for (int dy = -r; dy <= r; ++dy) {
-        int my = my0 + dy;
-        const bool row_in = my >= 0 && my < H;
-        const int row = (my - ry0) * rw - rx0;
-        for (int dx = -r; dx <= r; ++dx, ++k) {
-            int mx = mx0 + dx;
-            if (!row_in || mx < 0 || mx >= W) continue;
-            const uint4* d = sd + row + mx;
-            float s16 = dot16(q16, d[0], d[kRegionPx16], d[2 * kRegionPx16]);
-            run = fmaxf(run, s16);
+    const int x_lo = max(mx0 - r, 0), x_hi = min(mx0 + r, W - 1);
+    const int y_lo = max(my0 - r, 0), y_hi = min(my0 + r, H - 1);
+    for (int my = y_lo; my <= y_hi; ++my) {
+        const uint4* d = sd + (my - ry0) * rw - rx0;
+        int k = (my - my0 + r) * side + (x_lo - mx0 + r);
+        for (int mx = x_lo; mx <= x_hi; ++mx, ++k) {
+            const float s16 = dot16(q16, d[mx], d[mx + kRegionPx16], d[mx + 2 * kRegionPx16]);
+            run = __builtin_amdgcn_fmed3f(s16, run, INFINITY);
             if (s16 >= run - tau) {
                 if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
             }
