@@ -77,6 +77,10 @@ CASES = [
     ("least_squares", (4, 24, 32, 6), dict(noise=1e-3, loops=1), dict(huber=float("inf"))),
     ("full_512x384", (4, 384, 512, 7), dict(noise=1e-3, outlier_frac=0.05, scramble=False, loops=1),
      dict(iters=3)),
+    # Reduced systems larger than the LDS panel (the factorisation reads the panel from memory),
+    # up to the largest keyframe count.
+    ("long_chain_80", (80, 8, 12, 11), dict(loops=4), dict(iters=5)),
+    ("max_keyframes_128", (128, 6, 8, 12), dict(loops=2), dict(iters=4)),
 ]
 
 
