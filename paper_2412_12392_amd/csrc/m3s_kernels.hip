@@ -469,6 +469,7 @@ constexpr float kF16Max = 60000.f;        // larger magnitudes fall back to the 
 constexpr float kU16 = 4.8828125e-4f;     // 2^-11
 constexpr float kU32x24 = 1.4305115e-6f;  // 24 * 2^-24
 constexpr float kFlush16 = 6.1035156e-5f; // 2^-14
+constexpr float kSqrt24Up = 4.8989797f;   // sqrt(24) rounded up
 
 struct TileLds16 {
     union {
@@ -476,7 +477,7 @@ struct TileLds16 {
         float4 rays[3 * kRegionPx16];      // LM ray window (records of up to kRegionPx16 pixels)
     };
     int box[4 * 16];
-    float stat[3 * 16];                   // per wave: max partial |d|^2, max partial |d|_1, max |d_k|
+    float stat[16];                       // per wave: max over 8-float chunks of the chunk's |d|^2
 };
 
 __device__ __forceinline__ uint32_t pack_h2(float a, float b) {
@@ -516,6 +517,41 @@ __device__ __forceinline__ float exact24(const float* __restrict__ q, const floa
     return acc;
 }
 
+// Pass 1 over a window that lies inside the image, for a radius R fixed at
+// compile time: the candidates of a row are unrolled (LDS addresses are the
+// row base plus immediate offsets) and their survivor bits are shifted into a
+// 128-bit word hi:lo, leaving candidate j of the window on bit N - 1 - j; a
+// bit reversal then gives the row-major masks of the generic pass (candidate
+// j on bit j).  w: LDS record of the window's top-left candidate.
+template <int R>
+__device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* __restrict__ w, int rw, float tau,
+                                              float& run, uint64_t& mask0, uint64_t& mask1) {
+    constexpr int S = 2 * R + 1, N = S * S;
+    static_assert(N <= 128 && S < 32, "mask width");
+    uint64_t lo = 0, hi = 0;
+#pragma unroll 1
+    for (int dy = 0; dy < S; ++dy, w += rw) {
+        uint32_t rb = 0;
+#pragma unroll
+        for (int dx = 0; dx < S; ++dx) {
+            const float s16 = dot16(q16, w[dx], w[dx + kRegionPx16], w[dx + 2 * kRegionPx16]);
+            run = fmaxf(run, s16);
+            rb = rb + rb + (s16 >= run - tau ? 1u : 0u);
+        }
+        hi = (hi << S) | (lo >> (64 - S));
+        lo = (lo << S) | rb;
+    }
+    const uint64_t rhi = __builtin_bitreverse64(lo), rlo = __builtin_bitreverse64(hi);
+    constexpr int sh = 128 - N;  // forward mask = (rhi:rlo) >> sh
+    if constexpr (sh >= 64) {
+        mask0 = rhi >> (sh - 64);
+        mask1 = 0;
+    } else {
+        mask0 = (rlo >> sh) | (rhi << (64 - sh));
+        mask1 = rhi >> sh;
+    }
+}
+
 // dnorm: bound on |d| over the region, dl1: bound on |d|_1.
 __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QState& q, const uint4* __restrict__ sd,
                                            int rx0, int ry0, int rw, float dnorm, float dl1) {
@@ -547,14 +583,27 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     uint64_t mask0 = 0, mask1 = 0;
     const int x_lo = max(mx0 - r, 0), x_hi = min(mx0 + r, W - 1);
     const int y_lo = max(my0 - r, 0), y_hi = min(my0 + r, H - 1);
-    for (int my = y_lo; my <= y_hi; ++my) {
-        const uint4* d = sd + (my - ry0) * rw - rx0;
-        int k = (my - my0 + r) * side + (x_lo - mx0 + r);
-        for (int mx = x_lo; mx <= x_hi; ++mx, ++k) {
-            const float s16 = dot16(q16, d[mx], d[mx + kRegionPx16], d[mx + 2 * kRegionPx16]);
-            run = __builtin_amdgcn_fmed3f(s16, run, INFINITY);
-            if (s16 >= run - tau) {
-                if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
+    // Wave-uniform choice: the unrolled scan when every active lane's window
+    // is whole (then x_lo = mx0 - r etc.), the bounded loop otherwise.
+    const bool whole = x_lo == mx0 - r && x_hi == mx0 + r && y_lo == my0 - r && y_hi == my0 + r;
+    const uint4* w = sd + (y_lo - ry0) * rw + (x_lo - rx0);
+    const bool all_whole = __all(whole) != 0;
+    if (all_whole && r == 3) {
+        scan16_inside<3>(q16, w, rw, tau, run, mask0, mask1);
+    } else if (all_whole && r == 2) {
+        scan16_inside<2>(q16, w, rw, tau, run, mask0, mask1);
+    } else if (all_whole && r == 4) {
+        scan16_inside<4>(q16, w, rw, tau, run, mask0, mask1);
+    } else {
+        for (int my = y_lo; my <= y_hi; ++my) {
+            const uint4* d = sd + (my - ry0) * rw - rx0;
+            int k = (my - my0 + r) * side + (x_lo - mx0 + r);
+            for (int mx = x_lo; mx <= x_hi; ++mx, ++k) {
+                const float s16 = dot16(q16, d[mx], d[mx + kRegionPx16], d[mx + 2 * kRegionPx16]);
+                run = __builtin_amdgcn_fmed3f(s16, run, INFINITY);
+                if (s16 >= run - tau) {
+                    if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
+                }
             }
         }
     }
@@ -596,7 +645,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
     bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
-    float pn2 = 0.f, pl1 = 0.f, pmax = 0.f;
+    float pn2 = 0.f;
     if (use16) {
         // Stage: chunk c is pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7),
         // in batches of kBatch chunks per thread whose loads are all issued
@@ -625,37 +674,30 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
                     const int pix = c / 3, k = c - 3 * (c / 3);
                     const float4 u = lu[i], v = lv[i];
                     float e2 = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w + v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
-                    float e1 = fabsf(u.x) + fabsf(u.y) + fabsf(u.z) + fabsf(u.w) + fabsf(v.x) + fabsf(v.y) + fabsf(v.z) + fabsf(v.w);
-                    float em = fmaxf(fmaxf(fmaxf(fabsf(u.x), fabsf(u.y)), fmaxf(fabsf(u.z), fabsf(u.w))),
-                                     fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
-                    // NaN propagates through the sums and fails the range test below.
+                    // A NaN or infinite element, or squares that overflow, make e2
+                    // non-finite and fail the range test below.
                     pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
-                    pl1 = fmaxf(pl1, isfinite(e1) ? e1 : INFINITY);
-                    pmax = fmaxf(pmax, (em == em) ? em : INFINITY);
                     S.desc[k * kRegionPx16 + pix] =
                         make_uint4(pack_h2(u.x, u.y), pack_h2(u.z, u.w), pack_h2(v.x, v.y), pack_h2(v.z, v.w));
                 }
             }
         }
     }
-    // Region bounds: |d|^2 <= 3 max partial, |d|_1 <= 3 max partial.
+    // Region bounds from the largest chunk: |d|^2 <= 3 pn2, every element
+    // |d_k| <= sqrt(pn2) (so pn2 <= kF16Max^2 keeps the conversion finite), and
+    // |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
-        pl1 = fmaxf(pl1, __shfl_xor(pl1, o, 64));
-        pmax = fmaxf(pmax, __shfl_xor(pmax, o, 64));
-    }
-    if ((tid & 63) == 0) { S.stat[3 * wv] = pn2; S.stat[3 * wv + 1] = pl1; S.stat[3 * wv + 2] = pmax; }
+    for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
+    if ((tid & 63) == 0) S.stat[wv] = pn2;
     __syncthreads();
-    pn2 = S.stat[0]; pl1 = S.stat[1]; pmax = S.stat[2];
+    pn2 = S.stat[0];
 #pragma unroll
-    for (int w = 1; w < NT / 64; ++w) {
-        pn2 = fmaxf(pn2, S.stat[3 * w]); pl1 = fmaxf(pl1, S.stat[3 * w + 1]); pmax = fmaxf(pmax, S.stat[3 * w + 2]);
-    }
-    use16 = use16 && pmax <= kF16Max && isfinite(pn2) && isfinite(pl1);
+    for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
+    use16 = use16 && pn2 <= kF16Max * kF16Max;
     if (q.good) {
         const long n = (long)y * W + x;
-        long bi = use16 ? refine_f16(A, n, q, S.desc, lx, ly, rw, sqrtf(3.f * pn2) * 1.0001f, 3.f * pl1 * 1.0001f)
+        const float dnorm = sqrtf(3.f * pn2) * 1.0001f;
+        long bi = use16 ? refine_f16(A, n, q, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
                         : refine_global<24>(A, n, q);
         finish(A, n, q, bi);
     }
