@@ -213,7 +213,7 @@ m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, i
         A.tile_begin = (int32_t)tiles;
         tiles += (int64_t)A.tiles_x * A.tiles_y;
         plan->prep_begin.push_back((int32_t)prep);
-        prep += ((int64_t)E.in.H * E.in.W + 255) / 256;
+        prep += m3s::prep_tiles(E.in.H, E.in.W);
         if (tiles > INT32_MAX / 2 || prep > INT32_MAX / 2) return fail(M3S_ERR_SHAPE, "batch too large");
         if (!desc_in_regs(&E.in)) plan->desc_regs = false;
         plan->table.push_back(A);

@@ -23,6 +23,11 @@ bool tile_uses_lds(int tile_config);
 void timer_begin(const char* name, hipStream_t s);
 void timer_end(hipStream_t s);
 
+// Ray-record prep: one workgroup of 256 lanes per kPrepTX x kPrepTY pixels.
+constexpr int kPrepTX = 64, kPrepTY = 4;
+inline int64_t prep_tiles(int H, int W) {
+    return (int64_t)((W + kPrepTX - 1) / kPrepTX) * (int64_t)((H + kPrepTY - 1) / kPrepTY);
+}
 hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s);
 hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool xcd_remap, hipStream_t s);
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,

@@ -26,29 +26,73 @@ namespace m3s {
 
 // ---------------------------------------------------------------- prep
 
-__device__ __forceinline__ void prep_pixel(const float* __restrict__ X, float4* __restrict__ rec,
-                                           int H, int W, int x, int y) {
-    int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
-    int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
-    long row = (long)y * W;
-    float3 r = unit_ray(load_point(X, row + x));
-    float3 rxm = unit_ray(load_point(X, row + xm));
-    float3 rxp = unit_ray(load_point(X, row + xp));
-    float3 rym = unit_ray(load_point(X, (long)ym * W + x));
-    float3 ryp = unit_ray(load_point(X, (long)yp * W + x));
-    float sx = 1.0f / (float)(xp - xm), sy = 1.0f / (float)(yp - ym);
-    float3 gx = f3((rxp.x - rxm.x) * sx, (rxp.y - rxm.y) * sx, (rxp.z - rxm.z) * sx);
-    float3 gy = f3((ryp.x - rym.x) * sy, (ryp.y - rym.y) * sy, (ryp.z - rym.z) * sy);
-    float4* o = rec + kRecF4 * (row + x);
-    o[0] = make_float4(r.x, r.y, r.z, gx.x);
-    o[1] = make_float4(gx.y, gx.z, gy.x, gy.y);
-    o[2] = make_float4(gy.z, 0.f, 0.f, 0.f);
+// Streaming 16-byte store (non-temporal hint: the line is not kept dirty in
+// this XCD's L2 for a later write-back).
+typedef float f4v_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store_nt(float4* p, float4 v) {
+    __builtin_nontemporal_store(__builtin_bit_cast(f4v_t, v), reinterpret_cast<f4v_t*>(p));
+}
+
+// One prep tile of kPrepTX x kPrepTY pixels per workgroup of 256 lanes.  The
+// tile and a one-pixel halo of X (edge-replicated, which gives the one-sided
+// differences at the image border) are read with coalesced loads, each
+// pixel's unit ray is computed once in LDS, and the records are written back
+// as contiguous float4s.  Same arithmetic per pixel as reading the five points
+// directly: r, rx-, rx+, ry-, ry+ and (r+ - r-) / (x+ - x-).
+struct PrepLds {
+    float ray[(kPrepTY + 2) * (kPrepTX + 2) * 3];
+    float4 rec[kPrepTY * kPrepTX * kRecF4];
+};
+
+__device__ __forceinline__ void prep_tile(const float* __restrict__ X, float4* __restrict__ rec, int H, int W,
+                                          int tile, PrepLds& S) {
+    constexpr int HW_ = kPrepTX + 2, HROW = HW_ * 3;
+    const int tid = threadIdx.x;
+    const int tiles_x = (W + kPrepTX - 1) / kPrepTX;
+    const int x0 = (tile % tiles_x) * kPrepTX, y0 = (tile / tiles_x) * kPrepTY;
+    for (int i = tid; i < (kPrepTY + 2) * HROW; i += 256) {
+        const int j = i / HROW, rem = i - j * HROW, c = rem / 3, k = rem - 3 * c;
+        const int y = min(max(y0 - 1 + j, 0), H - 1), x = min(max(x0 - 1 + c, 0), W - 1);
+        S.ray[i] = X[((long)y * W + x) * 3 + k];
+    }
+    __syncthreads();
+    for (int i = tid; i < (kPrepTY + 2) * HW_; i += 256) {
+        const float3 r = unit_ray(f3(S.ray[3 * i], S.ray[3 * i + 1], S.ray[3 * i + 2]));
+        S.ray[3 * i] = r.x; S.ray[3 * i + 1] = r.y; S.ray[3 * i + 2] = r.z;
+    }
+    __syncthreads();
+    {
+        const int lx = tid % kPrepTX, ly = tid / kPrepTX;
+        const int x = x0 + lx, y = y0 + ly;
+        const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
+        const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
+        // Halo column of pixel x' is x' - x0 + 1 (clamped like the load above).
+        auto at = [&](int yy, int xx) {
+            const float* q = S.ray + 3 * ((yy - y0 + 1) * HW_ + (xx - x0 + 1));
+            return f3(q[0], q[1], q[2]);
+        };
+        if (x < W && y < H) {
+            const float3 r = at(y, x), rxm = at(y, xm), rxp = at(y, xp), rym = at(ym, x), ryp = at(yp, x);
+            float sx = 1.0f / (float)(xp - xm), sy = 1.0f / (float)(yp - ym);
+            float3 gx = f3((rxp.x - rxm.x) * sx, (rxp.y - rxm.y) * sx, (rxp.z - rxm.z) * sx);
+            float3 gy = f3((ryp.x - rym.x) * sy, (ryp.y - rym.y) * sy, (ryp.z - rym.z) * sy);
+            float4* o = S.rec + kRecF4 * tid;
+            o[0] = make_float4(r.x, r.y, r.z, gx.x);
+            o[1] = make_float4(gx.y, gx.z, gy.x, gy.y);
+            o[2] = make_float4(gy.z, 0.f, 0.f, 0.f);
+        }
+    }
+    __syncthreads();
+    const int nx = min(kPrepTX, W - x0);
+    for (int i = tid; i < kPrepTY * kPrepTX * kRecF4; i += 256) {
+        const int row = i / (kPrepTX * kRecF4), j = i - row * (kPrepTX * kRecF4);
+        if (j < nx * kRecF4 && y0 + row < H) store_nt(rec + ((long)(y0 + row) * W + x0) * kRecF4 + j, S.rec[i]);
+    }
 }
 
 __global__ void __launch_bounds__(256) prep_kernel(const float* __restrict__ X, float4* __restrict__ rec, int H, int W) {
-    long m = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= (long)H * W) return;
-    prep_pixel(X, rec, H, W, (int)(m % W), (int)(m / W));
+    __shared__ PrepLds S;
+    prep_tile(X, rec, H, W, blockIdx.x, S);
 }
 
 // Tile of workgroup b in a 1-D launch over `tiles` tiles.  Workgroups are
@@ -291,16 +335,21 @@ __global__ void __launch_bounds__(TX * TY) fwd_kernel(EdgeArgs A, int remap) {
     match_query<DT>(A, x, y);
 }
 
-__device__ __forceinline__ int wave_min(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-    return v;
+// Minimum / maximum over the 64 lanes of a wave (every lane active), in every
+// lane: DPP quad swaps, half-row and row mirrors give the 16-lane result in
+// each row, then the four rows are combined from scalar registers.
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme(int v) {
+    auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false));   // quad_perm [1,0,3,2]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false));   // quad_perm [2,3,0,1]
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, false));  // row_half_mirror
+    v = op(v, __builtin_amdgcn_mov_dpp(v, 0x140, 0xF, 0xF, false));  // row_mirror
+    return op(op(__builtin_amdgcn_readlane(v, 0), __builtin_amdgcn_readlane(v, 16)),
+              op(__builtin_amdgcn_readlane(v, 32), __builtin_amdgcn_readlane(v, 48)));
 }
-__device__ __forceinline__ int wave_max(int v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-    return v;
-}
+__device__ __forceinline__ int wave_min(int v) { return wave_extreme<false>(v); }
+__device__ __forceinline__ int wave_max(int v) { return wave_extreme<true>(v); }
 
 // ceil(2^32 / d): for 0 <= n < 2^16 and 1 <= d < 2^16, umulhi(n, magic) = n / d
 // (the rounding excess n (magic d - 2^32) / 2^32 stays below 1/d).
@@ -559,18 +608,17 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
     QueryDesc<24> qd;
     qd.load(A.Dji, n, 24);
-    float qn2 = 0.f, ql1 = 0.f, qmax = 0.f;
+    // |q_k| <= |q| bounds every element (fp16 range) and |q|_1 <= sqrt(24) |q|;
+    // the 1.0001 margin covers the rounding of the fp32 norm.
+    float qn2 = 0.f;
     uint32_t q16[12];
 #pragma unroll
-    for (int k = 0; k < 24; ++k) {
-        qn2 = fmaf(qd.q[k], qd.q[k], qn2);
-        ql1 += fabsf(qd.q[k]);
-        qmax = fmaxf(qmax, fabsf(qd.q[k]));
-    }
+    for (int k = 0; k < 24; ++k) qn2 = fmaf(qd.q[k], qd.q[k], qn2);
+    const float qn = sqrtf(qn2) * 1.0001f;
+    if (!(qn <= kF16Max)) return refine_global<24>(A, n, q);
 #pragma unroll
     for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k], qd.q[2 * k + 1]);
-    const float qn = sqrtf(qn2);
-    if (!(qmax <= kF16Max) || !isfinite(ql1)) return refine_global<24>(A, n, q);
+    const float ql1 = kSqrt24Up * qn;
     const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (ql1 + dl1);
     const float eps32 = kU32x24 * qn * dnorm;
     const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
@@ -735,9 +783,10 @@ __device__ __forceinline__ int find_edge(const EdgeArgs* __restrict__ E, int n_e
     return lo;
 }
 
-// One block of 256 pixels per prep tile; prep tiles of edge e start at prep_begin[e].
+// Prep tiles of edge e start at prep_begin[e] (prep_tiles(H, W) per edge).
 __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __restrict__ E, const int32_t* __restrict__ prep_begin,
                                                            int n_edges) {
+    __shared__ PrepLds S;
     int blk = blockIdx.x;
     int lo = 0, hi = n_edges - 1;
     while (lo < hi) {
@@ -745,9 +794,7 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
         if (prep_begin[mid] <= blk) lo = mid; else hi = mid - 1;
     }
     const EdgeArgs& A = E[lo];
-    long m = (long)(blk - prep_begin[lo]) * 256 + threadIdx.x;
-    if (m >= (long)A.H * A.W) return;
-    prep_pixel(A.Xii, const_cast<float4*>(A.rays), A.H, A.W, (int)(m % A.W), (int)(m / A.W));
+    prep_tile(A.Xii, const_cast<float4*>(A.rays), A.H, A.W, blk - prep_begin[lo], S);
 }
 
 // Persistent forward over all edges: workgroups pop tile ids from a counter
@@ -788,10 +835,18 @@ __global__ void __launch_bounds__(64) set_counter_kernel(int32_t* counter) {
 
 // ---------------------------------------------------------------- backward
 
+// Zeroes a[0, count): scalar stores up to the first 16-byte boundary and after
+// the last one, float4 stores in between.
 __global__ void __launch_bounds__(256) fill_zero_kernel(float* __restrict__ a, long count) {
-    long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    long stride = (long)gridDim.x * blockDim.x;
-    for (; i < count; i += stride) a[i] = 0.f;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long head = min(count, (long)(((16u - ((uint32_t)(uintptr_t)a & 15u)) & 15u) >> 2));
+    if (i < head) a[i] = 0.f;
+    float4* __restrict__ b = reinterpret_cast<float4*>(a + head);
+    const long nb = (count - head) >> 2;
+    for (long j = i; j < nb; j += stride) store_nt(b + j, make_float4(0.f, 0.f, 0.f, 0.f));
+    const long t = head + (nb << 2) + i;
+    if (t < count && i < 4) a[t] = 0.f;
 }
 
 // v -> N(X) v = (v - u (u.v)) / |X| with u = X/|X| (Supp. A, Eq. norm_jac).
@@ -992,9 +1047,8 @@ __global__ void __launch_bounds__(256) stats_kernel(const int32_t* __restrict__ 
 static inline unsigned blocks_for(long count, int per) { return (unsigned)((count + per - 1) / per); }
 
 hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s) {
-    long N = (long)H * W;
     timer_begin("prep", s);
-    prep_kernel<<<blocks_for(N, 256), 256, 0, s>>>(Xii, rays, H, W);
+    prep_kernel<<<(unsigned)prep_tiles(H, W), 256, 0, s>>>(Xii, rays, H, W);
     timer_end(s);
     return hipGetLastError();
 }
@@ -1090,7 +1144,7 @@ hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const fl
                       const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s) {
     long N = (long)H * W;
     timer_begin("fill", s);
-    fill_zero_kernel<<<min(blocks_for(3 * N, 256), 4096u), 256, 0, s>>>(dXii, 3 * N);
+    fill_zero_kernel<<<min(blocks_for(3 * N / 4 + 1, 256), 4096u), 256, 0, s>>>(dXii, 3 * N);
     timer_end(s);
     const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
     timer_begin("bwd", s);
