@@ -502,19 +502,22 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
 // Exact first-maximum refine with an fp16 pre-filter (D = 24, r <= 5).  The
 // staged region holds D^i_i in fp16 (three planes of eight halves: 48 B per
 // pixel), so one pass scores every window candidate with v_dot2_f32_f16.
-// Any candidate whose fp32 score could equal the fp32 maximum has an fp16
-// score within tau of the running fp16 maximum, where tau bounds twice the
-// sum of the fp16 error (conversion of both operands with round-to-nearest,
-// relative 2^-11, absolute 2^-14 for values that may flush, plus fp32
-// accumulation) and the fp32 error of the exact dot (24 u32 |q||d|).  Those
-// candidates are rescored exactly from global memory in row-major order with
-// the same products and order as every other refine path, so the result is
-// the same index.
+// Both operands are scaled by 2^8 before the conversion (exact), which moves
+// the fp16 subnormal range 2^8 below the values it would otherwise hold.
+// Any candidate whose fp32 score could equal the fp32 maximum has a scaled
+// fp16 score within tau of the running fp16 maximum, where tau bounds twice
+// the sum of the fp16 error (conversion of both scaled operands with
+// round-to-nearest, relative 2^-11, absolute 2^-14 for values that may flush,
+// plus fp32 accumulation) and the fp32 error of the exact dot (24 u32 |q||d|),
+// all in scaled units.  Those candidates are rescored exactly from global
+// memory in row-major order with the same products and order as every other
+// refine path, so the result is the same index.
 
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kRegionPx16 = 832;          // 832 px x 48 B = 39 KiB: four workgroups per CU
-constexpr float kF16Max = 60000.f;        // larger magnitudes fall back to the exact scan
+constexpr float kF16Max = 60000.f;        // larger scaled magnitudes fall back to the exact scan
+constexpr float kScale16 = 256.f;         // 2^8, applied to both operands before the conversion
 constexpr float kU16 = 4.8828125e-4f;     // 2^-11
 constexpr float kU32x24 = 1.4305115e-6f;  // 24 * 2^-24
 constexpr float kFlush16 = 6.1035156e-5f; // 2^-14
@@ -526,7 +529,7 @@ struct TileLds16 {
         float4 rays[3 * kRegionPx16];      // LM ray window (records of up to kRegionPx16 pixels)
     };
     int box[4 * 16];
-    float stat[16];                       // per wave: max over 8-float chunks of the chunk's |d|^2
+    float stat[16];                       // per wave: largest |d|^2 of a region pixel
 };
 
 __device__ __forceinline__ uint32_t pack_h2(float a, float b) {
@@ -614,11 +617,14 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     uint32_t q16[12];
 #pragma unroll
     for (int k = 0; k < 24; ++k) qn2 = fmaf(qd.q[k], qd.q[k], qn2);
-    const float qn = sqrtf(qn2) * 1.0001f;
+    // Bounds and tau in scaled units (both operands times kScale16).
+    const float qn = sqrtf(qn2) * 1.0001f * kScale16;
     if (!(qn <= kF16Max)) return refine_global<24>(A, n, q);
 #pragma unroll
-    for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k], qd.q[2 * k + 1]);
+    for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k] * kScale16, qd.q[2 * k + 1] * kScale16);
     const float ql1 = kSqrt24Up * qn;
+    dnorm *= kScale16;
+    dl1 *= kScale16;
     const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (ql1 + dl1);
     const float eps32 = kU32x24 * qn * dnorm;
     const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
@@ -655,17 +661,25 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
             }
         }
     }
-    // Pass 2: exact scores of the survivors in row-major order.
+    // Pass 2: exact scores of the survivors in row-major order, two per step
+    // so that both descriptor reads are in flight together.
+    auto pop = [&](uint64_t& m0, uint64_t& m1) -> int {
+        if (m0) { const int k = __builtin_ctzll(m0); m0 &= m0 - 1; return k; }
+        if (m1) { const int k = 64 + __builtin_ctzll(m1); m1 &= m1 - 1; return k; }
+        return -1;
+    };
+    auto pixel = [&](int kk) -> long {
+        const int dy = kk / side, dx = kk - dy * side;
+        return (long)(my0 + dy - r) * W + (mx0 + dx - r);
+    };
     float best = -INFINITY;
     long bi = -1;
     while (mask0 | mask1) {
-        int kk;
-        if (mask0) { kk = __builtin_ctzll(mask0); mask0 &= mask0 - 1; }
-        else { kk = 64 + __builtin_ctzll(mask1); mask1 &= mask1 - 1; }
-        int dy = kk / side, dx = kk - dy * side;
-        long m = (long)(my0 + dy - r) * W + (mx0 + dx - r);
-        float sc = exact24(qd.q, A.Dii, m);
-        if (sc > best) { best = sc; bi = m; }
+        const int k1 = pop(mask0, mask1), k2 = pop(mask0, mask1);
+        const long m1 = pixel(k1), m2 = k2 >= 0 ? pixel(k2) : m1;
+        const float s1 = exact24(qd.q, A.Dii, m1), s2 = exact24(qd.q, A.Dii, m2);
+        if (s1 > best) { best = s1; bi = m1; }
+        if (k2 >= 0 && s2 > best) { best = s2; bi = m2; }
     }
     return bi;
 }
@@ -693,47 +707,52 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
     bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
-    float pn2 = 0.f;
+    float pn2 = 0.f;  // largest |d|^2 over the region's pixels
     if (use16) {
-        // Stage: chunk c is pixel c / 3, plane c % 3 (descriptor floats 8k..8k+7),
-        // in batches of kBatch chunks per thread whose loads are all issued
-        // before their conversions and stores.
-        constexpr int kBatch = 5;
+        // Stage: each lane converts whole pixels (six float4 loads, the norm,
+        // three fp16 planes), kBatch pixels per step with all loads issued
+        // before the conversions and stores.
+        constexpr int kBatch = 2;
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
-        const int total = rw * rh * 3;
+        const int total = rw * rh;
         const uint32_t magic = div_magic(rw);
-        for (int c00 = 0; c00 < total; c00 += kBatch * NT) {
-            float4 lu[kBatch], lv[kBatch];
+        for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
+            float4 v[kBatch][6];
 #pragma unroll
             for (int i = 0; i < kBatch; ++i) {
-                const int c = c00 + tid + i * NT;
-                if (c < total) {
-                    const int pix = c / 3, k = c - 3 * (c / 3);
+                const int pix = p00 + tid + i * NT;
+                if (pix < total) {
                     const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
-                    const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6 + 2 * k;
-                    lu[i] = src[0];
-                    lv[i] = src[1];
+                    const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k) v[i][k] = src[k];
                 }
             }
 #pragma unroll
             for (int i = 0; i < kBatch; ++i) {
-                const int c = c00 + tid + i * NT;
-                if (c < total) {
-                    const int pix = c / 3, k = c - 3 * (c / 3);
-                    const float4 u = lu[i], v = lv[i];
-                    float e2 = u.x * u.x + u.y * u.y + u.z * u.z + u.w * u.w + v.x * v.x + v.y * v.y + v.z * v.z + v.w * v.w;
+                const int pix = p00 + tid + i * NT;
+                if (pix < total) {
+                    float e2 = 0.f;
+#pragma unroll
+                    for (int k = 0; k < 6; ++k)
+                        e2 += v[i][k].x * v[i][k].x + v[i][k].y * v[i][k].y + v[i][k].z * v[i][k].z + v[i][k].w * v[i][k].w;
                     // A NaN or infinite element, or squares that overflow, make e2
                     // non-finite and fail the range test below.
                     pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
-                    S.desc[k * kRegionPx16 + pix] =
-                        make_uint4(pack_h2(u.x, u.y), pack_h2(u.z, u.w), pack_h2(v.x, v.y), pack_h2(v.z, v.w));
+#pragma unroll
+                    for (int k = 0; k < 3; ++k) {
+                        const float4 u = v[i][2 * k], w = v[i][2 * k + 1];
+                        S.desc[k * kRegionPx16 + pix] =
+                            make_uint4(pack_h2(u.x * kScale16, u.y * kScale16), pack_h2(u.z * kScale16, u.w * kScale16),
+                                       pack_h2(w.x * kScale16, w.y * kScale16), pack_h2(w.z * kScale16, w.w * kScale16));
+                    }
                 }
             }
         }
     }
-    // Region bounds from the largest chunk: |d|^2 <= 3 pn2, every element
-    // |d_k| <= sqrt(pn2) (so pn2 <= kF16Max^2 keeps the conversion finite), and
-    // |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
+    // Region bounds: |d| <= sqrt(pn2) for every pixel, so every element
+    // |d_k| <= sqrt(pn2) (kScale16^2 pn2 <= kF16Max^2 keeps the scaled
+    // conversion finite), and |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
     if ((tid & 63) == 0) S.stat[wv] = pn2;
@@ -741,10 +760,10 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     pn2 = S.stat[0];
 #pragma unroll
     for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
-    use16 = use16 && pn2 <= kF16Max * kF16Max;
+    use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
     if (q.good) {
         const long n = (long)y * W + x;
-        const float dnorm = sqrtf(3.f * pn2) * 1.0001f;
+        const float dnorm = sqrtf(pn2) * 1.0001f;
         long bi = use16 ? refine_f16(A, n, q, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
                         : refine_global<24>(A, n, q);
         finish(A, n, q, bi);
