@@ -376,27 +376,72 @@ __device__ __forceinline__ void block_box(int& lx, int& hx, int& ly, int& hy, in
 }
 
 // Margin (pixels) of the staged ray window around the bilinear cells of the
-// tile's queries after the first LM iteration.
+// tile's queries.
 constexpr int kRayMargin = 2;
 
-// Phase 1 of a tile with the ray records staged in LDS.  The first LM
-// iteration reads global memory; the window around the cells it reached
-// (plus kRayMargin) is then copied into `lds` (at most cap_px pixels, direct
-// global -> LDS loads) and the remaining iterations read it, falling back to
-// global memory for cells outside it.  All lanes of the block call this.
+// Copies the ray records of window [lx, lx + rw) x [ly, ly + rh) into `lds`
+// (direct global -> LDS loads, record of window pixel k at lds[3k .. 3k+2]);
+// the caller waits for them and synchronises.
 template <int NT>
+__device__ __forceinline__ void stage_rays(const EdgeArgs& A, float4* lds, int lx, int ly, int rw, int rh) {
+    const int tid = threadIdx.x;
+    const int slots = kRecF4 * rw * rh;
+    const uint32_t magic = div_magic(rw);
+    for (int c0 = tid & ~63; c0 < slots; c0 += NT) {
+        const int c = c0 + (tid & 63);
+        if (c < slots) {
+            const int pix = c / kRecF4, j = c - kRecF4 * (c / kRecF4);
+            const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+            __builtin_amdgcn_global_load_lds(A.rays + ((long)(ly + ry) * A.W + lx + rx) * kRecF4 + j,
+                                             (__attribute__((address_space(3))) void*)(lds + c0), 16, 0, 0);
+        }
+    }
+}
+
+// Phase 1 of a tile with the ray records staged in LDS.  Queries that start on
+// their own pixel (no p_init) sample the cells of the tile's pixels first, so
+// the window of those cells (plus kRayMargin) is staged before the query
+// setup, with no dependence on it.  After the first LM iteration the window
+// around the cells every query has reached (plus kRayMargin) is staged
+// unless the first window already holds it (at most cap_px pixels).  Samples
+// outside the staged window read global memory.  All lanes of the block call
+// this; [tx_lo, tx_hi] x [ty_lo, ty_hi] are the tile's pixels in the image.
+// EARLY enables the first window: it shortens the latency of a launch with
+// one wave of tiles and costs bandwidth in a persistent launch, whose other
+// workgroups hide that latency anyway.
+template <int NT, bool EARLY>
 __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool inside, QState& q,
-                                        float4* lds, int cap_px, int* box) {
-    const int H = A.H, W = A.W, tid = threadIdx.x;
+                                        float4* lds, int cap_px, int* box, int tx_lo, int tx_hi, int ty_lo,
+                                        int ty_hi) {
+    const int H = A.H, W = A.W;
     float3 t;
     LMState st;
     q.good = false;
-    const bool act = inside && lm_setup(A, x, y, q, t, st);
     const GlobalRays g{ray_buffer(A.rays, H, W), W};
     const int first = min(A.K, 1);
+    int wx = 0, wy = 0, ww = 0, wh = 0;  // staged window (ww == 0: none)
+    if (EARLY && !A.p_init) {
+        const int lx = max(min(tx_lo, W - 2) - kRayMargin, 0), hx = min(min(tx_hi, W - 2) + 1 + kRayMargin, W - 1);
+        const int ly = max(min(ty_lo, H - 2) - kRayMargin, 0), hy = min(min(ty_hi, H - 2) + 1 + kRayMargin, H - 1);
+        if ((hx - lx + 1) * (hy - ly + 1) <= cap_px) {
+            wx = lx; wy = ly; ww = hx - lx + 1; wh = hy - ly + 1;
+            stage_rays<NT>(A, lds, wx, wy, ww, wh);
+        }
+    }
+    const bool act = inside && lm_setup(A, x, y, q, t, st);
+    if (ww) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
+    }
     if (act) {
-        lm_start(g, H, W, A.lambda0, t, st);
-        lm_iterate(g, H, W, t, first, st);
+        if (ww) {
+            const WindowRays wr{lds, wx, wy, ww, wh, g};
+            lm_start(wr, H, W, A.lambda0, t, st);
+            lm_iterate(wr, H, W, t, first, st);
+        } else {
+            lm_start(g, H, W, A.lambda0, t, st);
+            lm_iterate(g, H, W, t, first, st);
+        }
     }
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (act) {
@@ -404,27 +449,23 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
         lx = max(cx - kRayMargin, 0); hx = min(cx + 1 + kRayMargin, W - 1);
         ly = max(cy - kRayMargin, 0); hy = min(cy + 1 + kRayMargin, H - 1);
     }
-    block_box<NT>(lx, hx, ly, hy, box);
+    block_box<NT>(lx, hx, ly, hy, box);  // ends with a barrier: no lane reads the window any more
     const int rw = hx - lx + 1, rh = hy - ly + 1;
-    const bool stage = A.K > first && hx >= lx && rw * rh <= cap_px;
-    if (stage) {
-        const int slots = kRecF4 * rw * rh;
-        const uint32_t magic = div_magic(rw);
-        for (int c0 = tid & ~63; c0 < slots; c0 += NT) {
-            const int c = c0 + (tid & 63);
-            if (c < slots) {
-                const int pix = c / kRecF4, j = c - kRecF4 * (c / kRecF4);
-                const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
-                __builtin_amdgcn_global_load_lds(A.rays + ((long)(ly + ry) * W + lx + rx) * kRecF4 + j,
-                                                 (__attribute__((address_space(3))) void*)(lds + c0), 16, 0, 0);
-            }
+    const bool more = A.K > first && hx >= lx;
+    const bool held = ww && lx >= wx && hx < wx + ww && ly >= wy && hy < wy + wh;
+    if (more && !held) {
+        if (rw * rh <= cap_px) {
+            wx = lx; wy = ly; ww = rw; wh = rh;
+            stage_rays<NT>(A, lds, wx, wy, ww, wh);
+            __builtin_amdgcn_s_waitcnt(0);
+        } else {
+            ww = 0;
         }
-        __builtin_amdgcn_s_waitcnt(0);
     }
     __syncthreads();
     if (act) {
-        if (stage) {
-            const WindowRays wr{lds, lx, ly, rw, rh, g};
+        if (more && ww) {
+            const WindowRays wr{lds, wx, wy, ww, wh, g};
             lm_iterate(wr, H, W, t, A.K - first, st);
         } else {
             lm_iterate(g, H, W, t, A.K - first, st);
@@ -457,7 +498,8 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT>(A, x, y, inside, q, S.rays, 2 * kRegionPx, S.box);
+    tile_lm<NT, false>(A, x, y, inside, q, S.rays, 2 * kRegionPx, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+                min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (q.good) {
@@ -687,14 +729,15 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
 // One TX x TY tile with the fp16 pre-filtered refine.  Falls back to the exact
 // global scan for the whole tile when the region does not fit, r > 5, or a
 // region value is non-finite or too large for fp16.
-template <int TX, int TY>
+template <int TX, int TY, bool EARLY>
 __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16& S) {
     constexpr int NT = TX * TY;
     const int tid = threadIdx.x;
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT>(A, x, y, inside, q, S.rays, kRegionPx16, S.box);
+    tile_lm<NT, EARLY>(A, x, y, inside, q, S.rays, kRegionPx16, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+                min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (q.good) {
@@ -778,7 +821,7 @@ __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4)
     const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
     const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
     if (t < 0) return;
-    tile_f16<TX, TY>(A, t % tiles_x, t / tiles_x, S);
+    tile_f16<TX, TY, true>(A, t % tiles_x, t / tiles_x, S);
 }
 
 template <int TX, int TY>
@@ -839,7 +882,7 @@ batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
         if constexpr (MODE == 1) {
             tile_lds<TX, TY>(A, tx, ty, S);
         } else if constexpr (MODE == 2) {
-            tile_f16<TX, TY>(A, tx, ty, S);
+            tile_f16<TX, TY, false>(A, tx, ty, S);
         } else {
             int x = tx * TX + (int)(threadIdx.x % TX);
             int y = ty * TY + (int)(threadIdx.x / TX);
