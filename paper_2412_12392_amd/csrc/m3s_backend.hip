@@ -18,13 +18,13 @@
 //           workgroup.
 //   edge    one workgroup per edge: the edge's partials summed in fp64 in a
 //           fixed order; A^T H_e A and A^T g_e.
-//   solve   one workgroup: the edges' blocks scattered in edge order into the
-//           reduced 7(N-1) system (keyframe 0 holds the gauge) by one wave
-//           whose lanes own fixed block offsets (so every address has one
-//           writer); blocked right-looking Cholesky in fp64 with 32 x 32
-//           tiles, the diagonal tile factored in LDS and the panel kept in
-//           LDS; blocked substitutions; T_WC[k] <- Exp(tau_k) o T_WC[k]
-//           (Eq. 1).  A system that is not positive definite, or a step norm
+//   assemble one workgroup per block row of the reduced 7(N-1) system
+//           (keyframe 0 holds the gauge): the edges' blocks summed in LDS in
+//           edge order, one writer per entry, rows written out whole.
+//   solve   one workgroup: blocked right-looking Cholesky in fp64 with
+//           32 x 32 tiles, the diagonal tile factored by one wave in
+//           registers and the panel kept in LDS; blocked substitutions;
+//           T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  A system that is not positive definite, or a step norm
 //           below step_tol, ends the loop: later launches of the call return
 //           at once.
 //
@@ -199,6 +199,60 @@ __global__ void __launch_bounds__(kThreads) backend_edge_kernel(BackendArgs A, i
     }
 }
 
+// Assembly of the reduced system: one workgroup per block row (keyframe
+// p = blockIdx.x + 1, rows 7(p-1) .. 7(p-1)+6) and one for the padding rows.
+// The row block is summed in LDS from the edges' blocks in edge order (thread
+// (a, b) owns the entries at offset (a, b) of the diagonal block, thread
+// 64 + (a, b) those of the off-diagonal blocks, so every entry has one writer,
+// which visits the edges in order) and written out whole, zeros included,
+// with its right-hand side -g.
+constexpr int kAsmThreads = 128;
+constexpr int kMaxNp = (kMaxDim + kTile - 1) / kTile * kTile;
+
+__global__ void __launch_bounds__(kAsmThreads) backend_assemble_kernel(BackendArgs A) {
+    __shared__ double rows[7 * kMaxNp];
+    __shared__ double rr[7];
+    if (A.state[0]) return;
+    const int np = A.np, n = A.n, tid = threadIdx.x;
+    if ((int)blockIdx.x == A.N - 1) {
+        for (int r = n; r < np; ++r)
+            for (int c = tid; c < np; c += kAsmThreads) A.M[(long)r * np + c] = r == c ? 1.0 : 0.0;
+        for (int r = n + tid; r < np; r += kAsmThreads) A.rhs[r] = 0.0;
+        return;
+    }
+    for (int i = tid; i < 7 * np; i += kAsmThreads) rows[i] = 0.0;
+    if (tid < 7) rr[tid] = 0.0;
+    __syncthreads();
+    const int P = (int)blockIdx.x + 1, I = 7 * (P - 1);
+    const int a = (tid & 63) / 7, b = (tid & 63) % 7;
+    for (int e = 0; e < A.E; ++e) {
+        const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+        // A self edge has T_ij = I whatever the poses: its blocks cancel.
+        if (!edge_in_range(ei, ej, A.N) || ei == ej) continue;
+        const bool own_i = ei == P;
+        if (!own_i && ej != P) continue;
+        const double* blk = A.edge_blk + (size_t)e * kBlk;
+        const int other = own_i ? ej : ei;
+        if (tid < 49) {
+            // H_ii += A^T H_e A (own_i), H_jj += A^T H_e A (own_j)
+            rows[a * np + I + b] += blk[7 * a + b];
+        } else if (tid >= 64 && tid < 64 + 49) {
+            // H_ij -= A^T H_e A, H_ji -= (A^T H_e A)^T; keyframe 0 holds the gauge
+            if (other > 0) rows[a * np + 7 * (other - 1) + b] -= own_i ? blk[7 * a + b] : blk[7 * b + a];
+        } else if (tid >= 49 && tid < 56) {
+            // right-hand side -g: g_i -= A^T g_e, g_j += A^T g_e
+            const int o = tid - 49;
+            rr[o] += own_i ? blk[49 + o] : -blk[49 + o];
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < 7 * np; i += kAsmThreads) {
+        const int r = i / np, c = i - r * np;
+        A.M[(long)(I + r) * np + c] = rows[i];
+    }
+    if (tid < 7) A.rhs[I + tid] = rr[tid];
+}
+
 // Tile (ti, tj) of M as kTile x kTile, row-major with leading dimension np.
 __device__ __forceinline__ double* tile_ptr(const BackendArgs& A, int ti, int tj) {
     return A.M + (long)ti * kTile * A.np + (long)tj * kTile;
@@ -213,6 +267,12 @@ __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, 
     const int np = A.np;
     const int r0 = (lane >> 3) * 4, c0 = (lane & 7) * 4;
     const int ra = ti * kTile + r0, ca = tj * kTile + c0;
+    // The target entries are read first so their latency overlaps the product.
+    double cur[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) cur[u][v] = A.M[(long)(R0 + ra + u) * np + R0 + ca + v];
     double acc[4][4] = {};
     for (int t = 0; t < kTile; ++t) {
         double va[4], vb[4];
@@ -230,7 +290,7 @@ __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, 
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            if (ti != tj || c0 + v <= r0 + u) A.M[(long)(R0 + ra + u) * np + R0 + ca + v] -= acc[u][v];
+            if (ti != tj || c0 + v <= r0 + u) A.M[(long)(R0 + ra + u) * np + R0 + ca + v] = cur[u][v] - acc[u][v];
 }
 
 // One workgroup: assemble the reduced system, factor it (blocked Cholesky),
@@ -238,6 +298,7 @@ __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, 
 __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArgs A) {
     __shared__ double D[kTile][kTile + 1];        // diagonal tile being factored
     __shared__ double Dinv[kTile][kTile + 1];     // its inverse
+    __shared__ double V[kTile][kTile + 1];        // the inverse's rows before scaling
     __shared__ double panel[kPanelRows * kPanelStride];  // the factored panel below it
     __shared__ double x[kMaxDim + kTile];          // right-hand side, then the solution
     __shared__ double red[kSolveThreads / 64];
@@ -247,97 +308,78 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
     const int tid = threadIdx.x;
     const int n = A.n, np = A.np, nt = np / kTile;
 
-    // Zero M and the right-hand side; padding rows get a unit diagonal.
-    for (int r = 0; r < np; ++r)
-        for (int c = tid; c < np; c += kSolveThreads) A.M[(long)r * np + c] = (r == c && r >= n) ? 1.0 : 0.0;
-    for (int k = tid; k < np; k += kSolveThreads) x[k] = 0.0;
-    __syncthreads();
-
-    // Scatter the edges' blocks in edge order.  Wave w owns the block rows p
-    // with (p - 1) % waves == w; within it lane (a, b) owns the entries whose
-    // offsets in their 7x7 block are (a, b) and lane 49 + a the right-hand side
-    // entries with offset a, so every address has one writer, which visits
-    // the edges in order.
-    {
-        const int wave = tid >> 6, lane = tid & 63;
-        const int a = lane / 7, b = lane % 7;
-        constexpr int kWaves = kSolveThreads / 64;
-        const double* __restrict__ blks = A.edge_blk;
-        for (int e = 0; e < A.E; ++e) {
-            const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
-            // A self edge has T_ij = I whatever the poses: its blocks cancel.
-            if (!edge_in_range(ei, ej, A.N) || ei == ej) continue;
-            const bool own_i = ei > 0 && (ei - 1) % kWaves == wave;
-            const bool own_j = ej > 0 && (ej - 1) % kWaves == wave;
-            if (!own_i && !own_j) continue;
-            const double* blk = blks + (size_t)e * kBlk;
-            const int I = 7 * (ei - 1), J = 7 * (ej - 1);
-            if (lane < 49) {
-                const double v = blk[7 * a + b];
-                if (own_i) {
-                    A.M[(long)(I + a) * np + I + b] += v;
-                    if (ej > 0) A.M[(long)(I + a) * np + J + b] -= v;
-                }
-                if (own_j) {
-                    A.M[(long)(J + a) * np + J + b] += v;
-                    if (ei > 0) A.M[(long)(J + a) * np + I + b] -= blk[7 * b + a];
-                }
-            } else if (lane < 56) {
-                const int o = lane - 49;
-                // right-hand side -g: g_i -= A^T g_e, g_j += A^T g_e
-                if (own_i) x[I + o] += blk[49 + o];
-                if (own_j) x[J + o] -= blk[49 + o];
-            }
-        }
-    }
-    __syncthreads();
+    for (int k = tid; k < np; k += kSolveThreads) x[k] = A.rhs[k];
 
     // Blocked right-looking Cholesky, lower triangle, kTile x kTile tiles.
-    // Per tile column k: the diagonal tile is factored in LDS by the whole
-    // workgroup (one column per step), its inverse Dinv = L_kk^-1 is formed and
-    // kept for the substitutions, the panel below becomes A_ik Dinv^T (a
-    // product, no sequential chain) and the trailing lower triangle takes
-    // -= L_ik L_jk^T from the panel (in LDS when it fits).
+    // Per tile column k: the diagonal tile is factored, its inverse
+    // Dinv = L_kk^-1 is formed and kept for the substitutions, the panel below
+    // becomes A_ik Dinv^T (a product, no sequential chain) and the trailing
+    // lower triangle takes -= L_ik L_jk^T from the panel (in LDS when it fits).
     bool failed = false;  // the same in every thread: decided from LDS values read after a barrier
     for (int k = 0; k < nt; ++k) {
         double* Mk = tile_ptr(A, k, k);
         for (int q = tid; q < kTile * kTile; q += kSolveThreads) D[q / kTile][q % kTile] = Mk[(long)(q / kTile) * np + q % kTile];
-        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = (q / kTile == q % kTile) ? 1.0 : 0.0;
+        for (int q = tid; q < kTile * kTile; q += kSolveThreads) V[q / kTile][q % kTile] = (q / kTile == q % kTile) ? 1.0 : 0.0;
+        const int R0 = (k + 1) * kTile;
+        const int m = np - R0;
         __syncthreads();
-        // Factor the tile, one column at a time, with the whole workgroup:
-        // scale L[.][c] and row c of Dinv by 1/sqrt(D[c][c]); then the
-        // trailing update of D and the row operations of Dinv = L_kk^-1.
-        // Every thread reads the same pivot after a barrier, so the decision
-        // to stop is the same in every thread.
+        // Factor the tile with the whole workgroup, one column c per step and
+        // one barrier per step: with d = D[c][c], the entries below take
+        // D[r][q] -= D[r][c] D[q][c] / d and the rows of the running inverse
+        // V[r][q] -= D[r][c] V[c][q] / d (r > c), both from values no thread
+        // writes in that step; the scaled outputs, column c of L (to M) and
+        // row c of Dinv = L_kk^-1 = V[c] / sqrt(d), go to other arrays.  Every
+        // thread reads the same pivot after a barrier, so the decision to stop
+        // is the same in every thread.
         for (int c = 0; c < kTile; ++c) {
+            // Two entries per thread.  Their operands (all inside the tile) are
+            // read unconditionally together with the pivot, so one LDS round
+            // trip serves the step.
+            static_assert(kTile * kTile % kSolveThreads == 0, "whole entries per thread");
+            constexpr int kH = kTile * kTile / kSolveThreads;
+            double drc[kH], dqc[kH], drq[kH], vcq[kH], vrq[kH];
+#pragma unroll
+            for (int h = 0; h < kH; ++h) {
+                const int e2 = tid + h * kSolveThreads;
+                const int r = e2 / kTile, q = e2 % kTile;
+                drc[h] = D[r][c]; dqc[h] = D[q][c]; drq[h] = D[r][q];
+                vcq[h] = V[c][q]; vrq[h] = V[r][q];
+            }
             const double dg = D[c][c];
+            // Keeps the reads above here (no instruction): issued together
+            // rather than one branch at a time below.
+            __asm__ volatile("" :: "v"(drc[0]), "v"(dqc[0]), "v"(drq[0]), "v"(vcq[0]), "v"(vrq[0]),
+                             "v"(drc[1]), "v"(dqc[1]), "v"(drq[1]), "v"(vcq[1]), "v"(vrq[1]), "v"(dg));
             if (!(dg > 0.0) || !isfinite(dg)) {
                 failed = true;
                 break;
             }
-            const double sd = sqrt(dg);
-            if (tid > c && tid < kTile) D[tid][c] /= sd;
-            if (tid >= 64 && tid < 64 + kTile && tid - 64 <= c) Dinv[c][tid - 64] /= sd;
-            __syncthreads();
-            if (tid == 0) D[c][c] = sd;
-            for (int e2 = tid; e2 < kTile * kTile; e2 += kSolveThreads) {
+            // 1/sqrt(d): hardware estimate and two Newton steps (short dependent
+            // chain per column); sqrt(d) = d / sqrt(d).
+            double is = __builtin_amdgcn_rsq(dg);
+            is = is * fma(-0.5 * dg * is, is, 1.5);
+            is = is * fma(-0.5 * dg * is, is, 1.5);
+            const double sd = dg * is, idg = is * is;
+#pragma unroll
+            for (int h = 0; h < kH; ++h) {
+                const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                if (q > c && q <= r) D[r][q] -= D[r][c] * D[q][c];
-                if (r > c && q <= c) Dinv[r][q] -= D[r][c] * Dinv[c][q];
+                if (q > c && q <= r) D[r][q] = drq[h] - drc[h] * dqc[h] * idg;
+                else if (r > c && q <= c) V[r][q] = vrq[h] - drc[h] * vcq[h] * idg;
+                else if (r == c && q <= c) Dinv[c][q] = vcq[h] * is;
+                else if (q == c && r > c) Mk[(long)r * np + c] = drc[h] * is;
             }
+            if (tid == 0) Mk[(long)c * np + c] = sd;
             __syncthreads();
         }
         if (failed) break;
         double* inv = A.dinv + (size_t)k * kTile * kTile;
         for (int q = tid; q < kTile * kTile; q += kSolveThreads) {
             const int r = q / kTile, c = q % kTile;
-            if (c <= r) Mk[(long)r * np + c] = D[r][c];
-            inv[q] = Dinv[r][c];
+            inv[q] = c <= r ? Dinv[r][c] : 0.0;
         }
         // Panel: L_ik = A_ik Dinv^T, kStageRows rows at a time staged in LDS,
         // four elements per thread.
-        const int R0 = (k + 1) * kTile;
-        const int m = np - R0;
         const bool in_lds = m <= kPanelRows;
         for (int r0 = 0; r0 < m; r0 += kStageRows) {
             for (int q = tid; q < kStageRows * kTile; q += kSolveThreads) {
@@ -345,16 +387,24 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
                 if (rr < m) stage[(q / kTile) * kPanelStride + t] = A.M[(long)(R0 + rr) * np + k * kTile + t];
             }
             __syncthreads();
+            // Column c of four rows per thread: each Dinv[c][t] is read once for
+            // the four rows (same products and order per entry as a row-wise dot).
             const int c = tid % kTile;
+            constexpr int kU = kStageRows * kTile / kSolveThreads;
+            double acc[kU];
 #pragma unroll
-            for (int u = 0; u < kStageRows * kTile / kSolveThreads; ++u) {
-                const int sr = tid / kTile + u * (kSolveThreads / kTile);
-                const int rr = r0 + sr;
+            for (int u = 0; u < kU; ++u) acc[u] = 0.0;
+            for (int t = 0; t <= c; ++t) {
+                const double dv = Dinv[c][t];
+#pragma unroll
+                for (int u = 0; u < kU; ++u) acc[u] += stage[(tid / kTile + u * (kSolveThreads / kTile)) * kPanelStride + t] * dv;
+            }
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int rr = r0 + tid / kTile + u * (kSolveThreads / kTile);
                 if (rr < m) {
-                    double acc = 0.0;
-                    for (int t = 0; t <= c; ++t) acc += stage[sr * kPanelStride + t] * Dinv[c][t];
-                    A.M[(long)(R0 + rr) * np + k * kTile + c] = acc;
-                    if (in_lds) panel[rr * kPanelStride + c] = acc;
+                    A.M[(long)(R0 + rr) * np + k * kTile + c] = acc[u];
+                    if (in_lds) panel[rr * kPanelStride + c] = acc[u];
                 }
             }
             __syncthreads();
@@ -540,6 +590,7 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
         timer_end(s);
         if (final_pass) break;
         timer_begin("backend_solve", s);
+        backend_assemble_kernel<<<N, kAsmThreads, 0, s>>>(A);
         backend_solve_kernel<<<1, kSolveThreads, 0, s>>>(A);
         timer_end(s);
     }
