@@ -1023,17 +1023,20 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     __shared__ float acc[3 * kBwdLdsPx];
     __shared__ int box[4 * 4];
     const int tid = threadIdx.x;
+    // The whole accumulator is cleared up front, overlapped with the query
+    // reads; the barriers of block_box order it before the atomics.
+    for (int i = tid; i < 3 * kBwdLdsPx; i += 256) acc[i] = 0.f;
     const int x = (blockIdx.x % tiles_x) * 16 + (tid & 15), y = (blockIdx.x / tiles_x) * 16 + (tid >> 4);
     const bool inside = x < W && y < H;
     const long n = (long)y * W + x;
     long cm[4] = {-1, -1, -1, -1};
     float3 gc[4];
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    int cx0 = 0, cy0 = 0;  // cell of p*: corner c is (cx0 + (c & 1), cy0 + (c >> 1))
     if (inside) {
         if (!valid[n]) {
             dXji[3 * n] = 0.f; dXji[3 * n + 1] = 0.f; dXji[3 * n + 2] = 0.f;
         } else {
-            int cx0, cy0;
             bwd_query(H, W, Xii, Xji, p, grad_p, grad_xhat, dXji, n, cm, gc, cx0, cy0);
             lx = cx0; hx = cx0 + 1; ly = cy0; hy = cy0 + 1;
         }
@@ -1043,12 +1046,10 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     const bool any = hx >= lx;
     if (any && bw * bh <= kBwdLdsPx) {
         const int cnt = 3 * bw * bh;
-        for (int i = tid; i < cnt; i += 256) acc[i] = 0.f;
-        __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (cm[c] < 0) continue;
-            const int cy = (int)(cm[c] / W), cx = (int)(cm[c] - (long)cy * W);
+            const int cy = cy0 + (c >> 1), cx = cx0 + (c & 1);
             float* a = acc + 3 * ((cy - ly) * bw + (cx - lx));
             atomicAdd(a, gc[c].x);
             atomicAdd(a + 1, gc[c].y);
