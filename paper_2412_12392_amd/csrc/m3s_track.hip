@@ -116,6 +116,28 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
 
 // Normal equations of the matches of this workgroup at the current pose: one
 // fp32 partial of kVals values per workgroup.
+// Sum over the 64 lanes of a wave (every lane active), in every lane: DPP quad
+// swaps, half-row and row mirrors give each row's sum in its lanes, then the
+// four row sums are added in a fixed order.
+__device__ __forceinline__ float wave_sum(float v) {
+    auto dpp = [](float x, int ctrl) {
+        return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), ctrl, 0xF, 0xF, false));
+    };
+    v += dpp(v, 0xB1);   // quad_perm [1,0,3,2]
+    v += dpp(v, 0x4E);   // quad_perm [2,3,0,1]
+    v += dpp(v, 0x141);  // row_half_mirror
+    v += dpp(v, 0x140);  // row_mirror
+    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
+    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
+    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
+    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
+    return (r0 + r1) + (r2 + r3);
+}
+
+// Matches per lane and step of the accumulation: their reads are issued
+// together before the arithmetic.
+constexpr int kMatchesPerLane = 4;
+
 __global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
     __shared__ float red[kThreads / 64][kVals];
     float T[12];
@@ -125,24 +147,36 @@ __global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
 #pragma unroll
     for (int i = 0; i < kVals; ++i) acc[i] = 0.f;
 
-    for (int n = blockIdx.x * kThreads + threadIdx.x; n < A.N; n += gridDim.x * kThreads) {
-        if (!A.valid[n]) continue;
-        const int m = A.idx[n];
-        if (m < 0 || m >= A.N) continue;
-        float q;
-        if (!confidence_gate(A.Qf[m], A.Qk[n], A.q_min, A.q_minf, q)) continue;
-        accumulate_match(T, A.Xf[3 * m], A.Xf[3 * m + 1], A.Xf[3 * m + 2], A.Xk[3 * n], A.Xk[3 * n + 1],
-                         A.Xk[3 * n + 2], q, A.rw, acc);
+    constexpr int kStep = kThreads * kMatchesPerLane;
+    for (int base = blockIdx.x * kStep + threadIdx.x; base < A.N; base += gridDim.x * kStep) {
+        int nn[kMatchesPerLane], mm[kMatchesPerLane];
+        bool ok[kMatchesPerLane];
+#pragma unroll
+        for (int u = 0; u < kMatchesPerLane; ++u) {
+            nn[u] = base + u * kThreads;
+            ok[u] = nn[u] < A.N && A.valid[nn[u]];
+            mm[u] = ok[u] ? A.idx[nn[u]] : 0;
+            ok[u] = ok[u] && mm[u] >= 0 && mm[u] < A.N;
+        }
+        float qf[kMatchesPerLane], qk[kMatchesPerLane], xf[kMatchesPerLane][3], xk[kMatchesPerLane][3];
+#pragma unroll
+        for (int u = 0; u < kMatchesPerLane; ++u) {
+            const int m = ok[u] ? mm[u] : 0, n = ok[u] ? nn[u] : 0;
+            qf[u] = A.Qf[m]; qk[u] = A.Qk[n];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) { xf[u][j] = A.Xf[3 * m + j]; xk[u][j] = A.Xk[3 * n + j]; }
+        }
+#pragma unroll
+        for (int u = 0; u < kMatchesPerLane; ++u) {
+            float q;
+            if (ok[u] && confidence_gate(qf[u], qk[u], A.q_min, A.q_minf, q))
+                accumulate_match(T, xf[u][0], xf[u][1], xf[u][2], xk[u][0], xk[u][1], xk[u][2], q, A.rw, acc);
+        }
     }
 
-    // Block partial: wave butterflies, then the four waves through LDS.
+    // Block partial: wave sums, then the four waves through LDS.
 #pragma unroll
-    for (int i = 0; i < kVals; ++i) {
-        float v = acc[i];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        acc[i] = v;
-    }
+    for (int i = 0; i < kVals; ++i) acc[i] = wave_sum(acc[i]);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int i = 0; i < kVals; ++i) red[threadIdx.x >> 6][i] = acc[i];
@@ -237,7 +271,7 @@ __global__ void __launch_bounds__(256) fuse_kernel(int N, int first, const float
 }  // namespace
 
 int track_blocks(int N) {
-    const int nb = (N + kThreads - 1) / kThreads;
+    const int nb = (N + kThreads * kMatchesPerLane - 1) / (kThreads * kMatchesPerLane);
     return nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb);
 }
 
