@@ -62,6 +62,7 @@ struct BackendArgs {
     RobustWeights rw;
     double step_tol;
     double* T64;              // [N*12] world poses
+    float* Trel;              // [E*12] T_ij = T_WC[i]^-1 T_WC[j] per edge at the current poses (zero out of range)
     double* edge_sys;         // [E*kStride] fp64 relative normal equations per edge
     double* edge_blk;         // [E*kBlk] A^T H_e A (49) and A^T g_e (7) per edge
     float* partials;          // [E*blocks_per_edge*kStride]
@@ -93,28 +94,35 @@ __device__ __forceinline__ bool edge_in_range(int ei, int ej, int N) {
     return ei >= 0 && ei < N && ej >= 0 && ej < N;
 }
 
+// T_ij of edge e in fp32 from the fp64 world poses (zero for an edge out of range).
+__device__ __forceinline__ void write_relative_pose(const BackendArgs& A, int e) {
+    const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+    double Ti[12], Tij[12];
+    if (edge_in_range(ei, ej, A.N)) {
+        sim3_inverse(A.T64 + 12 * ei, Ti);
+        sim3_mul(Ti, A.T64 + 12 * ej, Tij);
+    } else {
+        for (int k = 0; k < 12; ++k) Tij[k] = 0.0;
+    }
+    for (int k = 0; k < 12; ++k) A.Trel[12 * e + k] = (float)Tij[k];
+}
+
+// Relative poses at the initial world poses, one thread per edge.
+__global__ void __launch_bounds__(256) backend_relpose_kernel(BackendArgs A) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < A.E) write_relative_pose(A, e);
+}
+
 // final: 0 = an iteration's accumulation (skipped once the loop has ended), 1 = the final one.
 __global__ void __launch_bounds__(kThreads) backend_accum_kernel(BackendArgs A, int final_pass) {
     __shared__ float red[kThreads / 64][kVals];
-    __shared__ float Ts[12];
     if (!final_pass && A.state[0]) return;
     const int e = blockIdx.y;
     const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
     const bool edge_ok = edge_in_range(ei, ej, A.N);
-    if (threadIdx.x == 0) {
-        double Ti[12], Tij[12];
-        if (edge_ok) {
-            sim3_inverse(A.T64 + 12 * ei, Ti);
-            sim3_mul(Ti, A.T64 + 12 * ej, Tij);
-        } else {
-            for (int k = 0; k < 12; ++k) Tij[k] = 0.0;
-        }
-        for (int k = 0; k < 12; ++k) Ts[k] = (float)Tij[k];
-    }
-    __syncthreads();
     float T[12];
 #pragma unroll
-    for (int k = 0; k < 12; ++k) T[k] = Ts[k];
+    for (int k = 0; k < 12; ++k) T[k] = A.Trel[12 * e + k];
     float acc[kVals];
 #pragma unroll
     for (int k = 0; k < kVals; ++k) acc[k] = 0.f;
@@ -131,23 +139,37 @@ __global__ void __launch_bounds__(kThreads) backend_accum_kernel(BackendArgs A, 
     const int bpe = A.blocks_per_edge;
     const int chunk = (bpe % 8 == 0) ? (int)(blockIdx.x % 8) * (bpe / 8) + (int)(blockIdx.x / 8) : (int)blockIdx.x;
     const int stride = bpe * kThreads;
-    for (int n = edge_ok ? chunk * kThreads + threadIdx.x : A.HW; n < A.HW; n += stride) {
-        if (!A.valid[ebase + n]) continue;
-        const int m = A.idx[ebase + n];
-        if (m < 0 || m >= A.HW) continue;
-        float q;
-        if (!confidence_gate(Qi[m], Qj[n], A.q_min, A.q_minf, q)) continue;
-        accumulate_match(T, Xj[3 * n], Xj[3 * n + 1], Xj[3 * n + 2], Xi[3 * m], Xi[3 * m + 1], Xi[3 * m + 2], q,
-                         A.rw, acc);
+    // kBatch consecutive matches of the lane (same order as one at a time)
+    // have their reads issued together before the arithmetic.
+    constexpr int kBatch = 4;
+    for (int n0 = edge_ok ? chunk * kThreads + threadIdx.x : A.HW; n0 < A.HW; n0 += kBatch * stride) {
+        int nn[kBatch], mm[kBatch];
+        bool ok[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            nn[u] = n0 + u * stride;
+            ok[u] = nn[u] < A.HW && A.valid[ebase + nn[u]];
+            mm[u] = ok[u] ? A.idx[ebase + nn[u]] : 0;
+            ok[u] = ok[u] && mm[u] >= 0 && mm[u] < A.HW;
+        }
+        float qi[kBatch], qj[kBatch], xi[kBatch][3], xj[kBatch][3];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            const int m = ok[u] ? mm[u] : 0, n = ok[u] ? nn[u] : 0;
+            qi[u] = Qi[m]; qj[u] = Qj[n];
+#pragma unroll
+            for (int j = 0; j < 3; ++j) { xi[u][j] = Xi[3 * m + j]; xj[u][j] = Xj[3 * n + j]; }
+        }
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u) {
+            float q;
+            if (ok[u] && confidence_gate(qi[u], qj[u], A.q_min, A.q_minf, q))
+                accumulate_match(T, xj[u][0], xj[u][1], xj[u][2], xi[u][0], xi[u][1], xi[u][2], q, A.rw, acc);
+        }
     }
 
 #pragma unroll
-    for (int k = 0; k < kVals; ++k) {
-        float v = acc[k];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-        acc[k] = v;
-    }
+    for (int k = 0; k < kVals; ++k) acc[k] = wave_sum(acc[k]);
     if ((threadIdx.x & 63) == 0) {
 #pragma unroll
         for (int k = 0; k < kVals; ++k) red[threadIdx.x >> 6][k] = acc[k];
@@ -485,6 +507,9 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         sim3_mul(E, A.T64 + 12 * k, Tn);
         for (int j = 0; j < 12; ++j) A.T64[12 * k + j] = Tn[j];
     }
+    // Relative poses of every edge at the new poses, for the next accumulation.
+    __syncthreads();
+    for (int e = tid; e < A.E; e += kSolveThreads) write_relative_pose(A, e);
     double sq = 0.0;
     for (int k = tid; k < n; k += kSolveThreads) sq += x[k] * x[k];
     for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
@@ -519,7 +544,7 @@ __global__ void __launch_bounds__(256) backend_finish_kernel(BackendArgs A) {
 
 // Workspace layout.
 struct BackendLayout {
-    size_t T64, edge_sys, edge_blk, partials, state, stat, M, rhs, dinv, total;
+    size_t T64, Trel, edge_sys, edge_blk, partials, state, stat, M, rhs, dinv, total;
 };
 
 int padded_dim(int N) { return (7 * (N - 1) + kTile - 1) / kTile * kTile; }
@@ -531,6 +556,7 @@ BackendLayout backend_layout(int N, int HW, int E) {
     BackendLayout L;
     size_t o = 0;
     L.T64 = o;      o = al(o + sizeof(double) * 12 * N);
+    L.Trel = o;     o = al(o + sizeof(float) * 12 * E);
     L.edge_sys = o; o = al(o + sizeof(double) * kStride * E);
     L.edge_blk = o; o = al(o + sizeof(double) * kBlk * E);
     L.partials = o; o = al(o + sizeof(float) * kStride * (size_t)bpe * E);
@@ -568,6 +594,7 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
     A.rw = robust_weights(sigma_ray, sigma_dist, huber);
     A.step_tol = step_tol;
     A.T64 = reinterpret_cast<double*>(w + L.T64);
+    A.Trel = reinterpret_cast<float*>(w + L.Trel);
     A.edge_sys = reinterpret_cast<double*>(w + L.edge_sys);
     A.edge_blk = reinterpret_cast<double*>(w + L.edge_blk);
     A.partials = reinterpret_cast<float*>(w + L.partials);
@@ -580,6 +607,7 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
     A.info = info;
     const dim3 grid(A.blocks_per_edge, E);
     backend_init_kernel<<<(12 * N + 255) / 256, 256, 0, s>>>(T, A.T64, N, A.state, A.stat);
+    backend_relpose_kernel<<<(E + 255) / 256, 256, 0, s>>>(A);
     for (int it = 0; it <= iters; ++it) {
         const int final_pass = it == iters ? 1 : 0;
         timer_begin("backend_accum", s);

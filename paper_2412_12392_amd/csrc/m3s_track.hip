@@ -116,26 +116,6 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
 
 // Normal equations of the matches of this workgroup at the current pose: one
 // fp32 partial of kVals values per workgroup.
-// Sum over the 64 lanes of a wave (every lane active), in every lane: DPP quad
-// swaps, half-row and row mirrors give each row's sum in its lanes, then the
-// four row sums are added in a fixed order.
-template <int CTRL>
-__device__ __forceinline__ float dpp_move(float x) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, x), CTRL, 0xF, 0xF, false));
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-    v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-    v += dpp_move<0x141>(v);  // row_half_mirror
-    v += dpp_move<0x140>(v);  // row_mirror
-    const float r0 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 0));
-    const float r1 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 16));
-    const float r2 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 32));
-    const float r3 = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 48));
-    return (r0 + r1) + (r2 + r3);
-}
-
 // Matches per lane and step of the accumulation: their reads are issued
 // together before the arithmetic.
 constexpr int kMatchesPerLane = 4;
