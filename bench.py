@@ -18,6 +18,9 @@ Further legs, reported in the same JSON line:
                  K in 5..15 and r in 2..4 per edge, same comparison;
   roofline       the forward kernel's algorithmic bytes over its average
                  duration, timed live with hipEvents around each launch;
+  roofline_alu   the same launch's wave64 VALU instructions (counted by
+                 rocprofv3, committed profile) over that duration, against
+                 the issue rate of 256 CUs x 4 SIMDs at 2.4 GHz;
   track_fuse     the tracking pose solve (10 Gauss-Newton iterations) and the
                  canonical pointmap fusion of one 512x384 keyframe (Sec. 3.3);
   backend        Gauss-Newton over 32 keyframe poses at 512x384 with 65 edges
@@ -62,6 +65,10 @@ def log(*a):
 
 
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "fwd_kernels_512x384_hbm_counters.md")
+VALU_FILE = os.path.join(ROOT, "profiles", "fwd_kernels_512x384_valu_l2.md")
+# wave64 VALU instructions issued per second at most: 256 CUs x 4 SIMDs x 2.4 GHz,
+# one instruction per SIMD every 4 cycles (16 lanes per cycle).
+VALU_PEAK_GINST = 256 * 4 * 2.4 / 4
 
 
 def kernel_source_hash() -> str:
@@ -71,6 +78,24 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_2412_12392_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def measured_valu_per_wave(kernel: str):
+    """VALU instructions per wave of `kernel` from the committed rocprofv3
+    counter summary (SQ_INSTS_VALU / SQ_WAVES), or None when the summary is
+    missing or was taken from different kernel sources."""
+    try:
+        text = open(VALU_FILE).read()
+    except OSError:
+        return None
+    src = [l.split(":", 1)[1].strip() for l in text.splitlines() if l.startswith("source_sha256_16:")]
+    if not src or src[0] != kernel_source_hash():
+        return None
+    for l in text.splitlines():
+        cells = [c.strip() for c in l.strip().strip("|").split("|")]
+        if len(cells) >= 3 and cells[0] == kernel:
+            return float(cells[2])
+    return None
 
 
 def measured_traffic(kernel: str):
@@ -223,6 +248,14 @@ def main():
                       "queries_per_step": N, "pool_pairs": len(pool), "device": props.name,
                       "gcn_arch": getattr(props, "gcnArchName", "")},
            "roofline": roofline}
+    vpw = measured_valu_per_wave("fwd_f16_kernel<16, 16>")
+    if vpw is not None:
+        waves = ((pool[0].W + 15) // 16) * ((pool[0].H + 15) // 16) * 4
+        ach = vpw * waves / (kt["fwd"] * 1e-3) / 1e9
+        out["roofline_alu"] = {"bound": "alu", "kernel": "fwd_f16_kernel<16,16>", "achieved": round(ach, 1),
+                               "peak": VALU_PEAK_GINST, "unit": "G wave64 VALU instructions/s",
+                               "frac": round(ach / VALU_PEAK_GINST, 4), "valu_instructions_per_wave": vpw,
+                               "waves_per_launch": waves}
 
     if not args.only_main:
         legs = set(args.legs.split(","))
