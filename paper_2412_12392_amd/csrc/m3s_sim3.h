@@ -127,33 +127,20 @@ __device__ __forceinline__ bool accumulate_match(const float* T, float X0, float
 }
 
 // Fixed-order fp64 sum of nparts fp32 partials of kPoseVals values each
-// (stride `stride` floats) by a workgroup of NT threads: thread t adds the
-// partials t, t + NT, ... for every value (all loads independent), then a
-// pairwise tree over the threads in LDS.  The order depends on NT and nparts
-// only.  `tree` is LDS of kPoseVals * NT doubles; the sums land in out[0 ..
+// (stride `stride` floats) by a workgroup of NT >= kPoseVals threads: thread
+// v adds value v of the partials 0, 1, ..., nparts - 1 in that order (the
+// threads' reads of one partial are contiguous).  The sums land in out[0 ..
 // kPoseVals) (LDS), visible to the whole workgroup on return.
 template <int NT>
-__device__ void sum_partials(const float* __restrict__ parts, int nparts, int stride, double* tree, double* out) {
+__device__ void sum_partials(const float* __restrict__ parts, int nparts, int stride, double* out) {
+    static_assert(NT >= kPoseVals, "one thread per value");
     const int t = threadIdx.x;
-    double acc[kPoseVals];
-#pragma unroll
-    for (int v = 0; v < kPoseVals; ++v) acc[v] = 0.0;
-    for (int b = t; b < nparts; b += NT) {
-        const float* p = parts + (size_t)b * stride;
-#pragma unroll
-        for (int v = 0; v < kPoseVals; ++v) acc[v] += (double)p[v];
+    if (t < kPoseVals) {
+        double acc = 0.0;
+#pragma unroll 8
+        for (int b = 0; b < nparts; ++b) acc += (double)parts[(size_t)b * stride + t];
+        out[t] = acc;
     }
-#pragma unroll
-    for (int v = 0; v < kPoseVals; ++v) tree[v * NT + t] = acc[v];
-    __syncthreads();
-    for (int h = NT / 2; h > 0; h >>= 1) {
-        if (t < h) {
-#pragma unroll
-            for (int v = 0; v < kPoseVals; ++v) tree[v * NT + t] += tree[v * NT + t + h];
-        }
-        __syncthreads();
-    }
-    if (t < kPoseVals) out[t] = tree[t * NT];
     __syncthreads();
 }
 

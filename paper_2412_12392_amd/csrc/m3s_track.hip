@@ -175,9 +175,8 @@ __global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
 // One workgroup: fixed-order fp64 sum of the nb partials; mode 0 solves and
 // updates the pose, mode 1 writes the outputs at the final pose.
 __global__ void __launch_bounds__(kThreads) track_solve_kernel(TrackArgs A, int nb, int mode) {
-    __shared__ double tree[kVals * kThreads];
     __shared__ double sum[kVals];
-    sum_partials<kThreads>(A.partials, nb, kStride, tree, sum);
+    sum_partials<kThreads>(A.partials, nb, kStride, sum);
     if (threadIdx.x != 0) return;
     if (mode == 0) {
         double step;
