@@ -22,8 +22,9 @@
 //           (keyframe 0 holds the gauge): the edges' blocks summed in LDS in
 //           edge order, one writer per entry, rows written out whole.
 //   solve   one workgroup: blocked right-looking Cholesky in fp64 with
-//           32 x 32 tiles, the diagonal tile factored by one wave in
-//           registers and the panel kept in LDS; blocked substitutions;
+//           32 x 32 tiles, the diagonal tile factored one column per
+//           barrier and the panel kept in LDS; the forward substitution
+//           folded into the factorization, the backward one blocked;
 //           T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  A system that is not positive definite, or a step norm
 //           below step_tol, ends the loop: later launches of the call return
 //           at once.
@@ -398,6 +399,15 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
             const int r = q / kTile, c = q % kTile;
             inv[q] = c <= r ? Dinv[r][c] : 0.0;
         }
+        // Forward substitution folded into the factorization: b_k has taken
+        // every earlier tile's -L_kj y_j, so y_k = Dinv_k b_k now; the rows
+        // below take -L_ik y_k during the trailing update.
+        double yk = 0.0;
+        if (tid < kTile) {
+            for (int t = 0; t <= tid; ++t) yk += Dinv[tid][t] * x[k * kTile + t];
+        }
+        __syncthreads();
+        if (tid < kTile) x[k * kTile + tid] = yk;
         // Panel: L_ik = A_ik Dinv^T, kStageRows rows at a time staged in LDS,
         // four elements per thread.
         const bool in_lds = m <= kPanelRows;
@@ -444,6 +454,14 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
                 else
                     trailing_tile(A, (const double*)(A.M + (long)R0 * np + k * kTile), np, R0, ti, tj, lane);
             }
+            // b_i -= L_ik y_k, one thread per panel row.
+            for (int rr = tid; rr < m; rr += kSolveThreads) {
+                double sacc = 0.0;
+                for (int t = 0; t < kTile; ++t)
+                    sacc += (in_lds ? panel[rr * kPanelStride + t] : A.M[(long)(R0 + rr) * np + k * kTile + t]) *
+                            x[k * kTile + t];
+                x[R0 + rr] -= sacc;
+            }
         }
         __syncthreads();
     }
@@ -452,28 +470,7 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         return;
     }
 
-    // Forward substitution L y = rhs, tile by tile: the rows of tile k first
-    // subtract L[k][0..k) y (32 threads per row), then y_k = Dinv_k b_k.
     const int lane = tid & 31;
-    for (int k = 0; k < nt; ++k) {
-        for (int row = tid >> 5; row < kTile; row += kSolveThreads / 32) {
-            const int R = k * kTile + row;
-            double s = 0.0;
-            for (int c = lane; c < k * kTile; c += 32) s += A.M[(long)R * np + c] * x[c];
-            for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
-            if (lane == 0) x[R] -= s;
-        }
-        const double* inv = A.dinv + (size_t)k * kTile * kTile;
-        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = inv[q];
-        __syncthreads();
-        double y = 0.0;
-        if (tid < kTile) {
-            for (int t = 0; t <= tid; ++t) y += Dinv[tid][t] * x[k * kTile + t];
-        }
-        __syncthreads();
-        if (tid < kTile) x[k * kTile + tid] = y;
-        __syncthreads();
-    }
     // Backward substitution L^T tau = y: column c of tile k first subtracts
     // the rows below the tile, sum of L[R][c] tau[R]; then tau_k = Dinv_k^T b_k.
     for (int k = nt - 1; k >= 0; --k) {
