@@ -75,7 +75,9 @@ __global__ void __launch_bounds__(64) track_init_kernel(const float* __restrict_
 // Solve H tau = -g (7x7 SPD) and apply T <- Exp(tau) o T.  Returns false
 // (pose unchanged) when H is not positive definite.
 __device__ bool solve_and_update(const double* sum, double* T, double* step_norm) {
-    double L[7][7];
+    // Cholesky by rows; each pivot's reciprocal serves its column and both
+    // substitutions (one fp64 division per pivot).
+    double L[7][7], inv[7];
     for (int r = 0; r < 7; ++r)
         for (int c = 0; c < 7; ++c) L[r][c] = 0.0;
     for (int r = 0; r < 7; ++r) {
@@ -85,8 +87,9 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
             if (r == c) {
                 if (!(s > 0.0) || !isfinite(s)) return false;
                 L[r][r] = sqrt(s);
+                inv[r] = 1.0 / L[r][r];
             } else {
-                L[r][c] = s / L[c][c];
+                L[r][c] = s * inv[c];
             }
         }
     }
@@ -94,12 +97,12 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
     for (int r = 0; r < 7; ++r) {
         double s = -sum[28 + r];
         for (int q = 0; q < r; ++q) s -= L[r][q] * y[q];
-        y[r] = s / L[r][r];
+        y[r] = s * inv[r];
     }
     for (int r = 6; r >= 0; --r) {
         double s = y[r];
         for (int q = r + 1; q < 7; ++q) s -= L[q][r] * tau[q];
-        tau[r] = s / L[r][r];
+        tau[r] = s * inv[r];
     }
     double E[12], Tn[12];
     sim3_exp(tau, E);
