@@ -186,12 +186,15 @@ def _with_desc(pair, Dii, Dji):
 
 
 @pytest.mark.parametrize("case", ["near_ties", "exact_ties", "huge", "tiny", "nan_ref", "unnormalised",
-                                  "r4", "r5", "r6"])
+                                  "ref_x200", "ref_x1000", "query_x300", "r4", "r5", "r6"])
 def test_fp16_prefilter_is_exact(m3s, case):
     """The fp16 pre-filtered refine (tile configuration 5) returns the same bits
     as the exact global-memory scan (configuration 0) on adversarial descriptors:
     near-ties within the fp16 error, exact ties, magnitudes outside fp16, values
-    in the fp16 subnormal range, NaN in the reference region, non-unit norms, and
+    in the fp16 subnormal range, NaN in the reference region, non-unit norms,
+    reference magnitudes on either side of the scaled fp16 range (x200 stays in
+    the pre-filter, x1000 sends its regions to the exact scan), query
+    descriptors beyond it (per-query exact scan inside a pre-filtered tile), and
     radii that need two candidate masks or fall back to the exact scan."""
     base = _pair(96, 128, 17)
     rng = np.random.Generator(np.random.PCG64(zlib.crc32(case.encode())))
@@ -215,6 +218,12 @@ def test_fp16_prefilter_is_exact(m3s, case):
     elif case == "unnormalised":
         Dii = Dii * rng.uniform(0.1, 30.0, Dii.shape[:2])[..., None]
         Dji = Dji * rng.uniform(0.1, 30.0, Dji.shape[:2])[..., None]
+    elif case == "ref_x200":
+        Dii = Dii * 200.0
+    elif case == "ref_x1000":
+        Dii = Dii * 1000.0
+    elif case == "query_x300":
+        Dji = Dji * 300.0
     elif case in ("r4", "r5", "r6"):
         prm["refine_radius"] = int(case[1])
     pair = _with_desc(base, Dii, Dji)
