@@ -84,6 +84,8 @@ CASES = [
     ("plain_least_squares", (32, 48, 6), dict(noise=1e-3), dict(huber=float("inf")), True),
     ("full_512x384", (384, 512, 7), dict(noise=1e-3, outlier_frac=0.1), {}, True),
     ("many_blocks", (1024, 1280, 8), dict(noise=1e-3, outlier_frac=0.05), dict(iters=4), True),
+    # More matches than the accumulation grid covers in one stride (2048 workgroups x 1024).
+    ("beyond_grid", (1536, 1536, 15), dict(noise=1e-3, outlier_frac=0.05), dict(iters=3), True),
 ]
 
 
