@@ -460,18 +460,18 @@ def track_fuse_leg(m3s, lib, dev, args):
         g.replay()
     torch.cuda.synchronize()
     el_graph = (time.perf_counter() - t0) / steps
-    ac_ms, _ = _timer(lib, "track_accum")
-    so_ms, _ = _timer(lib, "track_solve")
+    ac_ms, _ = _timer(lib, "track_step")
+    so_ms, _ = _timer(lib, "track_final")
     fu_ms, _ = _timer(lib, "fuse")
     n_match = int(tp.valid.sum())
     iters = prm.iters + 1
     out = {"workload": "512x384 keyframe: tracking pose solve (10 Gauss-Newton iterations + final cost) then "
                        "pointmap fusion; noise 1e-3, 5% outliers",
            "ms_per_frame": round(el * 1e3, 4), "ms_per_frame_graph": round(el_graph * 1e3, 4),
-           "track_accum_avg_us": round(ac_ms * 1e3, 2), "track_solve_avg_us": round(so_ms * 1e3, 2),
-           "launch_pairs_per_frame": iters,
+           "track_step_avg_us": round(ac_ms * 1e3, 2), "track_final_avg_us": round(so_ms * 1e3, 2),
+           "step_launches_per_frame": iters,
            "match_evaluations_per_s": round(n_match * iters / el, 1),
-           "track_accum_algorithmic_GBs": round(POSE_BYTES_PER_MATCH * H * W / (ac_ms * 1e-3) / 1e9, 1),
+           "track_step_algorithmic_GBs": round(POSE_BYTES_PER_MATCH * H * W / (ac_ms * 1e-3) / 1e9, 1),
            "fuse_avg_us": round(fu_ms * 1e3, 2),
            "fuse_algorithmic_GBs": round(FUSE_BYTES_PER_PIXEL * H * W / (fu_ms * 1e-3) / 1e9, 1),
            "fuse_frac_of_hbm_peak": round(FUSE_BYTES_PER_PIXEL * H * W / (fu_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}

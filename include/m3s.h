@@ -362,7 +362,8 @@ void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
  * launch, as "batched_graph").  m3s_timing_read synchronises on the recorded
  * events and returns, for the kernel `name` ("prep", "fwd", "fill", "bwd",
  * "batched_counter", "batched_prep", "batched_fwd", "batched_graph",
- * "track_accum", "track_solve", "fuse" (the vectorised launch),
+ * "track_step" (one Gauss-Newton iteration: the previous system's solve and
+ * the accumulation), "track_final", "fuse" (the vectorised launch),
  * "backend_accum", "backend_edge", "backend_solve"), the
  * summed duration in milliseconds and the number of launches since the last
  * reset.  Meant for benchmarks: the events cost a little time per launch.

@@ -4,25 +4,29 @@
 // Gauss-Newton in an iteratively reweighted least-squares loop (Eq.
 // gauss_newton) for the Sim(3) pose T_kf that maps frame points X^f_f into the
 // keyframe, over the matches of the keyframe's pixels found by the matcher.
-// Two launches per iteration:
+// One launch per iteration:
 //
-//   accum   one lane per match n: x = T Xf[m] with m = idx[n]; ray residual
-//           psi(x) - psi(Xk[n]) (Eq. track_ray) and distance residual
-//           |x| - |Xk[n]| (the small-weight distance term); Jacobians w.r.t. a
-//           left perturbation (Supp. A); weights q / sigma^2 (match confidence
-//           q = sqrt(Qf[m] Qk[n]) gated at q_min, Sec. 3.3) times the Huber
-//           weight of the whitened block norm; one fp32 partial of J^T W J
-//           (upper triangle), J^T W r, robust cost and count per workgroup.
-//   solve   one workgroup: the partials summed in fp64 in a fixed order, the
-//           7x7 system solved by Cholesky and T <- Exp(tau) o T applied
-//           (Eq. 1, left plus on Sim(3)) in fp64.
+//   step    every workgroup first sums the previous iteration's partials in
+//           fp64 in a fixed order, solves the 7x7 system by Cholesky and
+//           applies T <- Exp(tau) o T (Eq. 1, left plus on Sim(3)) in fp64:
+//           the same arithmetic in every workgroup, so every workgroup holds
+//           the same new pose, and workgroup 0 records it.  Then one lane per
+//           match n: x = T Xf[m] with m = idx[n]; ray residual psi(x) -
+//           psi(Xk[n]) (Eq. track_ray) and distance residual |x| - |Xk[n]|
+//           (the small-weight distance term); Jacobians w.r.t. a left
+//           perturbation (Supp. A); weights q / sigma^2 (match confidence q =
+//           sqrt(Qf[m] Qk[n]) gated at q_min, Sec. 3.3) times the Huber weight
+//           of the whitened block norm; one fp32 partial of J^T W J (upper
+//           triangle), J^T W r, robust cost and count per workgroup.
+//   final   one workgroup: the last partials summed (cost and count at the
+//           final pose), the fp32 pose and the statistics written.
 //
-// The kernel boundary orders the partials before their sum, so no workgroup
-// needs a device-scope fence (on this part a device-scope release writes back
-// the XCD's L2).  The pose lives in the workspace in fp64 between launches;
-// the last pair evaluates the cost at the final pose and writes the fp32 pose
-// and the statistics.  Launches are stream-ordered with no host
-// synchronisation, so the whole solve can be captured into a graph.
+// The partials and the fp64 pose are double-buffered by iteration parity, so
+// a launch reads what the previous launch wrote and no workgroup overwrites
+// what another still reads; kernel boundaries order every hand-off (no
+// device-scope fence: on this part a device-scope release writes back the
+// XCD's L2).  Launches are stream-ordered with no host synchronisation, so
+// the whole solve can be captured into a graph.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -39,11 +43,11 @@ constexpr int kVals = kPoseVals;
 constexpr int kStride = 40;         // floats per block partial
 constexpr int kMaxBlocks = 2048;
 
-// Workspace layout (bytes): pose, statistics, counters, then the partials.
-constexpr size_t kOffT = 0;         // double[12]
-constexpr size_t kOffStat = 96;     // double[2]: last step norm, reserved
-constexpr size_t kOffCnt = 128;     // int32[2]: reserved, solved iterations
-constexpr size_t kOffPart = 256;    // float[nblocks * kStride]
+// Workspace layout (bytes): poses, statistics, counters, then the partials.
+constexpr size_t kOffT = 0;         // double[2][12]: pose by iteration parity
+constexpr size_t kOffStat = 192;    // double[2]: last step norm, reserved
+constexpr size_t kOffCnt = 224;     // int32[2]: reserved, solved iterations
+constexpr size_t kOffPart = 256;    // float[2][nblocks * kStride]: partials by iteration parity
 
 struct TrackArgs {
     int N;
@@ -56,11 +60,12 @@ struct TrackArgs {
     double q_min;
     float q_minf;
     RobustWeights rw;
-    double* T64;
+    double* T64;            // [2][12]
     double* stat;
     int32_t* counter;       // [0] reserved, [1] solved iterations
     int32_t* solved;
-    float* partials;
+    float* partials;        // [2][nb * kStride]
+    int nb;
     float* T_out;
     float* info;
 };
@@ -123,11 +128,38 @@ __device__ bool solve_and_update(const double* sum, double* T, double* step_norm
 // together before the arithmetic.
 constexpr int kMatchesPerLane = 4;
 
-__global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
+__global__ void __launch_bounds__(kThreads) track_step_kernel(TrackArgs A, int it) {
     __shared__ float red[kThreads / 64][kVals];
+    __shared__ double sum[kVals];
+    __shared__ double Tn[12];
+    // Pose of the previous iteration (parity buffer); iteration 0 starts from
+    // the initial pose in buffer 0.
+    const double* Tprev = A.T64 + (it > 0 ? 12 * ((it + 1) & 1) : 0);
+    if (it > 0) {
+        // Iteration it - 1's system: the same fixed-order sum and solve in
+        // every workgroup.
+        sum_partials<kThreads>(A.partials + (size_t)((it + 1) & 1) * A.nb * kStride, A.nb, kStride, sum);
+        if (threadIdx.x == 0) {
+            double Tl[12], step;
+            for (int j = 0; j < 12; ++j) Tl[j] = Tprev[j];
+            const bool ok = solve_and_update(sum, Tl, &step);
+            for (int j = 0; j < 12; ++j) Tn[j] = Tl[j];
+            if (blockIdx.x == 0) {
+                double* Tout = A.T64 + 12 * (it & 1);
+                for (int j = 0; j < 12; ++j) Tout[j] = Tl[j];
+                if (ok) {
+                    A.solved[0] += 1;
+                    A.stat[0] = step;
+                }
+            }
+        }
+    } else if (threadIdx.x < 12) {
+        Tn[threadIdx.x] = Tprev[threadIdx.x];
+    }
+    __syncthreads();
     float T[12];
 #pragma unroll
-    for (int i = 0; i < 12; ++i) T[i] = (float)A.T64[i];
+    for (int i = 0; i < 12; ++i) T[i] = (float)Tn[i];
     float acc[kVals];
 #pragma unroll
     for (int i = 0; i < kVals; ++i) acc[i] = 0.f;
@@ -171,30 +203,23 @@ __global__ void __launch_bounds__(kThreads) track_accum_kernel(TrackArgs A) {
         float v = 0.f;
 #pragma unroll
         for (int w = 0; w < kThreads / 64; ++w) v += red[w][threadIdx.x];
-        A.partials[(size_t)blockIdx.x * kStride + threadIdx.x] = v;
+        A.partials[((size_t)(it & 1) * A.nb + blockIdx.x) * kStride + threadIdx.x] = v;
     }
 }
 
-// One workgroup: fixed-order fp64 sum of the nb partials; mode 0 solves and
-// updates the pose, mode 1 writes the outputs at the final pose.
-__global__ void __launch_bounds__(kThreads) track_solve_kernel(TrackArgs A, int nb, int mode) {
+// One workgroup: the last iteration's partials summed (cost and count at the
+// final pose), the fp32 pose and the statistics written.
+__global__ void __launch_bounds__(kThreads) track_final_kernel(TrackArgs A, int it) {
     __shared__ double sum[kVals];
-    sum_partials<kThreads>(A.partials, nb, kStride, sum);
+    sum_partials<kThreads>(A.partials + (size_t)(it & 1) * A.nb * kStride, A.nb, kStride, sum);
     if (threadIdx.x != 0) return;
-    if (mode == 0) {
-        double step;
-        if (solve_and_update(sum, A.T64, &step)) {
-            A.solved[0] += 1;
-            A.stat[0] = step;
-        }
-    } else {
-        for (int j = 0; j < 12; ++j) A.T_out[j] = (float)A.T64[j];
-        if (A.info) {
-            A.info[0] = (float)sum[35];
-            A.info[1] = (float)sum[36];
-            A.info[2] = (float)A.solved[0];
-            A.info[3] = (float)A.stat[0];
-        }
+    const double* T = A.T64 + 12 * (it & 1);
+    for (int j = 0; j < 12; ++j) A.T_out[j] = (float)T[j];
+    if (A.info) {
+        A.info[0] = (float)sum[35];
+        A.info[1] = (float)sum[36];
+        A.info[2] = (float)A.solved[0];
+        A.info[3] = (float)A.stat[0];
     }
 }
 
@@ -259,7 +284,7 @@ int track_blocks(int N) {
     return nb < 1 ? 1 : (nb > kMaxBlocks ? kMaxBlocks : nb);
 }
 
-size_t track_workspace_bytes(int N) { return kOffPart + (size_t)track_blocks(N) * kStride * sizeof(float); }
+size_t track_workspace_bytes(int N) { return kOffPart + 2 * (size_t)track_blocks(N) * kStride * sizeof(float); }
 
 hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* idx, const uint8_t* valid,
                         const float* Qf, const float* Qk, float q_min, float sigma_ray, float sigma_dist, float huber,
@@ -280,15 +305,16 @@ hipError_t launch_track(int N, const float* Xk, const float* Xf, const int32_t* 
     A.T_out = T;
     A.info = info;
     const int nb = track_blocks(N);
+    A.nb = nb;
     track_init_kernel<<<1, 64, 0, s>>>(T, A.T64, A.counter, A.stat);
     for (int it = 0; it <= iters; ++it) {
-        timer_begin("track_accum", s);
-        track_accum_kernel<<<nb, kThreads, 0, s>>>(A);
-        timer_end(s);
-        timer_begin("track_solve", s);
-        track_solve_kernel<<<1, kThreads, 0, s>>>(A, nb, it < iters ? 0 : 1);
+        timer_begin("track_step", s);
+        track_step_kernel<<<nb, kThreads, 0, s>>>(A, it);
         timer_end(s);
     }
+    timer_begin("track_final", s);
+    track_final_kernel<<<1, kThreads, 0, s>>>(A, iters);
+    timer_end(s);
     return hipGetLastError();
 }
 
