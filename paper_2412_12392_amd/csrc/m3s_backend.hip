@@ -188,10 +188,11 @@ __global__ void __launch_bounds__(kThreads) backend_accum_kernel(BackendArgs A, 
 // (iterations only) A = Ad(T_WC[i]^-1), A^T H_e A and A^T g_e.
 __global__ void __launch_bounds__(kThreads) backend_edge_kernel(BackendArgs A, int final_pass) {
     __shared__ double sys[kStride];
+    __shared__ double part[kThreads / kVals * kVals];
     __shared__ double Ad[49];
     if (!final_pass && A.state[0]) return;
     const int e = blockIdx.x;
-    sum_partials<kThreads>(A.partials + (size_t)e * A.blocks_per_edge * kStride, A.blocks_per_edge, kStride, sys);
+    sum_partials<kThreads>(A.partials + (size_t)e * A.blocks_per_edge * kStride, A.blocks_per_edge, kStride, part, sys);
     if (threadIdx.x < kVals) A.edge_sys[(size_t)e * kStride + threadIdx.x] = sys[threadIdx.x];
     if (final_pass) return;
     const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];

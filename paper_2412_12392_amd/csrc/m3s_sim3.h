@@ -127,19 +127,30 @@ __device__ __forceinline__ bool accumulate_match(const float* T, float X0, float
 }
 
 // Fixed-order fp64 sum of nparts fp32 partials of kPoseVals values each
-// (stride `stride` floats) by a workgroup of NT >= kPoseVals threads: thread
-// v adds value v of the partials 0, 1, ..., nparts - 1 in that order (the
-// threads' reads of one partial are contiguous).  The sums land in out[0 ..
-// kPoseVals) (LDS), visible to the whole workgroup on return.
+// (stride `stride` floats) by a workgroup of NT threads: G = NT / kPoseVals
+// groups of kPoseVals threads, thread (g, v) adding value v of the partials
+// g, g + G, g + 2G, ... in that order (a group's reads of one partial are
+// contiguous, and every group's reads are in flight together); then thread v
+// adds the G group sums in group order.  `part` is LDS of G * kPoseVals
+// doubles; the sums land in out[0 .. kPoseVals) (LDS), visible to the whole
+// workgroup on return.
 template <int NT>
-__device__ void sum_partials(const float* __restrict__ parts, int nparts, int stride, double* out) {
-    static_assert(NT >= kPoseVals, "one thread per value");
-    const int t = threadIdx.x;
-    if (t < kPoseVals) {
+__device__ void sum_partials(const float* __restrict__ parts, int nparts, int stride, double* part, double* out) {
+    constexpr int G = NT / kPoseVals;
+    static_assert(G >= 1, "one thread per value at least");
+    const int t = threadIdx.x, g = t / kPoseVals, v = t - g * kPoseVals;
+    if (g < G) {
         double acc = 0.0;
 #pragma unroll 8
-        for (int b = 0; b < nparts; ++b) acc += (double)parts[(size_t)b * stride + t];
-        out[t] = acc;
+        for (int b = g; b < nparts; b += G) acc += (double)parts[(size_t)b * stride + v];
+        part[g * kPoseVals + v] = acc;
+    }
+    __syncthreads();
+    if (t < kPoseVals) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < G; ++k) s += part[k * kPoseVals + t];
+        out[t] = s;
     }
     __syncthreads();
 }

@@ -131,6 +131,7 @@ constexpr int kMatchesPerLane = 4;
 __global__ void __launch_bounds__(kThreads) track_step_kernel(TrackArgs A, int it) {
     __shared__ float red[kThreads / 64][kVals];
     __shared__ double sum[kVals];
+    __shared__ double part[kThreads / kVals * kVals];
     __shared__ double Tn[12];
     // Pose of the previous iteration (parity buffer); iteration 0 starts from
     // the initial pose in buffer 0.
@@ -138,7 +139,7 @@ __global__ void __launch_bounds__(kThreads) track_step_kernel(TrackArgs A, int i
     if (it > 0) {
         // Iteration it - 1's system: the same fixed-order sum and solve in
         // every workgroup.
-        sum_partials<kThreads>(A.partials + (size_t)((it + 1) & 1) * A.nb * kStride, A.nb, kStride, sum);
+        sum_partials<kThreads>(A.partials + (size_t)((it + 1) & 1) * A.nb * kStride, A.nb, kStride, part, sum);
         if (threadIdx.x == 0) {
             double Tl[12], step;
             for (int j = 0; j < 12; ++j) Tl[j] = Tprev[j];
@@ -211,7 +212,8 @@ __global__ void __launch_bounds__(kThreads) track_step_kernel(TrackArgs A, int i
 // final pose), the fp32 pose and the statistics written.
 __global__ void __launch_bounds__(kThreads) track_final_kernel(TrackArgs A, int it) {
     __shared__ double sum[kVals];
-    sum_partials<kThreads>(A.partials + (size_t)(it & 1) * A.nb * kStride, A.nb, kStride, sum);
+    __shared__ double part[kThreads / kVals * kVals];
+    sum_partials<kThreads>(A.partials + (size_t)(it & 1) * A.nb * kStride, A.nb, kStride, part, sum);
     if (threadIdx.x != 0) return;
     const double* T = A.T64 + 12 * (it & 1);
     for (int j = 0; j < 12; ++j) A.T_out[j] = (float)T[j];
