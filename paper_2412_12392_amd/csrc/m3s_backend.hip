@@ -471,21 +471,13 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         return;
     }
 
-    const int lane = tid & 31;
-    // Backward substitution L^T tau = y: column c of tile k first subtracts
-    // the rows below the tile, sum of L[R][c] tau[R]; then tau_k = Dinv_k^T b_k.
+    // Backward substitution L^T tau = y, tile by tile from the last: tau_k =
+    // Dinv_k^T y_k (y_k has taken every later tile's share), then every earlier
+    // entry c takes -sum over the tile's rows r of L[r][c] tau_r: reads along
+    // rows of L, contiguous across threads.
     for (int k = nt - 1; k >= 0; --k) {
-        for (int row = tid >> 5; row < kTile; row += kSolveThreads / 32) {
-            const int C = k * kTile + row;
-            double s = 0.0;
-            for (int r = (k + 1) * kTile + lane; r < np; r += 32) s += A.M[(long)r * np + C] * x[r];
-            for (int o = 16; o > 0; o >>= 1) s += __shfl_xor(s, o, 32);
-            if (lane == 0) part[row] = s;
-        }
         const double* inv = A.dinv + (size_t)k * kTile * kTile;
         for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = inv[q];
-        __syncthreads();
-        if (tid < kTile) x[k * kTile + tid] -= part[tid];
         __syncthreads();
         double y = 0.0;
         if (tid < kTile) {
@@ -493,6 +485,13 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         }
         __syncthreads();
         if (tid < kTile) x[k * kTile + tid] = y;
+        __syncthreads();
+        for (int c = tid; c < k * kTile; c += kSolveThreads) {
+            double sacc = 0.0;
+#pragma unroll 8
+            for (int r = 0; r < kTile; ++r) sacc += A.M[(long)(k * kTile + r) * np + c] * x[k * kTile + r];
+            x[c] -= sacc;
+        }
         __syncthreads();
     }
 
