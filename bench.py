@@ -247,7 +247,11 @@ def main():
                                   "confidences gated at 1.5, identity init",
                       "queries_per_step": N, "pool_pairs": len(pool), "device": props.name,
                       "gcn_arch": getattr(props, "gcnArchName", "")},
-           "roofline": roofline}
+           "roofline": roofline,
+           # The paper's own timings on its own hardware (matching table, Sec. 4): context, not a target.
+           "paper_context": {"hardware": "NVIDIA RTX 4090", "match_ms_projection": 0.5,
+                             "match_ms_projection_refine": 2.0, "system_fps": 15,
+                             "this_ms_per_step": round(ms_per_step, 5)}}
     vpw = measured_valu_per_wave("fwd_f16_kernel<16, 16>")
     if vpw is not None:
         waves = ((pool[0].W + 15) // 16) * ((pool[0].H + 15) // 16) * 4
