@@ -327,6 +327,10 @@ def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
            "matches_per_s": round(N * args.steps / el, 1), "ms_per_step": round(el / args.steps * 1e3, 5),
            "kernels": kt,
            "bwd_achieved_GBs": round(BWD_BYTES_PER_QUERY * N / (bwd_us * 1e-6) / 1e9, 1)}
+    # Whole step: forward (with xhat) plus backward bytes over the measured step time.
+    step_gbs = (FWD_BYTES_PER_QUERY + 12 + BWD_BYTES_PER_QUERY) * N * args.steps / el / 1e9
+    res["step_algorithmic_GBs"] = round(step_gbs, 1)
+    res["step_frac_of_hbm_peak"] = round(step_gbs / HBM_PEAK_GBS, 4)
     log("fwd+bwd:", res)
     return res
 
@@ -400,7 +404,8 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
            "graph_launch_ms_events": round(graph_ms, 4),
            "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
            "speedup_vs_per_pair": round(el_p / el_b, 3), "launch": {"grid": grid, "tile_config": tile},
-           "algorithmic_GBs": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9, 1)}
+           "algorithmic_GBs": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9, 1),
+           "frac_of_hbm_peak": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9 / HBM_PEAK_GBS, 4)}
     log("batched:", res)
     del ws, pw, outs, edges
     torch.cuda.empty_cache()
