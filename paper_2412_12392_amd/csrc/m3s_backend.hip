@@ -382,14 +382,22 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
             is = is * fma(-0.5 * dg * is, is, 1.5);
             is = is * fma(-0.5 * dg * is, is, 1.5);
             const double sd = dg * is, idg = is * is;
+            // Each entry has at most one LDS output (D, V or Dinv), chosen by
+            // selects so that the step is one guarded store rather than a chain
+            // of branches; column c of L goes to memory.
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
                 const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                if (q > c && q <= r) D[r][q] = drq[h] - drc[h] * dqc[h] * idg;
-                else if (r > c && q <= c) V[r][q] = vrq[h] - drc[h] * vcq[h] * idg;
-                else if (r == c && q <= c) Dinv[c][q] = vcq[h] * is;
-                else if (q == c && r > c) Mk[(long)r * np + c] = drc[h] * is;
+                const bool d_upd = q > c && q <= r;
+                const bool v_upd = r > c && q <= c;
+                const bool i_row = r == c && q <= c;
+                const double a = d_upd ? drq[h] : vrq[h];
+                const double b = d_upd ? dqc[h] : vcq[h];
+                const double val = i_row ? vcq[h] * is : a - drc[h] * b * idg;
+                double* dst = d_upd ? &D[r][q] : (v_upd ? &V[r][q] : &Dinv[c][q]);
+                if (d_upd || v_upd || i_row) *dst = val;
+                if (q == c && r > c) Mk[(long)r * np + c] = drc[h] * is;
             }
             if (tid == 0) Mk[(long)c * np + c] = sd;
             __syncthreads();
