@@ -418,14 +418,30 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         __syncthreads();
         if (tid < kTile) x[k * kTile + tid] = yk;
         // Panel: L_ik = A_ik Dinv^T, kStageRows rows at a time staged in LDS,
-        // four elements per thread.
+        // four elements per thread.  The raw rows of the next stage are read
+        // into registers while the current one is computed (this stage writes
+        // only its own rows).
         const bool in_lds = m <= kPanelRows;
-        for (int r0 = 0; r0 < m; r0 += kStageRows) {
-            for (int q = tid; q < kStageRows * kTile; q += kSolveThreads) {
+        static_assert(kStageRows * kTile % kSolveThreads == 0, "whole raw values per thread");
+        constexpr int kL = kStageRows * kTile / kSolveThreads;
+        double raw[kL];
+        auto read_stage = [&](int r0) {
+#pragma unroll
+            for (int j = 0; j < kL; ++j) {
+                const int q = tid + j * kSolveThreads;
                 const int rr = r0 + q / kTile, t = q % kTile;
-                if (rr < m) stage[(q / kTile) * kPanelStride + t] = A.M[(long)(R0 + rr) * np + k * kTile + t];
+                raw[j] = rr < m ? A.M[(long)(R0 + rr) * np + k * kTile + t] : 0.0;
+            }
+        };
+        if (m > 0) read_stage(0);
+        for (int r0 = 0; r0 < m; r0 += kStageRows) {
+#pragma unroll
+            for (int j = 0; j < kL; ++j) {
+                const int q = tid + j * kSolveThreads;
+                stage[(q / kTile) * kPanelStride + q % kTile] = raw[j];
             }
             __syncthreads();
+            if (r0 + kStageRows < m) read_stage(r0 + kStageRows);
             // Column c of four rows per thread: each Dinv[c][t] is read once for
             // the four rows (same products and order per entry as a row-wise dot).
             const int c = tid % kTile;
