@@ -344,6 +344,20 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         for (int q = tid; q < kTile * kTile; q += kSolveThreads) V[q / kTile][q % kTile] = (q / kTile == q % kTile) ? 1.0 : 0.0;
         const int R0 = (k + 1) * kTile;
         const int m = np - R0;
+        static_assert(kStageRows * kTile % kSolveThreads == 0, "whole raw values per thread");
+        constexpr int kL = kStageRows * kTile / kSolveThreads;
+        double raw[kL];
+        auto read_stage = [&](int r0) {
+#pragma unroll
+            for (int j = 0; j < kL; ++j) {
+                const int q = tid + j * kSolveThreads;
+                const int rr = r0 + q / kTile, t = q % kTile;
+                raw[j] = rr < m ? A.M[(long)(R0 + rr) * np + k * kTile + t] : 0.0;
+            }
+        };
+        // The first panel stage's raw rows (below this tile, which the factor
+        // does not write) are read before the factor, to arrive during it.
+        if (m > 0) read_stage(0);
         __syncthreads();
         // Factor the tile with the whole workgroup, one column c per step and
         // one barrier per step: with d = D[c][c], the entries below take
@@ -422,18 +436,6 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         // into registers while the current one is computed (this stage writes
         // only its own rows).
         const bool in_lds = m <= kPanelRows;
-        static_assert(kStageRows * kTile % kSolveThreads == 0, "whole raw values per thread");
-        constexpr int kL = kStageRows * kTile / kSolveThreads;
-        double raw[kL];
-        auto read_stage = [&](int r0) {
-#pragma unroll
-            for (int j = 0; j < kL; ++j) {
-                const int q = tid + j * kSolveThreads;
-                const int rr = r0 + q / kTile, t = q % kTile;
-                raw[j] = rr < m ? A.M[(long)(R0 + rr) * np + k * kTile + t] : 0.0;
-            }
-        };
-        if (m > 0) read_stage(0);
         for (int r0 = 0; r0 < m; r0 += kStageRows) {
 #pragma unroll
             for (int j = 0; j < kL; ++j) {
