@@ -501,9 +501,25 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
     // Dinv_k^T y_k (y_k has taken every later tile's share), then every earlier
     // entry c takes -sum over the tile's rows r of L[r][c] tau_r: reads along
     // rows of L, contiguous across threads.
+    // A tile's reads of Dinv and of the L entries of each thread's first
+    // column are issued together, before either is needed.
     for (int k = nt - 1; k >= 0; --k) {
         const double* inv = A.dinv + (size_t)k * kTile * kTile;
-        for (int q = tid; q < kTile * kTile; q += kSolveThreads) Dinv[q / kTile][q % kTile] = inv[q];
+        constexpr int kI = kTile * kTile / kSolveThreads;
+        double dv[kI];
+#pragma unroll
+        for (int j = 0; j < kI; ++j) dv[j] = inv[tid + j * kSolveThreads];
+        const bool first = tid < k * kTile;
+        double lr[kTile];
+        if (first) {
+#pragma unroll
+            for (int r = 0; r < kTile; ++r) lr[r] = A.M[(long)(k * kTile + r) * np + tid];
+        }
+#pragma unroll
+        for (int j = 0; j < kI; ++j) {
+            const int q = tid + j * kSolveThreads;
+            Dinv[q / kTile][q % kTile] = dv[j];
+        }
         __syncthreads();
         double y = 0.0;
         if (tid < kTile) {
@@ -512,7 +528,13 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         __syncthreads();
         if (tid < kTile) x[k * kTile + tid] = y;
         __syncthreads();
-        for (int c = tid; c < k * kTile; c += kSolveThreads) {
+        if (first) {
+            double sacc = 0.0;
+#pragma unroll
+            for (int r = 0; r < kTile; ++r) sacc += lr[r] * x[k * kTile + r];
+            x[tid] -= sacc;
+        }
+        for (int c = tid + kSolveThreads; c < k * kTile; c += kSolveThreads) {
             double sacc = 0.0;
 #pragma unroll 8
             for (int r = 0; r < kTile; ++r) sacc += A.M[(long)(k * kTile + r) * np + c] * x[k * kTile + r];
