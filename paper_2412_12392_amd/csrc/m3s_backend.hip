@@ -282,10 +282,12 @@ __device__ __forceinline__ double* tile_ptr(const BackendArgs& A, int ti, int tj
 
 // Trailing update of one 32 x 32 tile (ti, tj), tj <= ti, of the lower
 // triangle below tile column k: M[R][C] -= L[R] . L[C], a 4 x 4 block per lane
-// of one wave.  P points at the panel rows (stride ps doubles): LDS or M.
+// of one wave.  P points at the panel rows (stride ps doubles): LDS or M.  Tile
+// (0, 0) is the next diagonal tile: its lower triangle goes to dl (the LDS tile
+// the next factor reads, stride kTile + 1) instead of M.
 template <typename PanelPtr>
 __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, int ps, int R0, int ti, int tj,
-                                              int lane) {
+                                              int lane, double* dl) {
     const int np = A.np;
     const int r0 = (lane >> 3) * 4, c0 = (lane & 7) * 4;
     const int ra = ti * kTile + r0, ca = tj * kTile + c0;
@@ -312,7 +314,11 @@ __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, 
     for (int u = 0; u < 4; ++u)
 #pragma unroll
         for (int v = 0; v < 4; ++v)
-            if (ti != tj || c0 + v <= r0 + u) A.M[(long)(R0 + ra + u) * np + R0 + ca + v] = cur[u][v] - acc[u][v];
+            if (ti != tj || c0 + v <= r0 + u) {
+                const double val = cur[u][v] - acc[u][v];
+                if (ti == 0 && tj == 0) dl[(r0 + u) * (kTile + 1) + c0 + v] = val;
+                else A.M[(long)(R0 + ra + u) * np + R0 + ca + v] = val;
+            }
 }
 
 // One workgroup: assemble the reduced system, factor it (blocked Cholesky),
@@ -340,7 +346,10 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
     bool failed = false;  // the same in every thread: decided from LDS values read after a barrier
     for (int k = 0; k < nt; ++k) {
         double* Mk = tile_ptr(A, k, k);
-        for (int q = tid; q < kTile * kTile; q += kSolveThreads) D[q / kTile][q % kTile] = Mk[(long)(q / kTile) * np + q % kTile];
+        // Tile 0 comes from M; every later diagonal tile was left in D by the
+        // previous trailing update (its lower triangle, the only part read).
+        if (k == 0)
+            for (int q = tid; q < kTile * kTile; q += kSolveThreads) D[q / kTile][q % kTile] = Mk[(long)(q / kTile) * np + q % kTile];
         for (int q = tid; q < kTile * kTile; q += kSolveThreads) V[q / kTile][q % kTile] = (q / kTile == q % kTile) ? 1.0 : 0.0;
         const int R0 = (k + 1) * kTile;
         const int m = np - R0;
@@ -477,9 +486,9 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
                 while ((ti + 1) * (ti + 2) / 2 <= tix) ++ti;
                 const int tj = tix - ti * (ti + 1) / 2;
                 if (in_lds)
-                    trailing_tile(A, (const double*)panel, kPanelStride, R0, ti, tj, lane);
+                    trailing_tile(A, (const double*)panel, kPanelStride, R0, ti, tj, lane, &D[0][0]);
                 else
-                    trailing_tile(A, (const double*)(A.M + (long)R0 * np + k * kTile), np, R0, ti, tj, lane);
+                    trailing_tile(A, (const double*)(A.M + (long)R0 * np + k * kTile), np, R0, ti, tj, lane, &D[0][0]);
             }
             // b_i -= L_ik y_k, one thread per panel row.
             for (int rr = tid; rr < m; rr += kSolveThreads) {
