@@ -277,7 +277,13 @@ def main():
     if args.copy_calibration:
         out["copy_calibration"] = copy_calibration(torch, dev)
     if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline(pool_pairs[0], args.cpu_seconds)
+        # Pair 0 once more in the default launch (the legs above changed tile
+        # configurations), for the agreement statement on the oracle's output.
+        fwd_step(0)
+        torch.cuda.synchronize()
+        out["cpu_baseline"], ora = cpu_baseline(pool_pairs[0], args.cpu_seconds)
+        out["parity"] = parity_statement(pool[0].res, ora)
+        log("parity vs oracle:", out["parity"])
     print(json.dumps(out), flush=True)
 
 
@@ -576,7 +582,7 @@ def cpu_baseline(pair, seconds):
     import oracle
     lib = oracle.load()
     args = dict(oracle.DEFAULTS, K=pair.K, r=pair.r)
-    oracle.match_pair(pair)  # warm-up (thread pool)
+    ora = oracle.match_pair(pair)  # warm-up (thread pool)
     calls = 0
     t0 = time.perf_counter()
     while True:
@@ -589,7 +595,33 @@ def cpu_baseline(pair, seconds):
     return {"value": round(N * calls / el, 1), "unit": "matches/s", "cores": oracle.max_threads(lib),
             "kind": "oracle", "sample": "%d repeated forward passes over one 512x384 pair (%d queries each), "
                                         "%.1f s, fp64 C with OpenMP over queries" % (calls, N, el),
-            "host_cpus": os.cpu_count()}
+            "host_cpus": os.cpu_count()}, ora
+
+
+def parity_statement(res, ora):
+    """This run's forward on the benchmark pair against the oracle's, on the
+    matching contract: valid flags agree on >= 99.9 % of queries; p* within
+    1e-3 px and theta within 1e-5 rad where both are valid; idx identical where
+    both are valid, the top-two window scores differ by more than 1e-5 and p*
+    is at least 1e-3 px from a rounding boundary in both axes."""
+    p = res.p.cpu().numpy().astype(np.float64).reshape(-1, 2)
+    idx = res.idx.cpu().numpy().astype(np.int64).reshape(-1)
+    vg = res.valid.cpu().numpy().astype(bool).reshape(-1)
+    th = res.theta.cpu().numpy().astype(np.float64).reshape(-1)
+    po = np.asarray(ora["p"], np.float64).reshape(-1, 2)
+    vo = np.asarray(ora["valid"], bool).reshape(-1)
+    both = vg & vo
+    frac = po - np.floor(po)
+    straddle = (np.abs(frac - 0.5) < 1e-3).any(-1)
+    comp = both & (np.asarray(ora["gap"]).reshape(-1) > 1e-5) & ~straddle
+    agree = float((vg == vo).mean())
+    dp = float(np.abs(p - po).max(-1)[both].max()) if both.any() else 0.0
+    dth = float(np.abs(th - np.asarray(ora["theta"]).reshape(-1))[both].max()) if both.any() else 0.0
+    mism = int((idx != np.asarray(ora["idx"]).reshape(-1))[comp].sum())
+    return {"queries": int(vg.size), "valid_gpu": int(vg.sum()), "valid_oracle": int(vo.sum()),
+            "valid_agreement": round(agree, 6), "max_dp_px": dp, "max_dtheta": dth,
+            "idx_compared": int(comp.sum()), "idx_mismatch": mism,
+            "pass": bool(agree >= 0.999 and dp <= 1e-3 and dth <= 1e-5 and mism == 0)}
 
 
 if __name__ == "__main__":
