@@ -376,53 +376,80 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         // row c of Dinv = L_kk^-1 = V[c] / sqrt(d), go to other arrays.  Every
         // thread reads the same pivot after a barrier, so the decision to stop
         // is the same in every thread.
-        for (int c = 0; c < kTile; ++c) {
+        // Two columns per step: every thread also forms what column c + 1 holds
+        // after column c's update (its entries and pivot) from the values it
+        // reads, so a step's writes (entries right of c + 1, rows of V below
+        // c + 1, Dinv, M) again touch nothing the step reads.
+        static_assert(kTile % 2 == 0, "column pairs");
+        for (int c = 0; c < kTile; c += 2) {
+            const int c1 = c + 1;
             // Two entries per thread.  Their operands (all inside the tile) are
-            // read unconditionally together with the pivot, so one LDS round
+            // read unconditionally together with the pivots, so one LDS round
             // trip serves the step.
             static_assert(kTile * kTile % kSolveThreads == 0, "whole entries per thread");
             constexpr int kH = kTile * kTile / kSolveThreads;
-            double drc[kH], dqc[kH], drq[kH], vcq[kH], vrq[kH];
+            double arc[kH], arc1[kH], aqc[kH], aqc1[kH], arq[kH], vcq[kH], vc1q[kH], vrq[kH];
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
                 const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                drc[h] = D[r][c]; dqc[h] = D[q][c]; drq[h] = D[r][q];
-                vcq[h] = V[c][q]; vrq[h] = V[r][q];
+                arc[h] = D[r][c]; arc1[h] = D[r][c1]; aqc[h] = D[q][c]; aqc1[h] = D[q][c1]; arq[h] = D[r][q];
+                vcq[h] = V[c][q]; vc1q[h] = V[c1][q]; vrq[h] = V[r][q];
             }
-            const double dg = D[c][c];
+            const double dg = D[c][c], e = D[c1][c], f = D[c1][c1];
             // Keeps the reads above here (no instruction): issued together
             // rather than one branch at a time below.
-            __asm__ volatile("" :: "v"(drc[0]), "v"(dqc[0]), "v"(drq[0]), "v"(vcq[0]), "v"(vrq[0]),
-                             "v"(drc[1]), "v"(dqc[1]), "v"(drq[1]), "v"(vcq[1]), "v"(vrq[1]), "v"(dg));
+            __asm__ volatile("" :: "v"(arc[0]), "v"(arc1[0]), "v"(aqc[0]), "v"(aqc1[0]), "v"(arq[0]),
+                             "v"(vcq[0]), "v"(vc1q[0]), "v"(vrq[0]), "v"(dg), "v"(e), "v"(f));
+            __asm__ volatile("" :: "v"(arc[1]), "v"(arc1[1]), "v"(aqc[1]), "v"(aqc1[1]), "v"(arq[1]),
+                             "v"(vcq[1]), "v"(vc1q[1]), "v"(vrq[1]));
             if (!(dg > 0.0) || !isfinite(dg)) {
                 failed = true;
                 break;
             }
-            // 1/sqrt(d): hardware estimate and two Newton steps (short dependent
-            // chain per column); sqrt(d) = d / sqrt(d).
+            // 1/sqrt(d): hardware estimate and two Newton steps; sqrt(d) = d / sqrt(d).
             double is = __builtin_amdgcn_rsq(dg);
             is = is * fma(-0.5 * dg * is, is, 1.5);
             is = is * fma(-0.5 * dg * is, is, 1.5);
             const double sd = dg * is, idg = is * is;
-            // Each entry has at most one LDS output (D, V or Dinv), chosen by
-            // selects so that the step is one guarded store rather than a chain
-            // of branches; column c of L goes to memory.
+            // Pivot of column c + 1 after column c's update.
+            const double d1 = f - e * e * idg;
+            if (!(d1 > 0.0) || !isfinite(d1)) {
+                failed = true;
+                break;
+            }
+            double is1 = __builtin_amdgcn_rsq(d1);
+            is1 = is1 * fma(-0.5 * d1 * is1, is1, 1.5);
+            is1 = is1 * fma(-0.5 * d1 * is1, is1, 1.5);
+            const double sd1 = d1 * is1, idg1 = is1 * is1;
+            // Each entry has at most one LDS output (D, V or a row of Dinv),
+            // chosen by selects; columns c and c + 1 of L go to memory.
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
                 const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                const bool d_upd = q > c && q <= r;
-                const bool v_upd = r > c && q <= c;
-                const bool i_row = r == c && q <= c;
-                const double a = d_upd ? drq[h] : vrq[h];
-                const double b = d_upd ? dqc[h] : vcq[h];
-                const double val = i_row ? vcq[h] * is : a - drc[h] * b * idg;
-                double* dst = d_upd ? &D[r][q] : (v_upd ? &V[r][q] : &Dinv[c][q]);
-                if (d_upd || v_upd || i_row) *dst = val;
-                if (q == c && r > c) Mk[(long)r * np + c] = drc[h] * is;
+                const bool d_upd = q > c1 && q <= r;
+                const bool v_upd = r > c1 && q <= c1;
+                const bool i_row0 = r == c && q <= c;
+                const bool i_row1 = r == c1 && q <= c1;
+                // After column c: entry (r, q) of D or V, entry (q, c + 1) of D
+                // or (c + 1, q) of V, and entry (r, c + 1) of D.
+                const double x = d_upd ? arq[h] : vrq[h];
+                const double y = d_upd ? aqc[h] : vcq[h];
+                const double z = d_upd ? aqc1[h] : vc1q[h];
+                const double p1 = x - arc[h] * y * idg;
+                const double p2 = z - e * y * idg;
+                const double prc1 = arc1[h] - arc[h] * e * idg;
+                const double val = i_row0 ? vcq[h] * is : (i_row1 ? p1 * is1 : p1 - prc1 * p2 * idg1);
+                double* dst = d_upd ? &D[r][q] : (v_upd ? &V[r][q] : (i_row0 ? &Dinv[c][q] : &Dinv[c1][q]));
+                if (d_upd || v_upd || i_row0 || i_row1) *dst = val;
+                if (q == c && r > c) Mk[(long)r * np + c] = arc[h] * is;
+                if (q == c1 && r > c1) Mk[(long)r * np + c1] = prc1 * is1;
             }
-            if (tid == 0) Mk[(long)c * np + c] = sd;
+            if (tid == 0) {
+                Mk[(long)c * np + c] = sd;
+                Mk[(long)c1 * np + c1] = sd1;
+            }
             __syncthreads();
         }
         if (failed) break;
