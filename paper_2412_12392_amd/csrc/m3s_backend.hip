@@ -368,18 +368,17 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         // does not write) are read before the factor, to arrive during it.
         if (m > 0) read_stage(0);
         __syncthreads();
-        // Factor the tile with the whole workgroup, one column c per step and
-        // one barrier per step: with d = D[c][c], the entries below take
+        // Factor the tile with the whole workgroup, one barrier per step.  Per
+        // column c, with d = D[c][c], the entries below take
         // D[r][q] -= D[r][c] D[q][c] / d and the rows of the running inverse
-        // V[r][q] -= D[r][c] V[c][q] / d (r > c), both from values no thread
-        // writes in that step; the scaled outputs, column c of L (to M) and
-        // row c of Dinv = L_kk^-1 = V[c] / sqrt(d), go to other arrays.  Every
-        // thread reads the same pivot after a barrier, so the decision to stop
-        // is the same in every thread.
-        // Two columns per step: every thread also forms what column c + 1 holds
-        // after column c's update (its entries and pivot) from the values it
-        // reads, so a step's writes (entries right of c + 1, rows of V below
-        // c + 1, Dinv, M) again touch nothing the step reads.
+        // V[r][q] -= D[r][c] V[c][q] / d (r > c); the scaled outputs, column c
+        // of L (to M) and row c of Dinv = L_kk^-1 = V[c] / sqrt(d), go to other
+        // arrays.  A step takes two columns: every thread also forms what
+        // column c + 1 holds after column c's update (its entries and pivot)
+        // from the values it reads, so a step's writes (entries right of c + 1,
+        // rows of V below c + 1, Dinv, M) touch nothing the step reads.  Every
+        // thread forms the same pivots from the same values read after a
+        // barrier, so the decision to stop is the same in every thread.
         static_assert(kTile % 2 == 0, "column pairs");
         for (int c = 0; c < kTile; c += 2) {
             const int c1 = c + 1;
