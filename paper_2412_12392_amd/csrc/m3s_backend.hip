@@ -379,76 +379,89 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         // rows of V below c + 1, Dinv, M) touch nothing the step reads.  Every
         // thread forms the same pivots from the same values read after a
         // barrier, so the decision to stop is the same in every thread.
-        static_assert(kTile % 2 == 0, "column pairs");
-        for (int c = 0; c < kTile; c += 2) {
-            const int c1 = c + 1;
+        constexpr int kC = 4;  // columns per step
+        static_assert(kTile % kC == 0, "whole column groups");
+        for (int c = 0; c < kTile; c += kC) {
             // Two entries per thread.  Their operands (all inside the tile) are
-            // read unconditionally together with the pivots, so one LDS round
-            // trip serves the step.
+            // read unconditionally together with the pivot block, so one LDS
+            // round trip serves the step.
             static_assert(kTile * kTile % kSolveThreads == 0, "whole entries per thread");
             constexpr int kH = kTile * kTile / kSolveThreads;
-            double arc[kH], arc1[kH], aqc[kH], aqc1[kH], arq[kH], vcq[kH], vc1q[kH], vrq[kH];
+            // Per entry: x = D[r][q] (entries right of the group) or V[r][q];
+            // rc[l] = D[r][c+l]; y[l] = D[q][c+l] or V[c+l][q] to match x.
+            double x[kH], rc[kH][kC], y[kH][kC];
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
                 const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                arc[h] = D[r][c]; arc1[h] = D[r][c1]; aqc[h] = D[q][c]; aqc1[h] = D[q][c1]; arq[h] = D[r][q];
-                vcq[h] = V[c][q]; vc1q[h] = V[c1][q]; vrq[h] = V[r][q];
+                const bool d_ent = q >= c + kC && q <= r;
+                x[h] = d_ent ? D[r][q] : V[r][q];
+#pragma unroll
+                for (int l = 0; l < kC; ++l) {
+                    rc[h][l] = D[r][c + l];
+                    y[h][l] = d_ent ? D[q][c + l] : V[c + l][q];
+                }
             }
-            const double dg = D[c][c], e = D[c1][c], f = D[c1][c1];
-            // Keeps the reads above here (no instruction): issued together
-            // rather than one branch at a time below.
-            __asm__ volatile("" :: "v"(arc[0]), "v"(arc1[0]), "v"(aqc[0]), "v"(aqc1[0]), "v"(arq[0]),
-                             "v"(vcq[0]), "v"(vc1q[0]), "v"(vrq[0]), "v"(dg), "v"(e), "v"(f));
-            __asm__ volatile("" :: "v"(arc[1]), "v"(arc1[1]), "v"(aqc[1]), "v"(aqc1[1]), "v"(arq[1]),
-                             "v"(vcq[1]), "v"(vc1q[1]), "v"(vrq[1]));
-            if (!(dg > 0.0) || !isfinite(dg)) {
+            // The group's pivot block (lower triangle), eliminated by every thread.
+            double B[kC][kC];
+#pragma unroll
+            for (int i = 0; i < kC; ++i)
+#pragma unroll
+                for (int j = 0; j <= i; ++j) B[i][j] = D[c + i][c + j];
+            bool bad = false;
+            double isv[kC], sdv[kC];
+            double mk[kH], dv[kH];
+#pragma unroll
+            for (int h = 0; h < kH; ++h) mk[h] = dv[h] = 0.0;
+#pragma unroll
+            for (int j = 0; j < kC; ++j) {
+                const double dj = B[j][j];
+                bad = bad || !(dj > 0.0) || !isfinite(dj);
+                // 1/sqrt(d): hardware estimate and two Newton steps.
+                double is = __builtin_amdgcn_rsq(dj);
+                is = is * fma(-0.5 * dj * is, is, 1.5);
+                is = is * fma(-0.5 * dj * is, is, 1.5);
+                const double idg = is * is;
+                isv[j] = is;
+                sdv[j] = dj * is;
+#pragma unroll
+                for (int i = j + 1; i < kC; ++i)
+#pragma unroll
+                    for (int l = j + 1; l <= i; ++l) B[i][l] -= B[i][j] * B[l][j] * idg;
+#pragma unroll
+                for (int h = 0; h < kH; ++h) {
+                    const int e2 = tid + h * kSolveThreads;
+                    const int r = e2 / kTile, q = e2 % kTile;
+                    // Outputs of column c + j: L[r][c+j] and row c + j of Dinv.
+                    if (q == c + j) mk[h] = rc[h][j] * is;
+                    if (r == c + j) dv[h] = y[h][j] * is;
+                    x[h] -= rc[h][j] * y[h][j] * idg;
+#pragma unroll
+                    for (int l = j + 1; l < kC; ++l) {
+                        rc[h][l] -= rc[h][j] * B[l][j] * idg;
+                        y[h][l] -= y[h][j] * B[l][j] * idg;
+                    }
+                }
+            }
+            if (bad) {
                 failed = true;
                 break;
             }
-            // 1/sqrt(d): hardware estimate and two Newton steps; sqrt(d) = d / sqrt(d).
-            double is = __builtin_amdgcn_rsq(dg);
-            is = is * fma(-0.5 * dg * is, is, 1.5);
-            is = is * fma(-0.5 * dg * is, is, 1.5);
-            const double sd = dg * is, idg = is * is;
-            // Pivot of column c + 1 after column c's update.
-            const double d1 = f - e * e * idg;
-            if (!(d1 > 0.0) || !isfinite(d1)) {
-                failed = true;
-                break;
-            }
-            double is1 = __builtin_amdgcn_rsq(d1);
-            is1 = is1 * fma(-0.5 * d1 * is1, is1, 1.5);
-            is1 = is1 * fma(-0.5 * d1 * is1, is1, 1.5);
-            const double sd1 = d1 * is1, idg1 = is1 * is1;
             // Each entry has at most one LDS output (D, V or a row of Dinv),
-            // chosen by selects; columns c and c + 1 of L go to memory.
+            // chosen by selects; the group's columns of L go to memory.
 #pragma unroll
             for (int h = 0; h < kH; ++h) {
                 const int e2 = tid + h * kSolveThreads;
                 const int r = e2 / kTile, q = e2 % kTile;
-                const bool d_upd = q > c1 && q <= r;
-                const bool v_upd = r > c1 && q <= c1;
-                const bool i_row0 = r == c && q <= c;
-                const bool i_row1 = r == c1 && q <= c1;
-                // After column c: entry (r, q) of D or V, entry (q, c + 1) of D
-                // or (c + 1, q) of V, and entry (r, c + 1) of D.
-                const double x = d_upd ? arq[h] : vrq[h];
-                const double y = d_upd ? aqc[h] : vcq[h];
-                const double z = d_upd ? aqc1[h] : vc1q[h];
-                const double p1 = x - arc[h] * y * idg;
-                const double p2 = z - e * y * idg;
-                const double prc1 = arc1[h] - arc[h] * e * idg;
-                const double val = i_row0 ? vcq[h] * is : (i_row1 ? p1 * is1 : p1 - prc1 * p2 * idg1);
-                double* dst = d_upd ? &D[r][q] : (v_upd ? &V[r][q] : (i_row0 ? &Dinv[c][q] : &Dinv[c1][q]));
-                if (d_upd || v_upd || i_row0 || i_row1) *dst = val;
-                if (q == c && r > c) Mk[(long)r * np + c] = arc[h] * is;
-                if (q == c1 && r > c1) Mk[(long)r * np + c1] = prc1 * is1;
+                const bool d_upd = q >= c + kC && q <= r;
+                const bool v_upd = r >= c + kC && q < c + kC;
+                const bool i_row = r >= c && r < c + kC && q <= r;
+                const double val = i_row ? dv[h] : x[h];
+                double* dst = d_upd ? &D[r][q] : (v_upd ? &V[r][q] : &Dinv[r][q]);
+                if (d_upd || v_upd || i_row) *dst = val;
+                if (q >= c && q < c + kC && r > q) Mk[(long)r * np + q] = mk[h];
             }
-            if (tid == 0) {
-                Mk[(long)c * np + c] = sd;
-                Mk[(long)c1 * np + c1] = sd1;
-            }
+            if (tid < kC) Mk[(long)(c + tid) * np + c + tid] = sdv[tid];
             __syncthreads();
         }
         if (failed) break;
