@@ -373,12 +373,13 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         // D[r][q] -= D[r][c] D[q][c] / d and the rows of the running inverse
         // V[r][q] -= D[r][c] V[c][q] / d (r > c); the scaled outputs, column c
         // of L (to M) and row c of Dinv = L_kk^-1 = V[c] / sqrt(d), go to other
-        // arrays.  A step takes two columns: every thread also forms what
-        // column c + 1 holds after column c's update (its entries and pivot)
-        // from the values it reads, so a step's writes (entries right of c + 1,
-        // rows of V below c + 1, Dinv, M) touch nothing the step reads.  Every
-        // thread forms the same pivots from the same values read after a
-        // barrier, so the decision to stop is the same in every thread.
+        // arrays.  A step takes a group of kC columns: every thread reads the
+        // group's pivot block and its entries' values in the group's columns,
+        // eliminates them through the group itself, and writes only entries
+        // right of the group, rows of V below it, Dinv and M, so a step writes
+        // nothing it reads.  Every thread forms the same pivots from the same
+        // values read after a barrier, so the decision to stop is the same in
+        // every thread.
         constexpr int kC = 4;  // columns per step
         static_assert(kTile % kC == 0, "whole column groups");
         for (int c = 0; c < kTile; c += kC) {
