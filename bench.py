@@ -145,6 +145,9 @@ def main():
                     help="comma-separated further legs to run after the single-pair forward")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--phases-only", action="store_true",
+                    help="run only the per-phase leg: the forward at (K, r) in (0,0), (10,0), (0,3), (10,3), "
+                         "single pair and 64-edge batch, four launches each in that order")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain device copy of known size (for HBM counter scaling)")
     args = ap.parse_args()
@@ -167,6 +170,10 @@ def main():
     props = torch.cuda.get_device_properties(dev)
     stream = torch.cuda.current_stream()
     sp = stream.cuda_stream
+
+    if args.phases_only:
+        print(json.dumps({"phases": phases_leg(m3s, lib, _lib, dev, sp)}), flush=True)
+        return
 
     # ------------------------------------------------------------ single pair
     t0 = time.time()
@@ -224,8 +231,7 @@ def main():
     # memory; 3-4: refine region staged in LDS; 5: fp16 pre-filter), same pool and steps.
     sweep = {}
     for tc, remap in [(t, "1") for t in range(6)] + [(3, "0"), (5, "0")]:
-        os.environ["M3S_TILE_CONFIG"] = str(tc)
-        os.environ["M3S_XCD_REMAP"] = remap
+        m3s.set_launch(tile_config=tc, xcd_remap=int(remap))
         lib.m3s_timing_reset()
         lib.m3s_timing_enable(1)
         for k in range(min(args.steps, 30)):
@@ -235,8 +241,7 @@ def main():
         tot, cnt = ctypes.c_double(), ctypes.c_int64()
         lib.m3s_timing_read(b"fwd", ctypes.byref(tot), ctypes.byref(cnt))
         sweep["%d%s" % (tc, "" if remap == "1" else "_no_xcd_remap")] = round(tot.value / max(cnt.value, 1) * 1e3, 2)
-    os.environ.pop("M3S_TILE_CONFIG", None)
-    os.environ.pop("M3S_XCD_REMAP", None)
+    m3s.set_launch()
     roofline["fwd_us_by_tile_config"] = sweep
     log("fwd kernel us by tile config:", sweep)
 
@@ -285,6 +290,64 @@ def main():
         out["parity"] = parity_statement(pool[0].res, ora)
         log("parity vs oracle:", out["parity"])
     print(json.dumps(out), flush=True)
+
+
+PHASE_VARIANTS = [(0, 0), (10, 0), (0, 3), (10, 3)]
+
+
+def phases_leg(m3s, lib, _lib, dev, sp, pairs=None):
+    """The forward at LM iterations K and refine radius r of PHASE_VARIANTS, so
+    that per-phase costs follow by difference (K=0, r=0: setup, initial sample,
+    staging and gates; the K and r increments: the LM iterations and the
+    window refine).  For each variant, in this order: one 512x384 pair
+    (m3s_match_fwd, default launch) 1 + 3 launches, then the 64-edge batch
+    (m3s_match_batched, eager, default tile configuration) 1 + 3 launches,
+    each timed with hipEvents.  Instruction counters of the same launches come
+    from rocprofv3 (dispatch order)."""
+    import torch
+    pairs = pairs if pairs is not None else synth.batched_uniform()
+    edges = []
+    for p in pairs:
+        t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+        edges.append(m3s.EdgeInput(t(p.Xii), t(p.Xji), t(p.Dii), t(p.Dji), t(p.Qii), t(p.Qji), None, -1, -1))
+    table, outs = m3s.make_edges(edges)
+    n = len(edges)
+    queries = sum(p.H * p.W for p in pairs)
+    out = []
+    for K, r in PHASE_VARIANTS:
+        prm = _lib.default_params(lib, max_iter=K, refine_radius=r)
+        nb = lib.m3s_batched_workspace_bytes(table, n, ctypes.byref(prm))
+        ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        pw = torch.empty(lib.m3s_workspace_bytes(ctypes.byref(table[0].in_), ctypes.byref(prm)), dtype=torch.uint8,
+                         device=dev)
+
+        def single():
+            st = lib.m3s_match_fwd(ctypes.byref(table[0].in_), ctypes.byref(prm), ctypes.byref(table[0].out),
+                                   pw.data_ptr(), pw.numel(), sp)
+            _lib.check(lib, "m3s_match_fwd", st)
+
+        def batch():
+            st = lib.m3s_match_batched(table, n, ctypes.byref(prm), 0, ws.data_ptr(), ws.numel(), sp)
+            _lib.check(lib, "m3s_match_batched", st)
+
+        rec = {"K": K, "r": r}
+        for name, fn, timer in (("single_fwd_us", single, "fwd"), ("batched_fwd_us", batch, "batched_fwd")):
+            fn()
+            torch.cuda.synchronize()
+            lib.m3s_timing_reset()
+            lib.m3s_timing_enable(1)
+            for _ in range(3):
+                fn()
+            torch.cuda.synchronize()
+            lib.m3s_timing_enable(0)
+            ms, _ = _timer(lib, timer)
+            rec[name] = round(ms * 1e3, 2)
+        rec["batched_matches_per_s"] = round(queries / (rec["batched_fwd_us"] * 1e-6), 1)
+        log("phases:", rec)
+        out.append(rec)
+        del ws, pw
+    return {"workload": "64 edges 512x384 (batched) and edge 0 alone (single pair); D=24, confidences",
+            "queries_batched": queries, "variants": out}
 
 
 def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):

@@ -348,13 +348,59 @@ size_t m3s_batched_workspace_bytes(const m3s_edge *edges, int32_t n_edges, const
  * workspace, so new pointers need no re-capture.  With M3S_BATCH_AUTOTUNE
  * the first call for a shape signature times candidate launch shapes
  * (synchronising the stream) and caches the fastest.  Calls that share a
- * workspace must not overlap.
+ * workspace must not overlap.  The call cannot itself be captured into a
+ * caller's hipGraph (it copies the edge table from host memory before each
+ * launch): on a capturing stream it returns M3S_ERR_UNSUPPORTED.
  */
 m3s_status m3s_match_batched(const m3s_edge *edges, int32_t n_edges, const m3s_params *common,
                              uint32_t flags, void *ws, size_t ws_bytes, void *stream);
 
 /* Launch shape the batched path used for its last call on this thread: workgroups, tile id. */
 void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
+
+/*
+ * Diagnostics: launch override and fallback-path counters (for tests and
+ * benchmarks; a production caller needs neither).
+ *
+ * m3s_debug_set_launch fixes the launch shape of later m3s_match_fwd and
+ * m3s_match_batched calls made by the CALLING THREAD (NULL restores the
+ * library's choice; -1 or 0 in a field keeps the library's choice for it):
+ *   tile_config  0: 32x8, 1: 16x16, 2: 64x4 query tiles refining from global
+ *                memory; 3: 16x16, 4: 32x8 with the refine region staged in LDS
+ *                (fp32); 5: 16x16 with an fp16 pre-filter (the default);
+ *   grid         workgroups of the persistent batched launch (> 0);
+ *   xcd_remap    0 turns off the tile-to-XCD band mapping of the single-pair launch.
+ * An override also disables M3S_BATCH_AUTOTUNE.  Every configuration gives
+ * the same output bits.
+ */
+typedef struct {
+    int32_t tile_config;
+    int32_t grid;
+    int32_t xcd_remap;
+} m3s_launch_config;
+void m3s_debug_set_launch(const m3s_launch_config *cfg);
+
+/*
+ * Counters of the fallback paths taken on the current device since the last
+ * reset, each a 64-bit count of tiles (of queries for M3S_PATH_REFINE_QUERY):
+ *   M3S_PATH_LM_GLOBAL      LM iterations 2..K read the ray records from global
+ *                           memory because the tile's window exceeded the LDS cap;
+ *   M3S_PATH_REFINE_GLOBAL  the refine scanned global memory exactly because the
+ *                           tile's region exceeded LDS, held a value outside the
+ *                           fp16 range, r > 5 or L > 1 (LDS tile configurations);
+ *   M3S_PATH_REFINE_QUERY   a query's own descriptor norm was outside the fp16
+ *                           range (fp16 configuration): exact global scan;
+ *   M3S_PATH_BWD_DIRECT     a backward tile's corner window exceeded LDS, so its
+ *                           gradients went to dL/dX^i_i by direct global atomics.
+ * Writes counts[M3S_PATH_COUNTERS] and, if reset != 0, zeroes the counters.
+ * Synchronises the device.
+ */
+#define M3S_PATH_LM_GLOBAL     0
+#define M3S_PATH_REFINE_GLOBAL 1
+#define M3S_PATH_REFINE_QUERY  2
+#define M3S_PATH_BWD_DIRECT    3
+#define M3S_PATH_COUNTERS      8
+m3s_status m3s_path_counters(int64_t *counts, int32_t reset);
 
 /*
  * Kernel timing (off by default).  When enabled, the library records a pair of

@@ -66,6 +66,14 @@ class BackendProblem(ctypes.Structure):
                 ("idx", ctypes.c_void_p), ("valid", ctypes.c_void_p)]
 
 
+class LaunchConfig(ctypes.Structure):
+    _fields_ = [("tile_config", ctypes.c_int32), ("grid", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+
+
+M3S_PATH_COUNTERS = 8
+PATH_NAMES = ["lm_global", "refine_global", "refine_query", "bwd_direct"]
+
+
 class M3SError(RuntimeError):
     def __init__(self, fn: str, status: int, detail: str):
         self.status = status
@@ -78,7 +86,8 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_clear_caches", "m3s_status_string", "m3s_last_error", "m3s_version",
            "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
            "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
-           "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn"]
+           "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn",
+           "m3s_debug_set_launch", "m3s_path_counters"]
 
 _lib = None
 
@@ -141,6 +150,10 @@ def load(path: str = LIB_PATH):
     lib.m3s_backend_workspace_bytes.restype = sz
     lib.m3s_backend_gn.argtypes = [BPr, BP, vp, vp, vp, sz, vp]
     lib.m3s_backend_gn.restype = ctypes.c_int
+    lib.m3s_debug_set_launch.argtypes = [ctypes.POINTER(LaunchConfig)]
+    lib.m3s_debug_set_launch.restype = None
+    lib.m3s_path_counters.argtypes = [ctypes.POINTER(ctypes.c_int64), i32]
+    lib.m3s_path_counters.restype = ctypes.c_int
     if path == LIB_PATH:
         _lib = lib
     return lib

@@ -72,15 +72,34 @@ def _stream(stream) -> int:
 
 
 _ws_cache: dict = {}
+_WS_CACHE_STREAMS = 16
 
 
-def _workspace(nbytes: int, device) -> torch.Tensor:
-    """A cached device buffer of at least nbytes (torch allocations are >= 256-byte aligned)."""
-    key = (torch.device(device).index, nbytes > 0)
+def _workspace(nbytes: int, device, stream=None) -> torch.Tensor:
+    """Device workspace of at least nbytes for one call on `stream` (torch
+    allocations are >= 256-byte aligned).
+
+    Outside a graph capture, one buffer per (device, stream) is kept and grown
+    as needed: the calls of one stream run in order, so they may share it, and
+    calls on different streams never do.  The buffer is allocated with its
+    stream current, so when it is dropped the allocator reuses its memory only
+    in that stream's order.  During a torch graph capture every call gets a
+    buffer of its own from the capture's memory pool, which torch keeps for
+    the graph's lifetime, and it is never cached: later eager calls cannot
+    overwrite what a replay reads.
+    """
+    s = torch.cuda.current_stream(device) if stream is None else stream
+    if torch.cuda.is_current_stream_capturing():
+        return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+    key = (torch.device(device).index, s.cuda_stream)
     buf = _ws_cache.get(key)
     if buf is None or buf.numel() < nbytes:
-        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        with torch.cuda.stream(s):
+            buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _ws_cache.pop(key, None)
         _ws_cache[key] = buf
+        while len(_ws_cache) > _WS_CACHE_STREAMS:
+            _ws_cache.pop(next(iter(_ws_cache)))
     return buf
 
 
@@ -117,7 +136,7 @@ def match(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, prm: Optional[_li
     res = out if out is not None else _alloc_outputs(H, W, Xii.device, want_theta, want_xhat)
     o = _outputs(res)
     nbytes = lib.m3s_workspace_bytes(ctypes.byref(pair), ctypes.byref(prm))
-    ws = _workspace(nbytes, Xii.device)
+    ws = _workspace(nbytes, Xii.device, stream)
     st = lib.m3s_match_fwd(ctypes.byref(pair), ctypes.byref(prm), ctypes.byref(o), ws.data_ptr(), ws.numel(),
                            _stream(stream))
     _lib.check(lib, "m3s_match_fwd", st)
@@ -164,7 +183,7 @@ def match_batched(inputs: Sequence[EdgeInput], prm: Optional[_lib.Params] = None
     nbytes = lib.m3s_batched_workspace_bytes(table, n, ctypes.byref(prm))
     if nbytes == 0:
         raise _lib.M3SError("m3s_batched_workspace_bytes", _lib.M3S_OK + 2, "invalid edges")
-    ws = _workspace(nbytes, inputs[0].Xii.device)
+    ws = _workspace(nbytes, inputs[0].Xii.device, stream)
     flags = (_lib.M3S_BATCH_GRAPH if graph else 0) | (_lib.M3S_BATCH_AUTOTUNE if autotune else 0)
     st = lib.m3s_match_batched(table, n, ctypes.byref(prm), flags, ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(lib, "m3s_match_batched", st)
@@ -178,7 +197,7 @@ def match_stats(res: MatchResult, stream=None) -> torch.Tensor:
     fwd = _lib.Outputs(0, _ptr(res.idx, torch.int32, shape=(H, W)), _ptr(res.valid, torch.uint8, shape=(H, W)), 0, 0)
     counts = torch.empty(2, dtype=torch.int32, device=res.idx.device)
     nbytes = lib.m3s_stats_workspace_bytes(H, W)
-    ws = _workspace(nbytes, res.idx.device)
+    ws = _workspace(nbytes, res.idx.device, stream)
     st = lib.m3s_match_stats(ctypes.byref(fwd), H, W, _ptr(counts, torch.int32), ws.data_ptr(), ws.numel(),
                              _stream(stream))
     _lib.check(lib, "m3s_match_stats", st)
@@ -203,7 +222,7 @@ def track_pose(Xk, Xf, idx, valid, Qf, Qk, T, prm: Optional[_lib.TrackParams] = 
     prm = prm if prm is not None else track_params()
     info = torch.empty(4, dtype=torch.float32, device=Xk.device)
     nbytes = lib.m3s_track_workspace_bytes(H, W)
-    ws = _workspace(nbytes, Xk.device)
+    ws = _workspace(nbytes, Xk.device, stream)
     st = lib.m3s_track_pose(ctypes.byref(prob), ctypes.byref(prm), _ptr(T, shape=(3, 4)), _ptr(info), ws.data_ptr(),
                             ws.numel(), _stream(stream))
     _lib.check(lib, "m3s_track_pose", st)
@@ -242,11 +261,29 @@ def backend_gn(Xc, Q, edges, idx, valid, T_WC, prm: Optional[_lib.BackendParams]
     prm = prm if prm is not None else backend_params()
     info = torch.empty(4, dtype=torch.float32, device=Xc.device)
     nbytes = lib.m3s_backend_workspace_bytes(N, H, W, E)
-    ws = _workspace(nbytes, Xc.device)
+    ws = _workspace(nbytes, Xc.device, stream)
     st = lib.m3s_backend_gn(ctypes.byref(prob), ctypes.byref(prm), _ptr(T_WC, shape=(N, 3, 4)), _ptr(info),
                             ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(lib, "m3s_backend_gn", st)
     return T_WC, info
+
+
+def set_launch(tile_config: int = -1, grid: int = -1, xcd_remap: int = -1):
+    """m3s_debug_set_launch for the calling thread (all -1: the library's choice)."""
+    lib = _lib.load()
+    if tile_config < 0 and grid <= 0 and xcd_remap < 0:
+        lib.m3s_debug_set_launch(None)
+    else:
+        cfg = _lib.LaunchConfig(tile_config, grid, xcd_remap)
+        lib.m3s_debug_set_launch(ctypes.byref(cfg))
+
+
+def path_counters(reset: bool = False) -> dict:
+    """m3s_path_counters: fallback paths taken on the current device since the last reset."""
+    lib = _lib.load()
+    buf = (ctypes.c_int64 * _lib.M3S_PATH_COUNTERS)()
+    _lib.check(lib, "m3s_path_counters", lib.m3s_path_counters(buf, 1 if reset else 0))
+    return {name: int(buf[k]) for k, name in enumerate(_lib.PATH_NAMES)}
 
 
 def last_batched_config():

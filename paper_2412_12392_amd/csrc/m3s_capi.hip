@@ -135,18 +135,17 @@ EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P,
     return E;
 }
 
-// Tile-to-XCD band mapping of the single-pair launch (M3S_XCD_REMAP=0 turns it off).
-bool env_xcd_remap() {
-    const char* s = std::getenv("M3S_XCD_REMAP");
-    return !(s && s[0] == '0');
+// Launch override of the calling thread (m3s_debug_set_launch); every field
+// -1 means the library's own choice.
+thread_local m3s_launch_config g_override = {-1, -1, -1};
+
+// Tile configuration of the single-pair launch and of an untuned batched launch.
+int chosen_tile_config() {
+    return g_override.tile_config >= 0 ? g_override.tile_config : m3s::kDefaultTileConfig;
 }
 
-int env_tile_config() {
-    const char* s = std::getenv("M3S_TILE_CONFIG");
-    if (!s) return m3s::kDefaultTileConfig;
-    int v = std::atoi(s);
-    return (v >= 0 && v < m3s::kNumTileConfigs) ? v : m3s::kDefaultTileConfig;
-}
+// Tile-to-XCD band mapping of the single-pair launch (on unless overridden).
+bool chosen_xcd_remap() { return g_override.xcd_remap != 0; }
 
 // ---------------------------------------------------------------- batched state
 
@@ -387,7 +386,7 @@ m3s_status m3s_match_fwd(const m3s_pair* pair, const m3s_params* params, const m
     EdgeArgs A = make_edge(pair, out, P, P->max_iter, P->refine_radius, rays);
     hipError_t e = m3s::launch_prep(pair->Xii, rays, pair->H, pair->W, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
-    e = m3s::launch_fwd(A, env_tile_config(), desc_in_regs(pair), env_xcd_remap(), st);
+    e = m3s::launch_fwd(A, chosen_tile_config(), desc_in_regs(pair), chosen_xcd_remap(), st);
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     g_last_error.clear();
     return M3S_OK;
@@ -572,7 +571,8 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
     const m3s_params* P = common ? common : &defaults;
     if (flags & ~(uint32_t)(M3S_BATCH_GRAPH | M3S_BATCH_AUTOTUNE))
         return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
-    int tile = env_tile_config();
+    int tile = chosen_tile_config();
+    const bool overridden = g_override.tile_config >= 0 || g_override.grid > 0;
     Plan plan;
     m3s_status s = plan_batched(edges, n_edges, P, tile, &plan);
     if (s != M3S_OK) return s;
@@ -583,11 +583,15 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
     DeviceInfo info;
     if ((s = current_device(&dev, &info)) != M3S_OK) return s;
     hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (capturing(st))
+        return fail(M3S_ERR_UNSUPPORTED,
+                    "m3s_match_batched cannot be captured: it copies its edge table from host memory before every "
+                    "launch; M3S_BATCH_GRAPH gives a library-managed graph instead");
     char* W = reinterpret_cast<char*>(ws);
     std::string tune_key = std::to_string(dev) + "|" + plan.signature;
 
-    int grid = info.cus * 4;
-    if (flags & M3S_BATCH_AUTOTUNE) {
+    int grid = g_override.grid > 0 ? g_override.grid : info.cus * 4;
+    if ((flags & M3S_BATCH_AUTOTUNE) && !overridden) {
         TuneResult tr;
         bool have = false;
         {
@@ -669,6 +673,27 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
         hipError_t e = run_batched(plan, W, tile, grid, st);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+void m3s_debug_set_launch(const m3s_launch_config* cfg) {
+    if (cfg) {
+        g_override = *cfg;
+        if (g_override.tile_config >= m3s::kNumTileConfigs) g_override.tile_config = -1;
+    } else {
+        g_override = m3s_launch_config{-1, -1, -1};
+    }
+}
+
+m3s_status m3s_path_counters(int64_t* counts, int32_t reset) {
+    if (!counts) return fail(M3S_ERR_NULL, "counts is NULL");
+    int dev;
+    DeviceInfo info;
+    m3s_status s = current_device(&dev, &info);
+    if (s != M3S_OK) return s;
+    hipError_t e = m3s::read_path_counters(counts, reset != 0);
+    if (e != hipSuccess) return hip_fail(e, "path counters");
     g_last_error.clear();
     return M3S_OK;
 }

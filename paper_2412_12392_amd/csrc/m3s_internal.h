@@ -18,6 +18,11 @@ constexpr int kDefaultTileConfig = 5;
 void tile_shape(int tile_config, int* tx, int* ty);
 bool tile_uses_lds(int tile_config);
 
+// Fallback-path counters kept on the device (indices match M3S_PATH_* of m3s.h).
+enum { kPathLmGlobal = 0, kPathRefineGlobal = 1, kPathRefineQuery = 2, kPathBwdDirect = 3, kNumPathCounters = 8 };
+// Synchronises the device, copies the counters to out[kNumPathCounters], optionally zeroes them.
+hipError_t read_path_counters(int64_t* out, bool reset);
+
 // Optional per-kernel event timing (implemented in m3s_capi.hip).  Both calls
 // are no-ops unless timing is enabled and the stream is not being captured.
 void timer_begin(const char* name, hipStream_t s);

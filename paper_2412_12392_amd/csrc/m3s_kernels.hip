@@ -107,6 +107,13 @@ __device__ __forceinline__ int tile_of_block(int b, int tiles, bool remap) {
     return t < tiles ? t : -1;
 }
 
+// Fallback-path counters (indices kPath*, read by read_path_counters): one
+// vector atomic per tile (per query for kPathRefineQuery) that leaves its
+// fast path, so tests can show that every branch ran.
+__device__ unsigned long long g_path_counts[kNumPathCounters];
+
+__device__ __forceinline__ void count_path(int k) { atomicAdd(&g_path_counts[k], 1ull); }
+
 // ---------------------------------------------------------------- forward
 
 // Descriptor dot product of the query (in registers for a compile-time D)
@@ -460,6 +467,7 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
             __builtin_amdgcn_s_waitcnt(0);
         } else {
             ww = 0;
+            if (threadIdx.x == 0) count_path(kPathLmGlobal);
         }
     }
     __syncthreads();
@@ -511,6 +519,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     const int rw = hx - lx + 1, rh = hy - ly + 1;
     const bool any = hx >= lx;
     const bool use_lds = any && rw * rh <= kRegionPx && A.levels == 1;
+    if (any && !use_lds && tid == 0) count_path(kPathRefineGlobal);
     if (use_lds) {
         // Direct global -> LDS loads (no registers, all in flight at once).  LDS
         // slot c = k * kRegionPx + pix holds float4 k of region pixel pix; each
@@ -661,7 +670,10 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     for (int k = 0; k < 24; ++k) qn2 = fmaf(qd.q[k], qd.q[k], qn2);
     // Bounds and tau in scaled units (both operands times kScale16).
     const float qn = sqrtf(qn2) * 1.0001f * kScale16;
-    if (!(qn <= kF16Max)) return refine_global<24>(A, n, q);
+    if (!(qn <= kF16Max)) {
+        count_path(kPathRefineQuery);
+        return refine_global<24>(A, n, q);
+    }
 #pragma unroll
     for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k] * kScale16, qd.q[2 * k + 1] * kScale16);
     const float ql1 = kSqrt24Up * qn;
@@ -804,6 +816,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
 #pragma unroll
     for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
     use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
+    if (any && !use16 && tid == 0) count_path(kPathRefineGlobal);
     if (q.good) {
         const long n = (long)y * W + x;
         const float dnorm = sqrtf(pn2) * 1.0001f;
@@ -1064,6 +1077,7 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
             unsafeAtomicAdd(dXii + 3 * ((long)(ly + row) * W + lx) + col, v);
         }
     } else {
+        if (any && tid == 0) count_path(kPathBwdDirect);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (cm[c] < 0) continue;
@@ -1201,6 +1215,20 @@ hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, 
     stats_kernel<<<blocks_for(N, 256), 256, 0, s>>>(idx, valid, N, N, bitmap, counts);
     timer_end(s);
     return hipGetLastError();
+}
+
+hipError_t read_path_counters(int64_t* out, bool reset) {
+    hipError_t e = hipDeviceSynchronize();
+    unsigned long long v[kNumPathCounters];
+    if (e == hipSuccess) e = hipMemcpyFromSymbol(v, HIP_SYMBOL(g_path_counts), sizeof v, 0, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return e;
+    for (int k = 0; k < kNumPathCounters; ++k) out[k] = (int64_t)v[k];
+    if (reset) {
+        for (int k = 0; k < kNumPathCounters; ++k) v[k] = 0ull;
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_path_counts), v, sizeof v, 0, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipDeviceSynchronize();
+    }
+    return e;
 }
 
 hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,

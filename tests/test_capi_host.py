@@ -344,3 +344,25 @@ def test_backend_validation(lib, case, expect):
                             None)
     assert st == expect, (st, lib.m3s_last_error())
     assert lib.m3s_last_error()
+
+
+def test_launch_override_struct_and_counters_null(tmp_path, lib):
+    prog = tmp_path / "launch.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "m3s.h"
+int main(void) {
+  printf("%zu %zu %zu %d\n", sizeof(m3s_launch_config), offsetof(m3s_launch_config, grid),
+         offsetof(m3s_launch_config, xcd_remap), M3S_PATH_COUNTERS);
+  return 0;
+}''')
+    exe = tmp_path / "launch"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(_lib.LaunchConfig), _lib.LaunchConfig.grid.offset,
+                    _lib.LaunchConfig.xcd_remap.offset, _lib.M3S_PATH_COUNTERS]
+    cfg = _lib.LaunchConfig(3, 64, 0)
+    lib.m3s_debug_set_launch(ctypes.byref(cfg))
+    lib.m3s_debug_set_launch(None)
+    assert lib.m3s_path_counters(None, 0) == 1

@@ -100,7 +100,7 @@ def _full_batch_check(m3s, pairs, sample, label):
         assert_same(ref[j], g, "%s edge %d" % (label, k))
         p = pairs[k]
         o = oracle.match_fwd(p.Xii, p.Xji, p.Dii, p.Dji, p.Qii, p.Qji, K=p.K, r=p.r)
-        print(parity.compare(g, o, "%s edge %d (%dx%d K%d r%d)" % (label, k, p.H, p.W, p.K, p.r)))
+        print(parity.compare(g, o, "%s edge %d (%dx%d K%d r%d)" % (label, k, p.H, p.W, p.K, p.r), pair=p, r=p.r))
 
 
 def test_batched_64_edges_512x384(m3s):

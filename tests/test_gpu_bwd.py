@@ -42,10 +42,13 @@ def test_bwd_matches_oracle_adjoint(m3s, H, W, seed):
     pair = synth.make_pair(H, W, seed)
     gi, gj, oi, oj, o = _fed(m3s, pair, seed)
     ei, ej = rel_l2(gi, oi), rel_l2(gj, oj)
-    print(dict(shape=(H, W), rel_l2_dXii=ei, rel_l2_dXji=ej))
+    mi = float(np.abs(gi - oi).max() / np.abs(oi).max())
+    mj = float(np.abs(gj - oj).max() / np.abs(oj).max())
+    print(dict(shape=(H, W), rel_l2_dXii=ei, rel_l2_dXji=ej, max_rel_dXii=mi, max_rel_dXji=mj))
     assert ei <= 1e-4 and ej <= 1e-4
-    # Per query: dXji elementwise within 1e-3 of the largest entry.
-    assert np.abs(gj - oj).max() <= 1e-3 * np.abs(oj).max()
+    # Element by element, both outputs within 1e-4 of their largest entry
+    # (same p* and mask on both sides, so every pixel is compared).
+    assert mi <= 1e-4 and mj <= 1e-4
     assert (gj[~o["valid"]] == 0).all()
 
 
@@ -97,16 +100,39 @@ def test_fwd_bwd_full_size_sampled(m3s):
     o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji)
     ogx = 2.0 * (o["xhat"] - pair.Xji) * o["valid"][..., None]
     oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, o["p"], o["valid"], None, ogx)
-    both = o["valid"] & res.valid.cpu().numpy().astype(bool)
+    vg = res.valid.cpu().numpy().astype(bool)
+    both = o["valid"] & vg
     # The exact sampler derivative is one-sided at bilinear cell edges, so a
     # query whose p* lies within 1e-4 px of one may sit in different cells on
-    # the two sides: those are compared only through the L2 norm below.
+    # the two sides: its own dXji entry and the dXii entries of the corners it
+    # touches on either side are left out, and so are the corners touched by
+    # queries that only one side calls valid.
     frac = o["p"] - np.floor(o["p"])
     edge = ((frac < 1e-4) | (frac > 1 - 1e-4)).any(-1)
-    print(dict(valid_both=int(both.sum()), cell_edge_excluded=int((both & edge).sum())))
+    skip = (both & edge) | (o["valid"] != vg)
+    gp = res.p.cpu().numpy().astype(np.float64)
+    touched = corner_pixels(o["p"], skip) | corner_pixels(gp, skip)
+    print(dict(valid_both=int(both.sum()), cell_edge_excluded=int((both & edge).sum()),
+               dXii_pixels_excluded=int(touched.sum())))
     both &= ~edge
     gj = gj.cpu().numpy()
+    gi = gi.cpu().numpy()
     err = np.abs(gj - oj)[both].max() / np.abs(oj[both]).max()
-    print(dict(max_rel_dXji_valid_both=float(err), rel_l2_dXii=rel_l2(gi.cpu().numpy(), oi)))
+    keep = ~touched
+    err_i = np.abs(gi - oi)[keep].max() / np.abs(oi).max()
+    print(dict(max_rel_dXji_valid_both=float(err), max_rel_dXii_compared=float(err_i), rel_l2_dXii=rel_l2(gi, oi)))
     assert err <= 1e-3
-    assert rel_l2(gi.cpu().numpy(), oi) <= 1e-2
+    assert err_i <= 1e-3
+
+
+def corner_pixels(p, mask):
+    """Pixels that are bilinear corners of p for the queries in mask."""
+    H, W = mask.shape
+    out = np.zeros((H, W), bool)
+    q = p[mask]
+    x0 = np.clip(np.minimum(np.floor(q[:, 0]).astype(int), W - 2), 0, W - 2)
+    y0 = np.clip(np.minimum(np.floor(q[:, 1]).astype(int), H - 2), 0, H - 2)
+    for dy in (0, 1):
+        for dx in (0, 1):
+            out[y0 + dy, x0 + dx] = True
+    return out

@@ -51,7 +51,7 @@ def check(m3s, pair, label, p_init=None, p_theta_max=None, **kw):
     kw.setdefault("r", pair.r)
     g = run(m3s, pair, p_init, **_prm_kw(kw))
     o = ora(pair, p_init, **kw)
-    st = parity.compare(g, o, label, p_theta_max=p_theta_max)
+    st = parity.compare(g, o, label, p_theta_max=p_theta_max, pair=pair, r=kw["r"], levels=kw.get("levels", 1))
     print(st)
     both = g["valid"] & o["valid"]
     if p_theta_max is not None:
@@ -162,22 +162,24 @@ def test_tile_configs_bitwise_and_deterministic(m3s):
     pair = _pair(200, 264, 16)
     outs = []
     try:
-        for tc in ("0", "1", "2", "3", "4", "5", "3"):
-            os.environ["M3S_TILE_CONFIG"] = tc
+        for tc in (0, 1, 2, 3, 4, 5, 3):
+            m3s.set_launch(tile_config=tc)
             outs.append(run(m3s, pair))
+        m3s.set_launch(tile_config=5, xcd_remap=0)
+        outs.append(run(m3s, pair))
     finally:
-        os.environ.pop("M3S_TILE_CONFIG", None)
+        m3s.set_launch()
     for o in outs[1:]:
         for k in ("p", "idx", "valid", "theta", "xhat"):
             assert np.array_equal(outs[0][k], o[k], equal_nan=True), k
 
 
 def _run_cfg(m3s, pair, cfg, **prm):
-    os.environ["M3S_TILE_CONFIG"] = cfg
+    m3s.set_launch(tile_config=int(cfg))
     try:
         return run(m3s, pair, **prm)
     finally:
-        os.environ.pop("M3S_TILE_CONFIG", None)
+        m3s.set_launch()
 
 
 def _with_desc(pair, Dii, Dji):
