@@ -146,6 +146,23 @@ m3s_status m3s_match_fwd(const m3s_pair *pair, const m3s_params *params, const m
                          void *ws, size_t ws_bytes, void *stream);
 
 /*
+ * m3s_match_fwd_noalloc -- m3s_match_fwd with no workspace argument, for
+ * callers that cannot allocate device memory (code under hipGraph stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc).  The ray
+ * records live in a static device array of the library, one copy per GPU,
+ * sized for M3S_NOALLOC_MAX_PIXELS pixels (48 B each: 12 MiB) and held until
+ * the process ends; the call itself allocates nothing (no hipMalloc, no
+ * hipFree, no events even with timing enabled).  H * W above the limit
+ * returns M3S_ERR_SHAPE.  Every call on one GPU shares that array: calls
+ * that overlap on one GPU (several streams or host threads at once) race and
+ * must be serialised by the caller.  The caller still provides the inputs
+ * and outputs.  Results equal m3s_match_fwd's bit for bit.
+ */
+#define M3S_NOALLOC_MAX_PIXELS (1 << 18)
+m3s_status m3s_match_fwd_noalloc(const m3s_pair *pair, const m3s_params *params, const m3s_outputs *out,
+                                 void *stream);
+
+/*
  * m3s_match_bwd -- implicit adjoint of the converged match (no counterpart in
  * the paper).  Given the forward's p and valid, and upstream gradients
  * grad_p [H*W*2] (required) and grad_xhat [H*W*3] (or NULL), writes

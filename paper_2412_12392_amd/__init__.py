@@ -8,6 +8,6 @@ tensors.  Build the library with ``python -m paper_2412_12392_amd.build``.
 """
 from .binding import (EdgeInput, MatchFunction, MatchResult, backend_gn, backend_params,  # noqa: F401
                     fuse_pointmap, last_batched_config,
-                    make_edges, match, match_backward, match_batched, match_stats, params, path_counters, set_launch,
+                    make_edges, match, match_backward, match_noalloc, match_batched, match_stats, params, path_counters, set_launch,
                     track_params, track_pose)
 from ._lib import M3SError, load as load_library  # noqa: F401

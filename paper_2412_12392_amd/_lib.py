@@ -71,6 +71,7 @@ class LaunchConfig(ctypes.Structure):
 
 
 M3S_PATH_COUNTERS = 8
+M3S_NOALLOC_MAX_PIXELS = 1 << 18
 PATH_NAMES = ["lm_global", "refine_global", "refine_query", "bwd_direct"]
 
 
@@ -87,7 +88,7 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
            "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
            "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn",
-           "m3s_debug_set_launch", "m3s_path_counters"]
+           "m3s_debug_set_launch", "m3s_path_counters", "m3s_match_fwd_noalloc"]
 
 _lib = None
 
@@ -108,6 +109,8 @@ def load(path: str = LIB_PATH):
     lib.m3s_workspace_bytes.restype = sz
     lib.m3s_match_fwd.argtypes = [PP, P, PO, vp, sz, vp]
     lib.m3s_match_fwd.restype = ctypes.c_int
+    lib.m3s_match_fwd_noalloc.argtypes = [PP, P, PO, vp]
+    lib.m3s_match_fwd_noalloc.restype = ctypes.c_int
     lib.m3s_match_bwd.argtypes = [PP, PO, vp, vp, vp, vp, vp]
     lib.m3s_match_bwd.restype = ctypes.c_int
     lib.m3s_batched_workspace_bytes.argtypes = [PE, i32, P]

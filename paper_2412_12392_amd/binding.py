@@ -143,6 +143,20 @@ def match(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, prm: Optional[_li
     return res
 
 
+def match_noalloc(Xii, Xji, Dii, Dji, Qii=None, Qji=None, p_init=None, prm: Optional[_lib.Params] = None,
+                  *, out: MatchResult, stream=None) -> MatchResult:
+    """m3s_match_fwd_noalloc: the forward with the library's static device scratch
+    (H * W <= M3S_NOALLOC_MAX_PIXELS) into the caller's outputs `out`; neither
+    this call nor the library allocates memory."""
+    lib = _lib.load()
+    pair = _pair(Xii, Xji, Dii, Dji, Qii, Qji, p_init)
+    prm = prm if prm is not None else params()
+    o = _outputs(out)
+    st = lib.m3s_match_fwd_noalloc(ctypes.byref(pair), ctypes.byref(prm), ctypes.byref(o), _stream(stream))
+    _lib.check(lib, "m3s_match_fwd_noalloc", st)
+    return out
+
+
 def match_backward(Xii, Xji, p, valid, grad_p, grad_xhat=None, stream=None):
     """m3s_match_bwd: (dL/dXii, dL/dXji) through p* and xhat."""
     lib = _lib.load()

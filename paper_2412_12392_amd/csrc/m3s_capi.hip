@@ -256,6 +256,7 @@ std::vector<hipEvent_t> g_event_pool;
 std::map<std::string, std::pair<double, int64_t>> g_timer_totals;
 thread_local std::string g_timer_name;
 thread_local hipEvent_t g_timer_e0 = nullptr;
+thread_local bool g_timer_suppressed = false;  // set around m3s_match_fwd_noalloc (no event creation)
 
 hipEvent_t pooled_event() {
     if (!g_event_pool.empty()) {
@@ -282,7 +283,7 @@ namespace m3s {
 void timer_begin(const char* name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_timer_mu);
     g_timer_e0 = nullptr;
-    if (!g_timer_on || capturing(s)) return;
+    if (!g_timer_on || g_timer_suppressed || capturing(s)) return;
     hipEvent_t e0 = pooled_event();
     if (!e0) return;
     if (hipEventRecord(e0, s) != hipSuccess) { g_event_pool.push_back(e0); return; }
@@ -320,6 +321,40 @@ m3s_status drain_timings() {
         g_event_pool.push_back(t.e1);
     }
     g_timed.clear();
+    return M3S_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- no-allocation scratch
+//
+// Ray records for m3s_match_fwd_noalloc live in this file-scope device array
+// (one copy per GPU, held until the process ends).  Host code never passes
+// the array's name to a kernel: on the host it is only a stand-in for the
+// symbol.  The device address of each GPU's copy is looked up once per
+// device with hipGetSymbolAddress, with that device current, and kept here.
+namespace m3s {
+__device__ __align__(256) float4 scratch[(size_t)M3S_NOALLOC_MAX_PIXELS * kRecF4];
+}  // namespace m3s
+
+namespace {
+
+std::mutex g_scratch_mu;
+std::map<int, float4*> g_scratch_ptr;
+
+m3s_status scratch_of_device(int dev, float4** out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(dev);
+    if (it != g_scratch_ptr.end()) {
+        *out = it->second;
+        return M3S_OK;
+    }
+    float4* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress((void**)&ptr, HIP_SYMBOL(m3s::scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (ptr == nullptr || !aligned(ptr, kAlign)) return fail(M3S_ERR_HIP, "scratch address is not 256-byte aligned");
+    g_scratch_ptr[dev] = ptr;
+    *out = ptr;
     return M3S_OK;
 }
 
@@ -387,6 +422,34 @@ m3s_status m3s_match_fwd(const m3s_pair* pair, const m3s_params* params, const m
     hipError_t e = m3s::launch_prep(pair->Xii, rays, pair->H, pair->W, st);
     if (e != hipSuccess) return hip_fail(e, "prep launch");
     e = m3s::launch_fwd(A, chosen_tile_config(), desc_in_regs(pair), chosen_xcd_remap(), st);
+    if (e != hipSuccess) return hip_fail(e, "forward launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+m3s_status m3s_match_fwd_noalloc(const m3s_pair* pair, const m3s_params* params, const m3s_outputs* out,
+                                 void* stream) {
+    m3s_params defaults;
+    m3s_default_params(&defaults);
+    const m3s_params* P = params ? params : &defaults;
+    m3s_status s = check_params(P);
+    if (s != M3S_OK) return s;
+    if ((s = check_pair(pair, true)) != M3S_OK) return s;
+    if ((s = check_outputs(out)) != M3S_OK) return s;
+    if ((int64_t)pair->H * pair->W > M3S_NOALLOC_MAX_PIXELS)
+        return fail(M3S_ERR_SHAPE, "H * W = %lld exceeds the no-allocation limit M3S_NOALLOC_MAX_PIXELS = %d",
+                    (long long)pair->H * pair->W, M3S_NOALLOC_MAX_PIXELS);
+    int dev;
+    DeviceInfo info;
+    if ((s = current_device(&dev, &info)) != M3S_OK) return s;
+    float4* rays = nullptr;
+    if ((s = scratch_of_device(dev, &rays)) != M3S_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    EdgeArgs A = make_edge(pair, out, P, P->max_iter, P->refine_radius, rays);
+    g_timer_suppressed = true;
+    hipError_t e = m3s::launch_prep(pair->Xii, rays, pair->H, pair->W, st);
+    if (e == hipSuccess) e = m3s::launch_fwd(A, chosen_tile_config(), desc_in_regs(pair), chosen_xcd_remap(), st);
+    g_timer_suppressed = false;
     if (e != hipSuccess) return hip_fail(e, "forward launch");
     g_last_error.clear();
     return M3S_OK;

@@ -346,6 +346,28 @@ def test_backend_validation(lib, case, expect):
     assert lib.m3s_last_error()
 
 
+@pytest.mark.parametrize("case,expect", [
+    (dict(pair=None), 1),
+    (dict(pair=dict(H=1)), 2),
+    (dict(pair=dict(H=513, W=512)), 2),          # above M3S_NOALLOC_MAX_PIXELS
+    (dict(pair=dict(Dji=0)), 1),
+    (dict(outs=dict(idx=0)), 1),
+    (dict(prm=dict(refine_radius=9)), 3),
+])
+def test_noalloc_validation(lib, case, expect):
+    """m3s_match_fwd_noalloc validates like m3s_match_fwd and rejects frames above
+    its scratch limit, all before any HIP call."""
+    pair = None if case.get("pair", {}) is None else _pair(**case.get("pair", {}))
+    prm = _lib.default_params(lib, **case.get("prm", {}))
+    outs = _outs(**case.get("outs", {}))
+    st = lib.m3s_match_fwd_noalloc(ctypes.byref(pair) if pair is not None else None, ctypes.byref(prm),
+                                   ctypes.byref(outs), None)
+    assert st == expect, (st, lib.m3s_last_error())
+    if expect == 2 and pair is not None and pair.H == 513:
+        assert b"M3S_NOALLOC_MAX_PIXELS" in lib.m3s_last_error()
+    assert _lib.M3S_NOALLOC_MAX_PIXELS == 1 << 18
+
+
 def test_launch_override_struct_and_counters_null(tmp_path, lib):
     prog = tmp_path / "launch.c"
     prog.write_text(r'''
