@@ -12,6 +12,8 @@ pixel matches per second over K timed steps (inputs resident in HBM).
 
 Further legs, reported in the same JSON line:
   fwd_bwd        forward (with xhat) then the implicit-adjoint backward per pair;
+  fwd_bwd_batched the differentiation workload: 16 edges at 512x384, one batched
+                 forward then one batched backward per step, against the per-pair loop;
   batched        64 edges at 512x384 in one persistent hipGraph launch
                  (autotuned) vs a loop of per-pair launches on the same GPU;
   batched_uneven 96 edges of mixed resolution (512x384, 384x512, 512x288),
@@ -270,6 +272,7 @@ def main():
         legs = set(args.legs.split(","))
         if "fwd_bwd" in legs:
             out["fwd_bwd"] = fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
+            out["fwd_bwd_batched"] = fwd_bwd_batched_leg(m3s, lib, _lib, dev, args)
         if "batched" in legs:
             out["batched"] = batched_leg(m3s, lib, _lib, synth.batched_uniform, dev, args,
                                          "64 edges 512x384, K=10, r=3")
@@ -401,6 +404,110 @@ def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
     res["step_algorithmic_GBs"] = round(step_gbs, 1)
     res["step_frac_of_hbm_peak"] = round(step_gbs / HBM_PEAK_GBS, 4)
     log("fwd+bwd:", res)
+    return res
+
+
+def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
+    """The differentiation workload: 16 edges at 512x384 per step, one batched
+    forward (with xhat; one persistent hipGraph launch) then one batched
+    backward (zero-fill + persistent launch, hipGraph) to dL/dX^i_i and
+    dL/dX^j_i for L = sum over valid matches of |xhat - x|^2 (grad_xhat =
+    2 (xhat - x) on valid queries, from one forward before timing)."""
+    import torch
+    t0 = time.time()
+    pairs = [synth.config_pair(5, e) for e in range(16)]
+    log("fwd_bwd_batched leg: %d edges generated in %.1fs" % (len(pairs), time.time() - t0))
+    t = lambda a: None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    edges = [m3s.EdgeInput(t(p.Xii), t(p.Xji), t(p.Dii), t(p.Dji), t(p.Qii), t(p.Qji), None, p.K, p.r) for p in pairs]
+    queries = sum(p.H * p.W for p in pairs)
+    n = len(edges)
+    prm = m3s.params()
+    table, outs = m3s.make_edges(edges, want_xhat=True)
+    ws = torch.empty(lib.m3s_batched_workspace_bytes(table, n, ctypes.byref(prm)), dtype=torch.uint8, device=dev)
+    s = torch.cuda.Stream()
+    fflags = _lib.M3S_BATCH_GRAPH | _lib.M3S_BATCH_AUTOTUNE
+
+    def fwd():
+        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), fflags, ws.data_ptr(), ws.numel(), s.cuda_stream)
+        _lib.check(lib, "m3s_match_batched", st)
+
+    with torch.cuda.stream(s):
+        fwd()
+    s.synchronize()
+    bins = []
+    for e, o in zip(edges, outs):
+        gx = (2.0 * (o.xhat - e.Xji) * o.valid[..., None].float()).contiguous()
+        bins.append(m3s.BwdEdgeInput(e.Xii, e.Xji, o.p, o.valid, torch.zeros_like(o.p), gx))
+    btable, grads = m3s.make_bwd_edges(bins)
+    wsb = torch.empty(lib.m3s_bwd_batched_workspace_bytes(n), dtype=torch.uint8, device=dev)
+
+    def bwd():
+        st = lib.m3s_match_bwd_batched(btable, n, _lib.M3S_BATCH_GRAPH, wsb.data_ptr(), wsb.numel(), s.cuda_stream)
+        _lib.check(lib, "m3s_match_bwd_batched", st)
+
+    def step():
+        fwd()
+        bwd()
+
+    steps = max(5, args.steps // 5)
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            step()
+    s.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(steps):
+            step()
+    s.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    lib.m3s_timing_reset()
+    lib.m3s_timing_enable(1)
+    with torch.cuda.stream(s):
+        for _ in range(3):
+            step()
+    s.synchronize()
+    lib.m3s_timing_enable(0)
+    fg, _ = _timer(lib, "batched_graph")
+    bg, _ = _timer(lib, "batched_bwd_graph")
+    # Per-pair loop of the same work on the same stream, for comparison.
+    pw = torch.empty(lib.m3s_workspace_bytes(ctypes.byref(table[0].in_), ctypes.byref(prm)), dtype=torch.uint8,
+                     device=dev)
+    bpairs = [_lib.Pair(e.Xii.shape[0], e.Xii.shape[1], 0, e.Xii.data_ptr(), e.Xji.data_ptr(), 0, 0, 0, 0, 0)
+              for e in edges]
+
+    def loop():
+        for k in range(n):
+            st = lib.m3s_match_fwd(ctypes.byref(table[k].in_), ctypes.byref(prm), ctypes.byref(table[k].out),
+                                   pw.data_ptr(), pw.numel(), s.cuda_stream)
+            _lib.check(lib, "m3s_match_fwd", st)
+            st = lib.m3s_match_bwd(ctypes.byref(bpairs[k]), ctypes.byref(table[k].out), bins[k].grad_p.data_ptr(),
+                                   bins[k].grad_xhat.data_ptr(), grads[k][0].data_ptr(), grads[k][1].data_ptr(),
+                                   s.cuda_stream)
+            _lib.check(lib, "m3s_match_bwd", st)
+
+    with torch.cuda.stream(s):
+        loop()
+    s.synchronize()
+    t0 = time.perf_counter()
+    with torch.cuda.stream(s):
+        for _ in range(max(3, steps // 2)):
+            loop()
+    s.synchronize()
+    el_p = (time.perf_counter() - t0) / max(3, steps // 2)
+    step_bytes = (FWD_BYTES_PER_QUERY + 12 + BWD_BYTES_PER_QUERY) * queries
+    res = {"workload": "16 edges 512x384 (W x H), K=10, r=3, confidences: batched forward with xhat then batched "
+                       "implicit-adjoint backward, L = sum of squared matched-point distances",
+           "edges": n, "queries": queries, "matches_per_s": round(queries / el, 1), "ms_per_step": round(el * 1e3, 4),
+           "fwd_graph_ms_events": round(fg, 4), "bwd_graph_ms_events": round(bg, 4),
+           "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
+           "speedup_vs_per_pair": round(el_p / el, 3),
+           "step_algorithmic_GBs": round(step_bytes / el / 1e9, 1),
+           "step_frac_of_hbm_peak": round(step_bytes / el / 1e9 / HBM_PEAK_GBS, 4),
+           "bwd_algorithmic_GBs": round(BWD_BYTES_PER_QUERY * queries / (bg * 1e-3) / 1e9, 1),
+           "bwd_frac_of_hbm_peak": round(BWD_BYTES_PER_QUERY * queries / (bg * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    log("fwd_bwd_batched:", res)
+    del ws, wsb, pw, outs, edges, grads
+    torch.cuda.empty_cache()
     return res
 
 
@@ -639,26 +746,53 @@ def copy_calibration(torch, dev):
     return {"bytes_read": n, "bytes_written": n, "launches": 3}
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (as lscpu reports it, from /proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(pair, seconds):
-    """The FP64 oracle (OpenMP over queries) on the host cores, repeated on one
-    512x384 pair for about `seconds` seconds of wall time."""
+    """The FP64 oracle (OpenMP over queries) on the host cores: the median of
+    5 timed runs after one warm-up, each run repeating forward passes over one
+    512x384 pair for about seconds/5 of wall time, with all threads; then the
+    same median with one thread (one pass per run)."""
     import oracle
     lib = oracle.load()
-    args = dict(oracle.DEFAULTS, K=pair.K, r=pair.r)
-    ora = oracle.match_pair(pair)  # warm-up (thread pool)
-    calls = 0
-    t0 = time.perf_counter()
-    while True:
-        oracle.match_pair(pair)
-        calls += 1
-        el = time.perf_counter() - t0
-        if el >= seconds:
-            break
     N = pair.H * pair.W
-    return {"value": round(N * calls / el, 1), "unit": "matches/s", "cores": oracle.max_threads(lib),
-            "kind": "oracle", "sample": "%d repeated forward passes over one 512x384 pair (%d queries each), "
-                                        "%.1f s, fp64 C with OpenMP over queries" % (calls, N, el),
-            "host_cpus": os.cpu_count()}, ora
+    ora = oracle.match_pair(pair)  # warm-up (thread pool)
+
+    def runs(nthreads, min_s):
+        rates, calls_total, wall = [], 0, 0.0
+        for _ in range(5):
+            calls = 0
+            t0 = time.perf_counter()
+            while True:
+                oracle.match_pair(pair, nthreads=nthreads)
+                calls += 1
+                el = time.perf_counter() - t0
+                if el >= min_s:
+                    break
+            rates.append(N * calls / el)
+            calls_total += calls
+            wall += el
+        return float(np.median(rates)), calls_total, wall
+
+    all_rate, all_calls, all_wall = runs(0, seconds / 5.0)
+    one_rate, one_calls, one_wall = runs(1, 0.0)
+    threads = oracle.max_threads(lib)
+    return {"value": round(all_rate, 1), "unit": "matches/s", "cores": threads, "kind": "oracle",
+            "sample": "median of 5 runs after one warm-up, each repeating the forward over one %dx%d pair "
+                      "(%d queries) for >= %.1f s: %d passes in %.1f s with %d threads; fp64 C, OpenMP over queries"
+                      % (pair.W, pair.H, N, seconds / 5.0, all_calls, all_wall, threads),
+            "one_thread": {"value": round(one_rate, 1), "unit": "matches/s", "cores": 1,
+                           "sample": "median of 5 single passes over the same pair (%.1f s)" % one_wall},
+            "host_cpus": os.cpu_count(), "cpu_model": cpu_model()}, ora
 
 
 def parity_statement(res, ora):

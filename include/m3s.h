@@ -64,7 +64,8 @@ typedef enum {
     M3S_ERR_PARAM = 3,        /* a parameter out of its documented range */
     M3S_ERR_WORKSPACE = 4,    /* workspace NULL, misaligned (256 B) or too small */
     M3S_ERR_HIP = 5,          /* a HIP runtime call failed */
-    M3S_ERR_UNSUPPORTED = 6   /* device is not gfx950, or an unsupported flag */
+    M3S_ERR_UNSUPPORTED = 6,  /* device is not gfx950, or an unsupported flag */
+    M3S_STATUS_RESERVED = 0x7fffffff  /* not returned; keeps any int32 a valid m3s_status value */
 } m3s_status;
 
 /*
@@ -179,6 +180,33 @@ m3s_status m3s_match_fwd_noalloc(const m3s_pair *pair, const m3s_params *params,
 m3s_status m3s_match_bwd(const m3s_pair *pair, const m3s_outputs *fwd,
                          const float *grad_p, const float *grad_xhat,
                          float *grad_Xii, float *grad_Xji, void *stream);
+
+/*
+ * m3s_match_bwd_batched -- m3s_match_bwd over n_edges edges (for example the
+ * edges just matched by m3s_match_batched) in two launches: one zeroes every
+ * grad_Xii, then one persistent launch works through the 16 x 16 query tiles
+ * of all edges.  `edges` is a HOST array, copied into the workspace on
+ * `stream` before the launches (the caller may reuse it when the call
+ * returns).  grad_Xji equals m3s_match_bwd's bit for bit; grad_Xii equals it
+ * up to the order of the fp32 atomic additions.  With M3S_BATCH_GRAPH the two
+ * launches are captured into a hipGraph keyed by (device, workspace address,
+ * edge shapes) and replayed.  The call cannot itself be captured into a
+ * caller's graph (it returns M3S_ERR_UNSUPPORTED on a capturing stream).
+ * Calls that share a workspace must not overlap.
+ */
+typedef struct {
+    int32_t H, W;
+    const float   *Xii, *Xji;      /* [H*W*3] the edge's pointmaps */
+    const float   *p;              /* [H*W*2] the forward's p */
+    const uint8_t *valid;          /* [H*W]   the forward's valid */
+    const float   *grad_p;         /* [H*W*2] required */
+    const float   *grad_xhat;      /* [H*W*3] or NULL */
+    float         *grad_Xii;       /* [H*W*3] overwritten */
+    float         *grad_Xji;       /* [H*W*3] overwritten */
+} m3s_bwd_edge;
+size_t m3s_bwd_batched_workspace_bytes(int32_t n_edges);
+m3s_status m3s_match_bwd_batched(const m3s_bwd_edge *edges, int32_t n_edges, uint32_t flags, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /*
  * Keyframe statistics of one match set (Sec. 3.4: tracking adds a keyframe

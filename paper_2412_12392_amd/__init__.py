@@ -6,8 +6,8 @@ Everything runs in libm3s.so: hand-written HIP kernels for gfx950 behind the C
 ABI of include/m3s.h.  This package is its thin Python binding over torch device
 tensors.  Build the library with ``python -m paper_2412_12392_amd.build``.
 """
-from .binding import (EdgeInput, MatchFunction, MatchResult, backend_gn, backend_params,  # noqa: F401
-                    fuse_pointmap, last_batched_config,
-                    make_edges, match, match_backward, match_noalloc, match_batched, match_stats, params, path_counters, set_launch,
-                    track_params, track_pose)
+from .binding import (BwdEdgeInput, EdgeInput, MatchFunction, MatchResult, backend_gn,  # noqa: F401
+                      backend_params, fuse_pointmap, last_batched_config, make_bwd_edges, make_edges, match,
+                      match_backward, match_backward_batched, match_batched, match_noalloc, match_stats, params,
+                      path_counters, set_launch, track_params, track_pose)
 from ._lib import M3SError, load as load_library  # noqa: F401

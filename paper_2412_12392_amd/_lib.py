@@ -39,6 +39,12 @@ class Edge(ctypes.Structure):
                 ("refine_radius", ctypes.c_int32)]
 
 
+class BwdEdge(ctypes.Structure):
+    _fields_ = [("H", ctypes.c_int32), ("W", ctypes.c_int32), ("Xii", ctypes.c_void_p), ("Xji", ctypes.c_void_p),
+                ("p", ctypes.c_void_p), ("valid", ctypes.c_void_p), ("grad_p", ctypes.c_void_p),
+                ("grad_xhat", ctypes.c_void_p), ("grad_Xii", ctypes.c_void_p), ("grad_Xji", ctypes.c_void_p)]
+
+
 class TrackParams(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("q_min", ctypes.c_float), ("sigma_ray", ctypes.c_float),
                 ("sigma_dist", ctypes.c_float), ("huber", ctypes.c_float)]
@@ -88,7 +94,8 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_timing_enable", "m3s_timing_read", "m3s_timing_reset", "m3s_stats_workspace_bytes",
            "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
            "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn",
-           "m3s_debug_set_launch", "m3s_path_counters", "m3s_match_fwd_noalloc"]
+           "m3s_debug_set_launch", "m3s_path_counters", "m3s_match_fwd_noalloc",
+           "m3s_bwd_batched_workspace_bytes", "m3s_match_bwd_batched"]
 
 _lib = None
 
@@ -113,6 +120,10 @@ def load(path: str = LIB_PATH):
     lib.m3s_match_fwd_noalloc.restype = ctypes.c_int
     lib.m3s_match_bwd.argtypes = [PP, PO, vp, vp, vp, vp, vp]
     lib.m3s_match_bwd.restype = ctypes.c_int
+    lib.m3s_bwd_batched_workspace_bytes.argtypes = [i32]
+    lib.m3s_bwd_batched_workspace_bytes.restype = sz
+    lib.m3s_match_bwd_batched.argtypes = [ctypes.POINTER(BwdEdge), i32, u32, vp, sz, vp]
+    lib.m3s_match_bwd_batched.restype = ctypes.c_int
     lib.m3s_batched_workspace_bytes.argtypes = [PE, i32, P]
     lib.m3s_batched_workspace_bytes.restype = sz
     lib.m3s_match_batched.argtypes = [PE, i32, P, u32, vp, sz, vp]

@@ -171,6 +171,50 @@ def match_backward(Xii, Xji, p, valid, grad_p, grad_xhat=None, stream=None):
     return gXii, gXji
 
 
+@dataclass
+class BwdEdgeInput:
+    Xii: torch.Tensor                 # (H, W, 3)
+    Xji: torch.Tensor                 # (H, W, 3)
+    p: torch.Tensor                   # (H, W, 2) forward p*
+    valid: torch.Tensor               # (H, W) uint8
+    grad_p: torch.Tensor              # (H, W, 2)
+    grad_xhat: Optional[torch.Tensor] = None   # (H, W, 3)
+
+
+def make_bwd_edges(inputs: Sequence[BwdEdgeInput], outs=None):
+    """Host backward edge table plus freshly allocated (or given) (grad_Xii, grad_Xji) per edge."""
+    n = len(inputs)
+    table = (_lib.BwdEdge * n)()
+    grads = []
+    for k, e in enumerate(inputs):
+        H, W = e.Xii.shape[:2]
+        if outs is not None:
+            gi, gj = outs[k]
+        else:
+            gi = torch.empty((H, W, 3), dtype=torch.float32, device=e.Xii.device)
+            gj = torch.empty((H, W, 3), dtype=torch.float32, device=e.Xii.device)
+        table[k] = _lib.BwdEdge(H, W, _ptr(e.Xii, shape=(H, W, 3)), _ptr(e.Xji, shape=(H, W, 3)),
+                                _ptr(e.p, shape=(H, W, 2)), _ptr(e.valid, torch.uint8, shape=(H, W)),
+                                _ptr(e.grad_p, shape=(H, W, 2)), _ptr(e.grad_xhat, shape=(H, W, 3)),
+                                _ptr(gi, shape=(H, W, 3)), _ptr(gj, shape=(H, W, 3)))
+        grads.append((gi, gj))
+    return table, grads
+
+
+def match_backward_batched(inputs: Sequence[BwdEdgeInput], graph: bool = True, outs=None, stream=None):
+    """m3s_match_bwd_batched: the implicit adjoint of every edge in one persistent launch
+    (after one launch that zeroes every grad_Xii); returns [(grad_Xii, grad_Xji)] per edge."""
+    lib = _lib.load()
+    table, grads = make_bwd_edges(inputs, outs)
+    n = len(inputs)
+    nbytes = lib.m3s_bwd_batched_workspace_bytes(n)
+    ws = _workspace(nbytes, inputs[0].Xii.device, stream)
+    flags = _lib.M3S_BATCH_GRAPH if graph else 0
+    st = lib.m3s_match_bwd_batched(table, n, flags, ws.data_ptr(), ws.numel(), _stream(stream))
+    _lib.check(lib, "m3s_match_bwd_batched", st)
+    return grads
+
+
 def make_edges(inputs: Sequence[EdgeInput], want_theta=True, want_xhat=False, outs=None):
     """Host edge table plus freshly allocated (or given) outputs."""
     n = len(inputs)

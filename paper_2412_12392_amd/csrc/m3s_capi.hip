@@ -117,6 +117,31 @@ m3s_status check_outputs(const m3s_outputs* O) {
     return M3S_OK;
 }
 
+m3s_status check_bwd(int32_t H, int32_t W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
+                     const float* grad_p, const float* grad_xhat, const float* grad_Xii, const float* grad_Xji) {
+    m3s_status s = check_shape(H, W);
+    if (s != M3S_OK) return s;
+    if (!Xii || !Xji) return fail(M3S_ERR_NULL, "Xii and Xji are required");
+    if (!aligned(Xii, 4) || !aligned(Xji, 4)) return fail(M3S_ERR_PARAM, "pointmaps must be 4-byte aligned");
+    if (!p || !valid) return fail(M3S_ERR_NULL, "forward outputs p and valid are required");
+    if (!grad_p || !grad_Xii || !grad_Xji) return fail(M3S_ERR_NULL, "grad_p, grad_Xii and grad_Xji are required");
+    if (!aligned(p, 4) || !aligned(grad_p, 4) || !aligned(grad_Xii, 4) || !aligned(grad_Xji, 4) ||
+        (grad_xhat && !aligned(grad_xhat, 4)))
+        return fail(M3S_ERR_PARAM, "gradients must be 4-byte aligned");
+    return M3S_OK;
+}
+
+m3s::BwdEdgeArgs make_bwd_edge(int32_t H, int32_t W, const float* Xii, const float* Xji, const float* p,
+                               const uint8_t* valid, const float* grad_p, const float* grad_xhat, float* grad_Xii,
+                               float* grad_Xji) {
+    m3s::BwdEdgeArgs B;
+    std::memset(&B, 0, sizeof B);
+    B.H = H; B.W = W; B.tiles_x = (W + 15) / 16; B.tiles_y = (H + 15) / 16; B.tile_begin = 0;
+    B.Xii = Xii; B.Xji = Xji; B.p = p; B.valid = valid; B.grad_p = grad_p; B.grad_xhat = grad_xhat;
+    B.dXii = grad_Xii; B.dXji = grad_Xji;
+    return B;
+}
+
 size_t ray_bytes(int32_t H, int32_t W) { return align_up((size_t)H * W * m3s::kRecF4 * sizeof(float4)); }
 
 // Descriptors go to registers with 16-byte loads when D == 24 and both arrays are 16-byte aligned.
@@ -457,19 +482,98 @@ m3s_status m3s_match_fwd_noalloc(const m3s_pair* pair, const m3s_params* params,
 
 m3s_status m3s_match_bwd(const m3s_pair* pair, const m3s_outputs* fwd, const float* grad_p, const float* grad_xhat,
                          float* grad_Xii, float* grad_Xji, void* stream) {
-    m3s_status s = check_pair(pair, false);
+    if (!pair) return fail(M3S_ERR_NULL, "pair is NULL");
+    if (!fwd) return fail(M3S_ERR_NULL, "forward outputs p and valid are required");
+    m3s_status s = check_bwd(pair->H, pair->W, pair->Xii, pair->Xji, fwd->p, fwd->valid, grad_p, grad_xhat, grad_Xii,
+                             grad_Xji);
     if (s != M3S_OK) return s;
-    if (!fwd || !fwd->p || !fwd->valid) return fail(M3S_ERR_NULL, "forward outputs p and valid are required");
-    if (!grad_p || !grad_Xii || !grad_Xji) return fail(M3S_ERR_NULL, "grad_p, grad_Xii and grad_Xji are required");
-    if (!aligned(fwd->p, 4) || !aligned(grad_p, 4) || !aligned(grad_Xii, 4) || !aligned(grad_Xji, 4) ||
-        (grad_xhat && !aligned(grad_xhat, 4)))
-        return fail(M3S_ERR_PARAM, "gradients must be 4-byte aligned");
     int dev;
     DeviceInfo info;
     if ((s = current_device(&dev, &info)) != M3S_OK) return s;
-    hipError_t e = m3s::launch_bwd(pair->H, pair->W, pair->Xii, pair->Xji, fwd->p, fwd->valid, grad_p, grad_xhat,
-                                   grad_Xii, grad_Xji, reinterpret_cast<hipStream_t>(stream));
+    hipError_t e = m3s::launch_bwd(make_bwd_edge(pair->H, pair->W, pair->Xii, pair->Xji, fwd->p, fwd->valid, grad_p,
+                                                 grad_xhat, grad_Xii, grad_Xji),
+                                   reinterpret_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "backward launch");
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+size_t m3s_bwd_batched_workspace_bytes(int32_t n_edges) {
+    if (n_edges < 1 || n_edges > (1 << 20)) return 0;
+    return align_up(sizeof(int32_t)) + align_up(sizeof(m3s::BwdEdgeArgs) * (size_t)n_edges);
+}
+
+m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uint32_t flags, void* ws,
+                                 size_t ws_bytes, void* stream) {
+    if (!edges) return fail(M3S_ERR_NULL, "edges is NULL");
+    if (n_edges < 1 || n_edges > (1 << 20)) return fail(M3S_ERR_SHAPE, "n_edges %d outside [1, 2^20]", n_edges);
+    if (flags & ~(uint32_t)M3S_BATCH_GRAPH) return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
+    std::vector<m3s::BwdEdgeArgs> table((size_t)n_edges);
+    int64_t tiles = 0;
+    long max_px = 0;
+    std::string sig = "B";
+    char buf[64];
+    for (int k = 0; k < n_edges; ++k) {
+        const m3s_bwd_edge& E = edges[k];
+        m3s_status s = check_bwd(E.H, E.W, E.Xii, E.Xji, E.p, E.valid, E.grad_p, E.grad_xhat, E.grad_Xii, E.grad_Xji);
+        if (s != M3S_OK) return fail(s, "edge %d: %s", k, g_last_error.c_str());
+        table[k] = make_bwd_edge(E.H, E.W, E.Xii, E.Xji, E.p, E.valid, E.grad_p, E.grad_xhat, E.grad_Xii, E.grad_Xji);
+        table[k].tile_begin = (int32_t)tiles;
+        tiles += (int64_t)table[k].tiles_x * table[k].tiles_y;
+        if (tiles > INT32_MAX / 2) return fail(M3S_ERR_SHAPE, "batch too large");
+        max_px = std::max(max_px, (long)E.H * E.W);
+        snprintf(buf, sizeof buf, "%d,%d;", E.H, E.W);
+        sig += buf;
+    }
+    const size_t need = m3s_bwd_batched_workspace_bytes(n_edges);
+    if (!ws || !aligned(ws, kAlign) || ws_bytes < need)
+        return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", need, ws_bytes);
+    int dev;
+    DeviceInfo info;
+    m3s_status s = current_device(&dev, &info);
+    if (s != M3S_OK) return s;
+    hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+    if (capturing(st))
+        return fail(M3S_ERR_UNSUPPORTED,
+                    "m3s_match_bwd_batched cannot be captured: it copies its edge table from host memory before every "
+                    "launch; M3S_BATCH_GRAPH gives a library-managed graph instead");
+    char* W = reinterpret_cast<char*>(ws);
+    int32_t* counter = reinterpret_cast<int32_t*>(W);
+    auto* dtable = reinterpret_cast<m3s::BwdEdgeArgs*>(W + align_up(sizeof(int32_t)));
+    hipError_t e = hipMemcpyAsync(dtable, table.data(), sizeof(m3s::BwdEdgeArgs) * table.size(), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(backward edge table)");
+    const int grid = std::max(1, std::min((int)tiles, g_override.grid > 0 ? g_override.grid : info.cus * 4));
+    if ((flags & M3S_BATCH_GRAPH) && st != nullptr) {
+        std::string gkey = std::to_string(dev) + "|" + sig + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) +
+                           "|" + std::to_string(grid);
+        hipGraphExec_t exec = nullptr;
+        {
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            auto it = g_graphs.find(gkey);
+            if (it != g_graphs.end()) exec = it->second;
+        }
+        if (!exec) {
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            hipError_t le = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, counter, grid, st);
+            hipGraph_t graph = nullptr;
+            e = hipStreamEndCapture(st, &graph);
+            if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "captured launch"); }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            hipGraphDestroy(graph);
+            if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+            std::lock_guard<std::mutex> lk(g_cache_mu);
+            g_graphs[gkey] = exec;
+        }
+        m3s::timer_begin("batched_bwd_graph", st);
+        e = hipGraphLaunch(exec, st);
+        m3s::timer_end(st);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    } else {
+        e = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, counter, grid, st);
+        if (e != hipSuccess) return hip_fail(e, "batched backward launch");
+    }
     g_last_error.clear();
     return M3S_OK;
 }
@@ -782,6 +886,7 @@ const char* m3s_status_string(m3s_status s) {
         case M3S_ERR_WORKSPACE: return "workspace missing, misaligned or too small";
         case M3S_ERR_HIP: return "HIP runtime error";
         case M3S_ERR_UNSUPPORTED: return "unsupported device or flag";
+        default: break;
     }
     return "unknown status";
 }

@@ -85,34 +85,38 @@ __device__ __forceinline__ float4 rec_load(RayBuf rb, uint32_t byte_off) {
 
 // Ray error of Eq. 2 from the four ray records around p (A = (x0, y0),
 // B = (x0+1, y0), C = (x0, y0+1), D = (x0+1, y0+1)) with bilinear weights a, b.
+// FULL = false evaluates the cost only (the last trial of the LM needs nothing
+// else).  A degenerate sample (interpolated ray zero or not finite) costs +inf;
+// its Jacobian blocks are then not meaningful, and they are never used: a
+// trial of infinite cost is never accepted, and a degenerate starting sample
+// gives a non-finite step, which the LM rejects without moving.
+template <bool FULL>
 __device__ __forceinline__ void ray_error_from(const float4* A, const float4* B, const float4* C, const float4* D,
                                                float a, float b, float3 t, Sample& s) {
     float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
 #define M3S_BL(i, c) (w00 * A[i].c + w10 * B[i].c + w01 * C[i].c + w11 * D[i].c)
     float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
-    float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
-    float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = M3S_BL(2, x);
-#undef M3S_BL
     float n2 = rx * rx + ry * ry + rz * rz;
-    if (!(n2 > 0.0f) || !isfinite(n2)) {
-        s.c = INFINITY;
-        s.a00 = s.a01 = s.a11 = s.g0 = s.g1 = 0.f;
-        return;
-    }
+    const bool ok = n2 > 0.0f && n2 < INFINITY;  // false for 0, +inf and NaN
     float inv = rsq(n2);
     float p0 = rx * inv, p1 = ry * inv, p2 = rz * inv;
-    float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
-    float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
-    // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
-    float jx0 = (gxx - p0 * pgx) * inv, jx1 = (gxy - p1 * pgx) * inv, jx2 = (gxz - p2 * pgx) * inv;
-    float jy0 = (gyx - p0 * pgy) * inv, jy1 = (gyy - p1 * pgy) * inv, jy2 = (gyz - p2 * pgy) * inv;
     float e0 = p0 - t.x, e1 = p1 - t.y, e2 = p2 - t.z;
-    s.c = e0 * e0 + e1 * e1 + e2 * e2;
-    s.a00 = jx0 * jx0 + jx1 * jx1 + jx2 * jx2;
-    s.a01 = jx0 * jy0 + jx1 * jy1 + jx2 * jy2;
-    s.a11 = jy0 * jy0 + jy1 * jy1 + jy2 * jy2;
-    s.g0 = jx0 * e0 + jx1 * e1 + jx2 * e2;
-    s.g1 = jy0 * e0 + jy1 * e1 + jy2 * e2;
+    s.c = ok ? e0 * e0 + e1 * e1 + e2 * e2 : INFINITY;
+    if constexpr (FULL) {
+        float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
+        float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = M3S_BL(2, x);
+        float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
+        float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
+        // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
+        float jx0 = (gxx - p0 * pgx) * inv, jx1 = (gxy - p1 * pgx) * inv, jx2 = (gxz - p2 * pgx) * inv;
+        float jy0 = (gyx - p0 * pgy) * inv, jy1 = (gyy - p1 * pgy) * inv, jy2 = (gyz - p2 * pgy) * inv;
+        s.a00 = jx0 * jx0 + jx1 * jx1 + jx2 * jx2;
+        s.a01 = jx0 * jy0 + jx1 * jy1 + jx2 * jy2;
+        s.a11 = jy0 * jy0 + jy1 * jy1 + jy2 * jy2;
+        s.g0 = jx0 * e0 + jx1 * e1 + jx2 * e2;
+        s.g1 = jy0 * e0 + jy1 * e1 + jy2 * e2;
+    }
+#undef M3S_BL
 }
 
 // Ray records from the workspace in global memory.
@@ -142,8 +146,9 @@ struct WindowRays {
     GlobalRays g;
     __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D) const {
         const int lx = x0 - rx0, ly = y0 - ry0;
-        if (lx >= 0 && ly >= 0 && lx + 1 < rw && ly + 1 < rh) {
-            const float4* a = lds + kRecF4 * (ly * rw + lx);
+        // 0 <= lx <= rw - 2 and 0 <= ly <= rh - 2 (the whole cell in the window).
+        if ((uint32_t)lx < (uint32_t)(rw - 1) && (uint32_t)ly < (uint32_t)(rh - 1)) {
+            const float4* a = lds + (uint32_t)(kRecF4 * (ly * rw + lx));
             const float4* c = a + kRecF4 * rw;
 #pragma unroll
             for (int j = 0; j < kRecF4; ++j) {
@@ -159,17 +164,19 @@ struct WindowRays {
 };
 
 // Ray error of Eq. 2 at pixel (px, py) (inside the domain) for target ray t.
-template <class Src>
-__device__ __forceinline__ void sample_ray_error(const Src& src, int H, int W, float px, float py, float3 t, Sample& s) {
-    int x0 = min((int)floorf(px), W - 2);
-    int y0 = min((int)floorf(py), H - 2);
-    float a = px - (float)x0, b = py - (float)y0;
+// The cell origin is min(floor(p), size - 2), formed in fp32 (exact for
+// integers), so p = size - 1 lies on the last cell's far edge.
+template <bool FULL = true, class Src>
+__device__ __forceinline__ void sample_ray_error(const Src& src, float xcell, float ycell, float px, float py,
+                                                 float3 t, Sample& s) {
+    const float fx0 = fminf(floorf(px), xcell), fy0 = fminf(floorf(py), ycell);
+    const float a = px - fx0, b = py - fy0;
     float4 A[kRecF4], B[kRecF4], C[kRecF4], D[kRecF4];
-    src.fetch(x0, y0, A, B, C, D);
-    ray_error_from(A, B, C, D, a, b, t, s);
+    src.fetch((int)fx0, (int)fy0, A, B, C, D);
+    ray_error_from<FULL>(A, B, C, D, a, b, t, s);
 }
 
-__device__ __forceinline__ float clampf(float v, float lo, float hi) { return fminf(fmaxf(v, lo), hi); }
+__device__ __forceinline__ float clampf(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
 
 // Levenberg-Marquardt state of one query: current pixel, damping and the
 // sample at the current pixel.
@@ -180,35 +187,49 @@ struct LMState {
 
 template <class Src>
 __device__ __forceinline__ void lm_start(const Src& src, int H, int W, float lambda0, float3 t, LMState& st) {
-    sample_ray_error(src, H, W, st.px, st.py, t, st.cur);
+    sample_ray_error(src, (float)(W - 2), (float)(H - 2), st.px, st.py, t, st.cur);
     st.lambda = lambda0;
 }
 
+// Damped 2x2 step of Eq. 2's normal equations at the current state; false
+// when it is not finite.  A coordinate on its bound whose step points out of
+// the image is held, and the other coordinate takes its own 1-D damped step.
+// Returns the clamped trial pixel.
+__device__ __forceinline__ bool lm_step(const Sample& cur, float lambda, float px, float py, float xmax, float ymax,
+                                        float& qx, float& qy) {
+    float a00 = cur.a00 + lambda, a01 = cur.a01, a11 = cur.a11 + lambda;
+    float g0 = cur.g0, g1 = cur.g1;
+    float idet = rcp(a00 * a11 - a01 * a01);
+    float dx = -(a11 * g0 - a01 * g1) * idet;
+    float dy = -(a00 * g1 - a01 * g0) * idet;
+    if (!isfinite(dx) || !isfinite(dy)) return false;
+    bool hold_x = (px <= 0.f && dx < 0.f) || (px >= xmax && dx > 0.f);
+    bool hold_y = (py <= 0.f && dy < 0.f) || (py >= ymax && dy > 0.f);
+    if (__builtin_expect(hold_x | hold_y, 0)) {
+        float fx = -g0 * rcp(a00), fy = -g1 * rcp(a11);
+        dx = hold_x ? 0.f : fx;
+        dy = hold_y ? 0.f : fy;
+    }
+    qx = clampf(px + dx, 0.f, xmax);
+    qy = clampf(py + dy, 0.f, ymax);
+    return true;
+}
+
 // `iters` LM iterations on Eq. 2: damped 2x2 step, bound hold, clamp,
-// acceptance on strictly lower cost.
+// acceptance on strictly lower cost.  With `final` set these are the last
+// iterations of the query, and the last trial evaluates its cost only.
 template <class Src>
-__device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 t, int iters, LMState& st) {
+__device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 t, int iters, LMState& st,
+                                           bool final = true) {
     const float xmax = (float)(W - 1), ymax = (float)(H - 1);
+    const float xcell = (float)(W - 2), ycell = (float)(H - 2);
     float px = st.px, py = st.py, lambda = st.lambda;
     Sample cur = st.cur, nxt;
-    for (int it = 0; it < iters; ++it) {
-        float a00 = cur.a00 + lambda, a01 = cur.a01, a11 = cur.a11 + lambda;
-        float g0 = cur.g0, g1 = cur.g1;
-        float idet = rcp(a00 * a11 - a01 * a01);
-        float dx = -(a11 * g0 - a01 * g1) * idet;
-        float dy = -(a00 * g1 - a01 * g0) * idet;
-        if (!isfinite(dx) || !isfinite(dy)) { lambda *= 10.f; continue; }
-        // A coordinate on its bound whose step points out of the image is
-        // held; the other coordinate then takes its own 1-D damped step.
-        bool hold_x = (px <= 0.f && dx < 0.f) || (px >= xmax && dx > 0.f);
-        bool hold_y = (py <= 0.f && dy < 0.f) || (py >= ymax && dy > 0.f);
-        if (hold_x | hold_y) {
-            float fx = -g0 * rcp(a00), fy = -g1 * rcp(a11);
-            dx = hold_x ? 0.f : fx;
-            dy = hold_y ? 0.f : fy;
-        }
-        float qx = clampf(px + dx, 0.f, xmax), qy = clampf(py + dy, 0.f, ymax);
-        sample_ray_error(src, H, W, qx, qy, t, nxt);
+    const int full = final ? iters - 1 : iters;
+    for (int it = 0; it < full; ++it) {
+        float qx, qy;
+        if (!lm_step(cur, lambda, px, py, xmax, ymax, qx, qy)) { lambda *= 10.f; continue; }
+        sample_ray_error<true>(src, xcell, ycell, qx, qy, t, nxt);
         // Accept on strictly lower cost: selects, no branch.
         const bool acc = nxt.c < cur.c;
         px = acc ? qx : px;
@@ -220,6 +241,16 @@ __device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 
         cur.g0 = acc ? nxt.g0 : cur.g0;
         cur.g1 = acc ? nxt.g1 : cur.g1;
         lambda = acc ? lambda * 0.1f : lambda * 10.f;
+    }
+    if (final && iters > 0) {
+        float qx, qy;
+        if (lm_step(cur, lambda, px, py, xmax, ymax, qx, qy)) {
+            sample_ray_error<false>(src, xcell, ycell, qx, qy, t, nxt);
+            const bool acc = nxt.c < cur.c;
+            px = acc ? qx : px;
+            py = acc ? qy : py;
+            cur.c = acc ? nxt.c : cur.c;
+        }
     }
     st.px = px; st.py = py; st.lambda = lambda; st.cur = cur;
 }

@@ -40,8 +40,25 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
                           hipStream_t s);
 hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, uint32_t* bitmap, int32_t* counts,
                         hipStream_t s);
-hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
-                      const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s);
+// Backward of one edge: 16 x 16 query tiles (tiles_x x tiles_y), tile ids of
+// the batched launch start at tile_begin.
+struct BwdEdgeArgs {
+    int32_t H, W, tiles_x, tiles_y, tile_begin;
+    const float* Xii;
+    const float* Xji;
+    const float* p;
+    const uint8_t* valid;
+    const float* grad_p;
+    const float* grad_xhat;        // may be nullptr
+    float* dXii;
+    float* dXji;
+};
+hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s);
+// Zero every edge's dXii and reset the counter (one launch), then the
+// persistent backward over all edges' tiles (one launch).  max_pixels: the
+// largest H * W of the table.
+hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles,
+                              int32_t* counter, int grid, hipStream_t s);
 
 // Tracking pose solve (m3s_track.hip): workgroups of one iteration launch,
 // workspace bytes, and the launch sequence (init + iters + 1 launches).

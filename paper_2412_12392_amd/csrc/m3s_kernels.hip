@@ -358,11 +358,17 @@ __device__ __forceinline__ int wave_extreme(int v) {
 __device__ __forceinline__ int wave_min(int v) { return wave_extreme<false>(v); }
 __device__ __forceinline__ int wave_max(int v) { return wave_extreme<true>(v); }
 
-// ceil(2^32 / d): for 0 <= n < 2^16 and 1 <= d < 2^16, umulhi(n, magic) = n / d
-// (the rounding excess n (magic d - 2^32) / 2^32 stays below 1/d).
-__device__ __forceinline__ uint32_t div_magic(int d) {
-    return (uint32_t)((0x100000000ull + (unsigned long long)d - 1ull) / (unsigned long long)d);
-}
+// n / d for 0 <= n < 2^16 and 1 <= d < 2^16 with one 32-bit multiply-high:
+// magic = ceil(2^32 / d), and the rounding excess n (magic d - 2^32) / 2^32
+// stays below 1/d.  d = 1, whose magic 2^32 does not fit in 32 bits, is
+// taken apart (a one-column window or region).
+struct SmallDiv {
+    uint32_t magic;
+    bool one;
+    __device__ __forceinline__ explicit SmallDiv(int d)
+        : magic((uint32_t)((0x100000000ull + (unsigned long long)d - 1ull) / (unsigned long long)d)), one(d == 1) {}
+    __device__ __forceinline__ int operator()(int n) const { return one ? n : (int)__umulhi((uint32_t)n, magic); }
+};
 
 // Bounding box (lx, hx, ly, hy) over the block: min / max of every lane's
 // values (INT_MAX / INT_MIN for lanes without one).  Ends with a barrier.
@@ -393,12 +399,12 @@ template <int NT>
 __device__ __forceinline__ void stage_rays(const EdgeArgs& A, float4* lds, int lx, int ly, int rw, int rh) {
     const int tid = threadIdx.x;
     const int slots = kRecF4 * rw * rh;
-    const uint32_t magic = div_magic(rw);
+    const SmallDiv div_rw(rw);
     for (int c0 = tid & ~63; c0 < slots; c0 += NT) {
         const int c = c0 + (tid & 63);
         if (c < slots) {
             const int pix = c / kRecF4, j = c - kRecF4 * (c / kRecF4);
-            const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+            const int ry = div_rw(pix), rx = pix - ry * rw;
             __builtin_amdgcn_global_load_lds(A.rays + ((long)(ly + ry) * A.W + lx + rx) * kRecF4 + j,
                                              (__attribute__((address_space(3))) void*)(lds + c0), 16, 0, 0);
         }
@@ -444,10 +450,10 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
         if (ww) {
             const WindowRays wr{lds, wx, wy, ww, wh, g};
             lm_start(wr, H, W, A.lambda0, t, st);
-            lm_iterate(wr, H, W, t, first, st);
+            lm_iterate(wr, H, W, t, first, st, A.K == first);
         } else {
             lm_start(g, H, W, A.lambda0, t, st);
-            lm_iterate(g, H, W, t, first, st);
+            lm_iterate(g, H, W, t, first, st, A.K == first);
         }
     }
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
@@ -527,12 +533,12 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
         constexpr int kSlots = 6 * kRegionPx;
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
         const int np = rw * rh;
-        const uint32_t magic = div_magic(rw);
+        const SmallDiv div_rw(rw);
         for (int c0 = tid & ~63; c0 < kSlots; c0 += NT) {
             const int c = c0 + (tid & 63);
             const int k = c / kRegionPx, pix = c - (c / kRegionPx) * kRegionPx;
             if (k < 6 && pix < np) {
-                const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+                const int ry = div_rw(pix), rx = pix - ry * rw;
                 __builtin_amdgcn_global_load_lds(src4 + ((long)(ly + ry) * W + lx + rx) * 6 + k,
                                                  (__attribute__((address_space(3))) void*)(S.desc + c0), 16, 0, 0);
             }
@@ -622,10 +628,15 @@ __device__ __forceinline__ float exact24(const float* __restrict__ q, const floa
 
 // Pass 1 over a window that lies inside the image, for a radius R fixed at
 // compile time: the candidates of a row are unrolled (LDS addresses are the
-// row base plus immediate offsets) and their survivor bits are shifted into a
-// 128-bit word hi:lo, leaving candidate j of the window on bit N - 1 - j; a
-// bit reversal then gives the row-major masks of the generic pass (candidate
-// j on bit j).  w: LDS record of the window's top-left candidate.
+// row base plus immediate offsets), the row's scores are kept in registers,
+// the running maximum takes the row's maximum, and each candidate of the row
+// survives if its score is within tau of that running maximum.  A candidate
+// that survives against the final maximum survives against any earlier one,
+// so no candidate that can be the exact maximum is dropped.  The survivor
+// bits are shifted into a 128-bit word hi:lo, leaving candidate j of the
+// window on bit N - 1 - j; a bit reversal then gives the row-major masks of
+// the generic pass (candidate j on bit j).  w: LDS record of the window's
+// top-left candidate.
 template <int R>
 __device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* __restrict__ w, int rw, float tau,
                                               float& run, uint64_t& mask0, uint64_t& mask1) {
@@ -634,13 +645,17 @@ __device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* 
     uint64_t lo = 0, hi = 0;
 #pragma unroll 1
     for (int dy = 0; dy < S; ++dy, w += rw) {
+        float sc[S];
+#pragma unroll
+        for (int dx = 0; dx < S; ++dx) sc[dx] = dot16(q16, w[dx], w[dx + kRegionPx16], w[dx + 2 * kRegionPx16]);
+        float rm = sc[0];
+#pragma unroll
+        for (int dx = 1; dx < S; ++dx) rm = fmaxf(rm, sc[dx]);
+        run = fmaxf(run, rm);
+        const float thr = run - tau;
         uint32_t rb = 0;
 #pragma unroll
-        for (int dx = 0; dx < S; ++dx) {
-            const float s16 = dot16(q16, w[dx], w[dx + kRegionPx16], w[dx + 2 * kRegionPx16]);
-            run = fmaxf(run, s16);
-            rb = rb + rb + (s16 >= run - tau ? 1u : 0u);
-        }
+        for (int dx = 0; dx < S; ++dx) rb = rb + rb + (sc[dx] >= thr ? 1u : 0u);
         hi = (hi << S) | (lo >> (64 - S));
         lo = (lo << S) | rb;
     }
@@ -770,14 +785,14 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
         constexpr int kBatch = 2;
         const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
         const int total = rw * rh;
-        const uint32_t magic = div_magic(rw);
+        const SmallDiv div_rw(rw);
         for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
             float4 v[kBatch][6];
 #pragma unroll
             for (int i = 0; i < kBatch; ++i) {
                 const int pix = p00 + tid + i * NT;
                 if (pix < total) {
-                    const int ry = (int)__umulhi((uint32_t)pix, magic), rx = pix - ry * rw;
+                    const int ry = div_rw(pix), rx = pix - ry * rw;
                     const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
 #pragma unroll
                     for (int k = 0; k < 6; ++k) v[i][k] = src[k];
@@ -1028,18 +1043,15 @@ constexpr int kBwdLdsPx = 1536;
 // LDS window covering every corner its queries touch (LDS float atomics) and
 // then added to global memory once per window entry, in row order; a tile
 // whose window exceeds kBwdLdsPx adds each corner to global memory directly.
-__global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __restrict__ Xii,
-                                                  const float* __restrict__ Xji, const float* __restrict__ p,
-                                                  const uint8_t* __restrict__ valid, const float* __restrict__ grad_p,
-                                                  const float* __restrict__ grad_xhat, float* __restrict__ dXii,
-                                                  float* __restrict__ dXji, int tiles_x) {
-    __shared__ float acc[3 * kBwdLdsPx];
-    __shared__ int box[4 * 4];
+// All 256 lanes of the block call this; it ends without a barrier, so a
+// caller that reuses acc for another tile synchronises first.
+__device__ __forceinline__ void bwd_tile(const BwdEdgeArgs& B, int tile, float* acc, int* box) {
+    const int H = B.H, W = B.W;
     const int tid = threadIdx.x;
     // The whole accumulator is cleared up front, overlapped with the query
     // reads; the barriers of block_box order it before the atomics.
     for (int i = tid; i < 3 * kBwdLdsPx; i += 256) acc[i] = 0.f;
-    const int x = (blockIdx.x % tiles_x) * 16 + (tid & 15), y = (blockIdx.x / tiles_x) * 16 + (tid >> 4);
+    const int x = (tile % B.tiles_x) * 16 + (tid & 15), y = (tile / B.tiles_x) * 16 + (tid >> 4);
     const bool inside = x < W && y < H;
     const long n = (long)y * W + x;
     long cm[4] = {-1, -1, -1, -1};
@@ -1047,16 +1059,17 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     int cx0 = 0, cy0 = 0;  // cell of p*: corner c is (cx0 + (c & 1), cy0 + (c >> 1))
     if (inside) {
-        if (!valid[n]) {
-            dXji[3 * n] = 0.f; dXji[3 * n + 1] = 0.f; dXji[3 * n + 2] = 0.f;
+        if (!B.valid[n]) {
+            B.dXji[3 * n] = 0.f; B.dXji[3 * n + 1] = 0.f; B.dXji[3 * n + 2] = 0.f;
         } else {
-            bwd_query(H, W, Xii, Xji, p, grad_p, grad_xhat, dXji, n, cm, gc, cx0, cy0);
+            bwd_query(H, W, B.Xii, B.Xji, B.p, B.grad_p, B.grad_xhat, B.dXji, n, cm, gc, cx0, cy0);
             lx = cx0; hx = cx0 + 1; ly = cy0; hy = cy0 + 1;
         }
     }
     block_box<256>(lx, hx, ly, hy, box);
     const int bw = hx - lx + 1, bh = hy - ly + 1;
     const bool any = hx >= lx;
+    float* __restrict__ dXii = B.dXii;
     if (any && bw * bh <= kBwdLdsPx) {
         const int cnt = 3 * bw * bh;
 #pragma unroll
@@ -1069,11 +1082,11 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
             atomicAdd(a + 2, gc[c].z);
         }
         __syncthreads();
-        const uint32_t magic = div_magic(3 * bw);
+        const SmallDiv div_row(3 * bw);
         for (int i = tid; i < cnt; i += 256) {
             const float v = acc[i];
             if (v == 0.f) continue;
-            const int row = (int)__umulhi((uint32_t)i, magic), col = i - row * 3 * bw;
+            const int row = div_row(i), col = i - row * 3 * bw;
             unsafeAtomicAdd(dXii + 3 * ((long)(ly + row) * W + lx) + col, v);
         }
     } else {
@@ -1085,6 +1098,61 @@ __global__ void __launch_bounds__(256) bwd_kernel(int H, int W, const float* __r
             unsafeAtomicAdd(dXii + 3 * cm[c] + 1, gc[c].y);
             unsafeAtomicAdd(dXii + 3 * cm[c] + 2, gc[c].z);
         }
+    }
+}
+
+__global__ void __launch_bounds__(256) bwd_kernel(BwdEdgeArgs B) {
+    __shared__ float acc[3 * kBwdLdsPx];
+    __shared__ int box[4 * 4];
+    bwd_tile(B, blockIdx.x, acc, box);
+}
+
+// Zeroes dXii of every edge of a batched backward (blockIdx.y = edge, grid-
+// stride over blockIdx.x) and resets the work-queue counter.
+__global__ void __launch_bounds__(256) batched_bwd_zero_kernel(const BwdEdgeArgs* __restrict__ E,
+                                                               int32_t* __restrict__ counter) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) counter[0] = 0;
+    const BwdEdgeArgs& B = E[blockIdx.y];
+    float* __restrict__ a = B.dXii;
+    const long count = 3L * B.H * B.W;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long stride = (long)gridDim.x * blockDim.x;
+    const long head = min(count, (long)(((16u - ((uint32_t)(uintptr_t)a & 15u)) & 15u) >> 2));
+    if (i < head) a[i] = 0.f;
+    float4* __restrict__ b = reinterpret_cast<float4*>(a + head);
+    const long nb = (count - head) >> 2;
+    for (long j = i; j < nb; j += stride) store_nt(b + j, make_float4(0.f, 0.f, 0.f, 0.f));
+    const long t = head + (nb << 2) + i;
+    if (t < count && i < 4) a[t] = 0.f;
+}
+
+// Edge of a global backward tile id: the last edge whose tile_begin <= tile.
+__device__ __forceinline__ int find_bwd_edge(const BwdEdgeArgs* __restrict__ E, int n_edges, int tile) {
+    int lo = 0, hi = n_edges - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (E[mid].tile_begin <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Persistent backward over every edge: workgroups pop 16 x 16 tiles from the
+// counter until none is left (every workgroup exits once the counter passes
+// the last tile).  dXii of every edge was zeroed by the previous launch.
+__global__ void __launch_bounds__(256) batched_bwd_kernel(const BwdEdgeArgs* __restrict__ E, int n_edges,
+                                                          int total_tiles, int32_t* __restrict__ counter) {
+    __shared__ float acc[3 * kBwdLdsPx];
+    __shared__ int box[4 * 4];
+    __shared__ int s_tile;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+        __syncthreads();  // also: the previous tile's reads of acc are done
+        const int tile = s_tile;
+        __syncthreads();
+        if (tile >= total_tiles) return;
+        const int e = find_bwd_edge(E, n_edges, tile);
+        const BwdEdgeArgs B = E[e];
+        bwd_tile(B, tile - B.tile_begin, acc, box);
     }
 }
 
@@ -1231,15 +1299,25 @@ hipError_t read_path_counters(int64_t* out, bool reset) {
     return e;
 }
 
-hipError_t launch_bwd(int H, int W, const float* Xii, const float* Xji, const float* p, const uint8_t* valid,
-                      const float* grad_p, const float* grad_xhat, float* dXii, float* dXji, hipStream_t s) {
-    long N = (long)H * W;
+hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s) {
+    long N = (long)B.H * B.W;
     timer_begin("fill", s);
-    fill_zero_kernel<<<min(blocks_for(3 * N / 4 + 1, 256), 4096u), 256, 0, s>>>(dXii, 3 * N);
+    fill_zero_kernel<<<min(blocks_for(3 * N / 4 + 1, 256), 4096u), 256, 0, s>>>(B.dXii, 3 * N);
     timer_end(s);
-    const int tiles_x = (W + 15) / 16, tiles_y = (H + 15) / 16;
     timer_begin("bwd", s);
-    bwd_kernel<<<tiles_x * tiles_y, 256, 0, s>>>(H, W, Xii, Xji, p, valid, grad_p, grad_xhat, dXii, dXji, tiles_x);
+    bwd_kernel<<<B.tiles_x * B.tiles_y, 256, 0, s>>>(B);
+    timer_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles,
+                              int32_t* counter, int grid, hipStream_t s) {
+    timer_begin("batched_bwd_zero", s);
+    const unsigned zx = min(blocks_for(3 * max_pixels / 4 + 1, 256), 1024u);
+    batched_bwd_zero_kernel<<<dim3(zx, (unsigned)n_edges), 256, 0, s>>>(table, counter);
+    timer_end(s);
+    timer_begin("batched_bwd", s);
+    batched_bwd_kernel<<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
     timer_end(s);
     return hipGetLastError();
 }

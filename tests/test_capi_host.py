@@ -388,3 +388,40 @@ int main(void) {
     lib.m3s_debug_set_launch(ctypes.byref(cfg))
     lib.m3s_debug_set_launch(None)
     assert lib.m3s_path_counters(None, 0) == 1
+
+
+def test_bwd_batched_validation(tmp_path, lib):
+    """m3s_match_bwd_batched: struct layout, workspace size and argument errors before any HIP call."""
+    prog = tmp_path / "bwdb.c"
+    prog.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "m3s.h"
+int main(void) {
+  printf("%zu %zu %zu\n", sizeof(m3s_bwd_edge), offsetof(m3s_bwd_edge, grad_xhat), offsetof(m3s_bwd_edge, grad_Xji));
+  return 0;
+}''')
+    exe = tmp_path / "bwdb"
+    subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    assert vals == [ctypes.sizeof(_lib.BwdEdge), _lib.BwdEdge.grad_xhat.offset, _lib.BwdEdge.grad_Xji.offset]
+    assert lib.m3s_bwd_batched_workspace_bytes(0) == 0
+    need = lib.m3s_bwd_batched_workspace_bytes(3)
+    assert need >= 256 + 3 * 80
+    base = (ctypes.addressof(_ws) + 255) // 256 * 256
+    good = _lib.BwdEdge(4, 4, _addr, _addr, _addr, _addr, _addr, 0, _addr, _addr)
+    cases = [
+        (None, 1, 0, (base, 1024), 1),
+        ([good], 0, 0, (base, 1024), 2),
+        ([good], 1, 0x4, (base, 1024), 6),
+        ([_lib.BwdEdge(1, 4, _addr, _addr, _addr, _addr, _addr, 0, _addr, _addr)], 1, 0, (base, 1024), 2),
+        ([_lib.BwdEdge(4, 4, 0, _addr, _addr, _addr, _addr, 0, _addr, _addr)], 1, 0, (base, 1024), 1),
+        ([_lib.BwdEdge(4, 4, _addr, _addr, _addr, _addr, 0, 0, _addr, _addr)], 1, 0, (base, 1024), 1),
+        ([_lib.BwdEdge(4, 4, _addr, _addr, _addr, _addr, _addr, 0, _addr + 2, _addr)], 1, 0, (base, 1024), 3),
+        ([good], 1, 0, (0, 0), 4),
+        ([good], 1, 0, (base + 4, 1024), 4),
+    ]
+    for edges, n, flags, (ws, nb), expect in cases:
+        arr = None if edges is None else (_lib.BwdEdge * len(edges))(*edges)
+        st = lib.m3s_match_bwd_batched(arr, n, flags, ws, nb, None)
+        assert st == expect, (edges, n, flags, st, lib.m3s_last_error())

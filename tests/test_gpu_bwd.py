@@ -136,3 +136,45 @@ def corner_pixels(p, mask):
         for dx in (0, 1):
             out[y0 + dy, x0 + dx] = True
     return out
+
+
+def test_bwd_batched_matches_per_edge(m3s):
+    """m3s_match_bwd_batched over edges of mixed size (with and without
+    grad_xhat) against m3s_match_bwd per edge: dXji bit for bit, dXii up to the
+    order of the fp32 atomics; eager, graph capture and graph replay; two edges
+    against the oracle's adjoint element by element."""
+    import torch
+    dims = [(48, 64), (37, 53), (96, 128), (2, 2), (130, 70)]
+    pairs = [synth.make_pair(H, W, 820 + k) for k, (H, W) in enumerate(dims)]
+    inputs, refs, fed = [], [], []
+    for k, pr in enumerate(pairs):
+        t = parity.pair_tensors(pr)
+        res = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"], want_xhat=True)
+        rng = np.random.Generator(np.random.PCG64(900 + k))
+        gp = parity.to_dev(rng.normal(size=(pr.H, pr.W, 2)))
+        gx = None if k == 1 else parity.to_dev(rng.normal(size=(pr.H, pr.W, 3)))
+        inputs.append(m3s.BwdEdgeInput(t["Xii"], t["Xji"], res.p, res.valid, gp, gx))
+        refs.append(m3s.match_backward(t["Xii"], t["Xji"], res.p, res.valid, gp, gx))
+        fed.append((res.p, res.valid, gp, gx))
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for rep, graph in enumerate((False, True, True)):
+        print("case bwd batched rep %d graph %s" % (rep, graph), flush=True)
+        with torch.cuda.stream(s):
+            outs = m3s.match_backward_batched(inputs, graph=graph)
+        s.synchronize()
+        torch.zeros(100, device="cuda").sum().item()  # unrelated eager work between replays
+        for k, ((ri, rj), (gi, gj)) in enumerate(zip(refs, outs)):
+            assert torch.equal(rj, gj), (rep, k)
+            scale = max(float(ri.abs().max()), 1e-30)
+            assert float((gi - ri).abs().max()) <= 1e-6 * scale, (rep, k)
+    for k in (0, 2):
+        p, v, gp, gx = fed[k]
+        oi, oj = oracle.match_bwd(pairs[k].Xii, pairs[k].Xji, p.cpu().numpy().astype(np.float64),
+                                  v.cpu().numpy().astype(bool), gp.cpu().numpy(),
+                                  None if gx is None else gx.cpu().numpy())
+        gi, gj = (a.cpu().numpy() for a in outs[k])
+        mi = float(np.abs(gi - oi).max() / np.abs(oi).max())
+        mj = float(np.abs(gj - oj).max() / np.abs(oj).max())
+        print(dict(edge=k, max_rel_dXii=mi, max_rel_dXji=mj))
+        assert mi <= 1e-4 and mj <= 1e-4

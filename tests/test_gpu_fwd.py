@@ -85,6 +85,14 @@ def test_ragged_shapes(m3s, H, W):
     check(m3s, _pair(H, W, 31 * H + W), "%dx%d" % (H, W))
 
 
+@pytest.mark.parametrize("H,W,r", [(40, 2, 0), (40, 2, 3), (2, 40, 0), (2, 40, 3), (3, 2, 1)])
+def test_one_column_and_one_row_frames(m3s, H, W, r):
+    """Frames two pixels wide or tall: staged windows and refine regions one
+    column or one row wide (the staging's row/column split divides by 1)."""
+    check(m3s, _pair(H, W, 7 * H + W), "%dx%d r%d" % (H, W, r), r=r)
+    check(m3s, synth.identity_pair(H, W, 12), "identity %dx%d r%d" % (H, W, r), r=r)
+
+
 @pytest.mark.parametrize("K,r", [(0, 3), (1, 3), (3, 0), (10, 1), (15, 8), (30, 2)])
 def test_iterations_and_radius(m3s, K, r):
     check(m3s, _pair(48, 64, 7), "K%d r%d" % (K, r), K=K, r=r)
