@@ -538,7 +538,7 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
         for _ in range(max(2, args.warmup // 5)):
             call()
     s.synchronize()
-    grid, tile = m3s.last_batched_config()
+    launch = m3s.last_batched_launch()
     t0 = time.perf_counter()
     with torch.cuda.stream(s):
         for _ in range(steps):
@@ -579,7 +579,7 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
            "batched_matches_per_s": round(queries / el_b, 1), "batched_ms": round(el_b * 1e3, 4),
            "graph_launch_ms_events": round(graph_ms, 4),
            "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
-           "speedup_vs_per_pair": round(el_p / el_b, 3), "launch": {"grid": grid, "tile_config": tile},
+           "speedup_vs_per_pair": round(el_p / el_b, 3), "launch": launch,
            "algorithmic_GBs": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9, 1),
            "frac_of_hbm_peak": round(queries * FWD_BYTES_PER_QUERY / el_b / 1e9 / HBM_PEAK_GBS, 4)}
     log("batched:", res)

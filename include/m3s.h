@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define M3S_VERSION 1
+#define M3S_VERSION 2
 #define M3S_MAX_RADIUS 8      /* largest refine radius r */
 #define M3S_MAX_ITER 1000     /* largest LM iteration count K */
 #define M3S_MAX_DESC 64       /* largest descriptor dimension D */
@@ -226,8 +226,8 @@ m3s_status m3s_match_stats(const m3s_outputs *fwd, int32_t H, int32_t W, int32_t
  * keyframe k with the keyframe's pixels as queries (m3s_match_fwd with
  * Xii = X^f_f and Xji = X^k_f), so idx[n] is the frame pixel m of keyframe
  * pixel n.  The pose T_kf = [sR | t] (Sim(3), maps frame points into the
- * keyframe) is refined by Gauss-Newton in an iteratively reweighted
- * least-squares loop (Eq. gauss_newton) over every valid match with
+ * keyframe) is refined by Gauss-Newton with robust weights recomputed at
+ * every iteration (Eq. gauss_newton) over every valid match with
  * q = sqrt(Qf[m] Qk[n]) > q_min:
  *   ray residual      psi(T Xf[m]) - psi(Xk[n])    weight q / sigma_ray^2
  *   distance residual |T Xf[m]| - |Xk[n]|           weight q / sigma_dist^2
@@ -391,8 +391,10 @@ size_t m3s_batched_workspace_bytes(const m3s_edge *edges, int32_t n_edges, const
  * into a hipGraph keyed by (device, workspace address, edge shapes) and
  * replayed on later calls with the same key; the edge table lives in the
  * workspace, so new pointers need no re-capture.  With M3S_BATCH_AUTOTUNE
- * the first call for a shape signature times candidate launch shapes
- * (synchronising the stream) and caches the fastest.  Calls that share a
+ * the first call for a shape signature times candidate launch shapes (see
+ * m3s_set_tune_cache; this first call synchronises the stream) and caches the
+ * fastest; later calls with that signature, in this process or, with a cache
+ * file, in another, are asynchronous.  Calls that share a
  * workspace must not overlap.  The call cannot itself be captured into a
  * caller's hipGraph (it copies the edge table from host memory before each
  * launch): on a capturing stream it returns M3S_ERR_UNSUPPORTED.
@@ -414,16 +416,36 @@ void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
  *                memory; 3: 16x16, 4: 32x8 with the refine region staged in LDS
  *                (fp32); 5: 16x16 with an fp16 pre-filter (the default);
  *   grid         workgroups of the persistent batched launch (> 0);
- *   xcd_remap    0 turns off the tile-to-XCD band mapping of the single-pair launch.
+ *   xcd_remap    0 turns off the tile-to-XCD band mapping of the single-pair launch;
+ *   ray_margin   margin in pixels (1..3, default 2) of the LM ray window the
+ *                batched fp16 configuration stages around its queries' cells;
+ *   lm_unroll    unroll factor (1 or 2) of its LM iteration loop.
  * An override also disables M3S_BATCH_AUTOTUNE.  Every configuration gives
- * the same output bits.
+ * the same output bits.  m3s_batched_last_launch reads back the launch the
+ * calling thread's last m3s_match_batched used (xcd_remap -1).
  */
 typedef struct {
     int32_t tile_config;
     int32_t grid;
     int32_t xcd_remap;
+    int32_t ray_margin;
+    int32_t lm_unroll;
 } m3s_launch_config;
 void m3s_debug_set_launch(const m3s_launch_config *cfg);
+void m3s_batched_last_launch(m3s_launch_config *cfg);
+
+/*
+ * Autotuning cache on disk.  M3S_BATCH_AUTOTUNE times, once per batch shape,
+ * every tile configuration at 1, 2, 4 and 8 workgroups per CU and then, for
+ * the fp16 configuration, every ray-window margin and LM unroll at its best
+ * grid, and keeps the fastest launch keyed by (device architecture, CU count,
+ * shape signature of the edges).  m3s_set_tune_cache(path) loads the entries
+ * of a cache file written earlier (a missing file is fine; a file of another
+ * format or version returns M3S_ERR_PARAM and changes nothing) and from then
+ * on writes every new result back to it (a temporary file renamed over the
+ * old one).  NULL stops writing; the results already loaded stay.
+ */
+m3s_status m3s_set_tune_cache(const char *path);
 
 /*
  * Counters of the fallback paths taken on the current device since the last

@@ -73,7 +73,8 @@ class BackendProblem(ctypes.Structure):
 
 
 class LaunchConfig(ctypes.Structure):
-    _fields_ = [("tile_config", ctypes.c_int32), ("grid", ctypes.c_int32), ("xcd_remap", ctypes.c_int32)]
+    _fields_ = [("tile_config", ctypes.c_int32), ("grid", ctypes.c_int32), ("xcd_remap", ctypes.c_int32),
+                ("ray_margin", ctypes.c_int32), ("lm_unroll", ctypes.c_int32)]
 
 
 M3S_PATH_COUNTERS = 8
@@ -95,7 +96,8 @@ EXPORTS = ["m3s_default_params", "m3s_workspace_bytes", "m3s_match_fwd", "m3s_ma
            "m3s_match_stats", "m3s_default_track_params", "m3s_track_workspace_bytes", "m3s_track_pose",
            "m3s_fuse_pointmap", "m3s_default_backend_params", "m3s_backend_workspace_bytes", "m3s_backend_gn",
            "m3s_debug_set_launch", "m3s_path_counters", "m3s_match_fwd_noalloc",
-           "m3s_bwd_batched_workspace_bytes", "m3s_match_bwd_batched"]
+           "m3s_bwd_batched_workspace_bytes", "m3s_match_bwd_batched", "m3s_batched_last_launch",
+           "m3s_set_tune_cache"]
 
 _lib = None
 
@@ -166,6 +168,10 @@ def load(path: str = LIB_PATH):
     lib.m3s_backend_gn.restype = ctypes.c_int
     lib.m3s_debug_set_launch.argtypes = [ctypes.POINTER(LaunchConfig)]
     lib.m3s_debug_set_launch.restype = None
+    lib.m3s_batched_last_launch.argtypes = [ctypes.POINTER(LaunchConfig)]
+    lib.m3s_batched_last_launch.restype = None
+    lib.m3s_set_tune_cache.argtypes = [ctypes.c_char_p]
+    lib.m3s_set_tune_cache.restype = ctypes.c_int
     lib.m3s_path_counters.argtypes = [ctypes.POINTER(ctypes.c_int64), i32]
     lib.m3s_path_counters.restype = ctypes.c_int
     if path == LIB_PATH:

@@ -326,14 +326,29 @@ def backend_gn(Xc, Q, edges, idx, valid, T_WC, prm: Optional[_lib.BackendParams]
     return T_WC, info
 
 
-def set_launch(tile_config: int = -1, grid: int = -1, xcd_remap: int = -1):
+def set_launch(tile_config: int = -1, grid: int = -1, xcd_remap: int = -1, ray_margin: int = -1,
+               lm_unroll: int = -1):
     """m3s_debug_set_launch for the calling thread (all -1: the library's choice)."""
     lib = _lib.load()
-    if tile_config < 0 and grid <= 0 and xcd_remap < 0:
+    if tile_config < 0 and grid <= 0 and xcd_remap < 0 and ray_margin <= 0 and lm_unroll <= 0:
         lib.m3s_debug_set_launch(None)
     else:
-        cfg = _lib.LaunchConfig(tile_config, grid, xcd_remap)
+        cfg = _lib.LaunchConfig(tile_config, grid, xcd_remap, ray_margin, lm_unroll)
         lib.m3s_debug_set_launch(ctypes.byref(cfg))
+
+
+def last_batched_launch() -> dict:
+    """m3s_batched_last_launch: the launch the calling thread's last batched call used."""
+    lib = _lib.load()
+    cfg = _lib.LaunchConfig()
+    lib.m3s_batched_last_launch(ctypes.byref(cfg))
+    return dict(tile_config=cfg.tile_config, grid=cfg.grid, ray_margin=cfg.ray_margin, lm_unroll=cfg.lm_unroll)
+
+
+def set_tune_cache(path: Optional[str]):
+    """m3s_set_tune_cache: load and from now on update the on-disk autotuning cache (None: stop writing)."""
+    lib = _lib.load()
+    _lib.check(lib, "m3s_set_tune_cache", lib.m3s_set_tune_cache(None if path is None else path.encode()))
 
 
 def path_counters(reset: bool = False) -> dict:

@@ -21,7 +21,7 @@ using m3s::EdgeArgs;
 namespace {
 
 thread_local std::string g_last_error;
-thread_local int32_t g_last_grid = 0, g_last_tile = 0;
+thread_local int32_t g_last_grid = 0, g_last_tile = 0, g_last_margin = 0, g_last_unroll = 0;
 
 m3s_status fail(m3s_status s, const char* fmt, ...) {
     char buf[512];
@@ -162,7 +162,7 @@ EdgeArgs make_edge(const m3s_pair* A, const m3s_outputs* O, const m3s_params* P,
 
 // Launch override of the calling thread (m3s_debug_set_launch); every field
 // -1 means the library's own choice.
-thread_local m3s_launch_config g_override = {-1, -1, -1};
+thread_local m3s_launch_config g_override = {-1, -1, -1, -1, -1};
 
 // Tile configuration of the single-pair launch and of an untuned batched launch.
 int chosen_tile_config() {
@@ -183,10 +183,81 @@ struct Plan {
     std::string signature;
 };
 
-struct TuneResult { int tile = 0; int grid = 0; };
+// Launch shape of the persistent forward: tile configuration, workgroups,
+// and (tile configuration 5) ray-window margin and LM unroll.
+struct Launch {
+    int tile = m3s::kDefaultTileConfig;
+    int grid = 0;
+    int margin = m3s::kDefaultMargin;
+    int unroll = 1;
+};
 std::mutex g_cache_mu;
-std::map<std::string, TuneResult> g_tune;           // signature -> best launch shape
+std::map<std::string, Launch> g_tune;               // arch + CU count + shape signature -> best launch
 std::map<std::string, hipGraphExec_t> g_graphs;     // signature + ws + launch shape -> graph
+std::string g_tune_path;                            // on-disk autotuning cache ("" = none)
+
+// On-disk autotuning cache: one JSON object written by this library,
+//   {"format": "m3s-autotune", "version": 1,
+//    "entries": {"<key>": [tile, grid, margin, unroll], ...}}
+// with keys "<arch>|<CUs>cu|<shape signature>".  Keys hold no quote or
+// backslash, so the reader below only has to find strings and integers.
+constexpr int kTuneFileVersion = 1;
+
+bool parse_tune_file(const std::string& text, std::map<std::string, Launch>* out) {
+    if (text.find("\"format\": \"m3s-autotune\"") == std::string::npos) return false;
+    const size_t v = text.find("\"version\":");
+    if (v == std::string::npos || std::atoi(text.c_str() + v + 10) != kTuneFileVersion) return false;
+    size_t pos = text.find("\"entries\"");
+    if (pos == std::string::npos) return false;
+    pos = text.find('{', pos);
+    if (pos == std::string::npos) return false;
+    ++pos;
+    for (;;) {
+        const size_t q0 = text.find_first_of("\"}", pos);
+        if (q0 == std::string::npos) return false;
+        if (text[q0] == '}') return true;
+        const size_t q1 = text.find('"', q0 + 1);
+        const size_t lb = q1 == std::string::npos ? q1 : text.find('[', q1);
+        const size_t rb = lb == std::string::npos ? lb : text.find(']', lb);
+        if (rb == std::string::npos) return false;
+        Launch L;
+        int vals[4];
+        const char* c = text.c_str() + lb + 1;
+        for (int k = 0; k < 4; ++k) {
+            char* end = nullptr;
+            long x = std::strtol(c, &end, 10);
+            if (end == c || x < 0 || x > (1 << 20)) return false;
+            vals[k] = (int)x;
+            c = end;
+            while (*c == ' ' || *c == ',') ++c;
+        }
+        L.tile = vals[0]; L.grid = vals[1]; L.margin = vals[2]; L.unroll = vals[3];
+        if (L.tile >= m3s::kNumTileConfigs || L.grid < 1 || L.margin < m3s::kMarginMin || L.margin > m3s::kMarginMax ||
+            L.unroll < 1 || L.unroll > m3s::kUnrollMax)
+            return false;
+        (*out)[text.substr(q0 + 1, q1 - q0 - 1)] = L;
+        pos = rb + 1;
+    }
+}
+
+// Writes g_tune to g_tune_path (caller holds g_cache_mu): a temporary file
+// renamed over the old one, so a reader never sees half a file.
+bool save_tune_file() {
+    if (g_tune_path.empty()) return true;
+    const std::string tmp = g_tune_path + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return false;
+    std::fprintf(f, "{\"format\": \"m3s-autotune\", \"version\": %d,\n \"entries\": {", kTuneFileVersion);
+    bool first = true;
+    for (const auto& kv : g_tune) {
+        std::fprintf(f, "%s\n  \"%s\": [%d, %d, %d, %d]", first ? "" : ",", kv.first.c_str(), kv.second.tile,
+                     kv.second.grid, kv.second.margin, kv.second.unroll);
+        first = false;
+    }
+    std::fprintf(f, "\n }}\n");
+    const bool ok = std::fclose(f) == 0;
+    return ok && std::rename(tmp.c_str(), g_tune_path.c_str()) == 0;
+}
 
 m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, int tile_config, Plan* plan) {
     if (!edges) return fail(M3S_ERR_NULL, "edges is NULL");
@@ -264,11 +335,73 @@ m3s_status upload_plan(Plan& plan, char* ws, hipStream_t s) {
     return M3S_OK;
 }
 
-hipError_t run_batched(const Plan& plan, char* ws, int tile, int grid, hipStream_t s) {
+hipError_t run_batched(const Plan& plan, char* ws, const Launch& L, hipStream_t s) {
     return m3s::launch_batched(reinterpret_cast<const EdgeArgs*>(ws + plan.off_table),
                                reinterpret_cast<const int32_t*>(ws + plan.off_prep), (int)plan.table.size(),
-                               plan.total_prep, plan.total_tiles, reinterpret_cast<int32_t*>(ws), tile, grid,
-                               plan.desc_regs, s);
+                               plan.total_prep, plan.total_tiles, reinterpret_cast<int32_t*>(ws), L.tile,
+                               std::max(1, std::min(L.grid, plan.total_tiles)), L.margin, L.unroll, plan.desc_regs,
+                               s);
+}
+
+// Times every candidate launch of one batch (warm-up plus three timed
+// launches each) and returns the fastest: first the tile configuration x
+// grid (1, 2, 4 or 8 workgroups per CU) with the default margin and unroll,
+// then, for the fp16 configuration, ray-window margin x LM unroll at its best
+// grid.  Synchronises the stream; every candidate writes the same outputs.
+m3s_status autotune(const m3s_edge* edges, int32_t n, const m3s_params* P, char* W, int cus, hipStream_t st,
+                    Launch* best_out) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) hipEventDestroy(e0);
+        return fail(M3S_ERR_HIP, "hipEventCreate failed");
+    }
+    float best_ms = INFINITY;
+    Launch best;
+    m3s_status s = M3S_OK;
+    auto time_it = [&](const Plan& plan, const Launch& L) -> bool {
+        hipError_t e = run_batched(plan, W, L, st);  // warm-up
+        float sum = 0.f;
+        for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+            hipEventRecord(e0, st);
+            e = run_batched(plan, W, L, st);
+            hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            sum += ms;
+        }
+        if (e != hipSuccess) { s = hip_fail(e, "autotune launch"); return false; }
+        if (sum < best_ms) { best_ms = sum; best = L; }
+        return true;
+    };
+    const int mults[] = {1, 2, 4, 8};
+    for (int tc = 0; tc < m3s::kNumTileConfigs && s == M3S_OK; ++tc) {
+        Plan plan;
+        if ((s = plan_batched(edges, n, P, tc, &plan)) != M3S_OK) break;
+        if ((s = upload_plan(plan, W, st)) != M3S_OK) break;
+        for (int mult : mults) {
+            Launch L;
+            L.tile = tc; L.grid = cus * mult;
+            if (!time_it(plan, L)) break;
+        }
+    }
+    if (s == M3S_OK && best.tile == 5) {
+        Plan plan;
+        if ((s = plan_batched(edges, n, P, best.tile, &plan)) == M3S_OK && (s = upload_plan(plan, W, st)) == M3S_OK) {
+            const Launch base = best;
+            for (int m = m3s::kMarginMin; m <= m3s::kMarginMax && s == M3S_OK; ++m)
+                for (int u = 1; u <= m3s::kUnrollMax; ++u) {
+                    if (m == base.margin && u == base.unroll) continue;
+                    Launch L = base;
+                    L.margin = m; L.unroll = u;
+                    if (!time_it(plan, L)) break;
+                }
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s == M3S_OK) *best_out = best;
+    return s;
 }
 
 // ---------------------------------------------------------------- kernel timing
@@ -738,10 +871,14 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
     const m3s_params* P = common ? common : &defaults;
     if (flags & ~(uint32_t)(M3S_BATCH_GRAPH | M3S_BATCH_AUTOTUNE))
         return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
-    int tile = chosen_tile_config();
-    const bool overridden = g_override.tile_config >= 0 || g_override.grid > 0;
+    Launch L;
+    L.tile = chosen_tile_config();
+    if (g_override.ray_margin > 0) L.margin = std::min(std::max(g_override.ray_margin, m3s::kMarginMin), m3s::kMarginMax);
+    if (g_override.lm_unroll > 0) L.unroll = std::min(g_override.lm_unroll, m3s::kUnrollMax);
+    const bool overridden = g_override.tile_config >= 0 || g_override.grid > 0 || g_override.ray_margin > 0 ||
+                            g_override.lm_unroll > 0;
     Plan plan;
-    m3s_status s = plan_batched(edges, n_edges, P, tile, &plan);
+    m3s_status s = plan_batched(edges, n_edges, P, L.tile, &plan);
     if (s != M3S_OK) return s;
     if (!ws || !aligned(ws, kAlign) || ws_bytes < plan.total_bytes)
         return fail(M3S_ERR_WORKSPACE, "workspace must be 256-byte aligned and >= %zu bytes (got %zu)", plan.total_bytes,
@@ -755,11 +892,11 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
                     "m3s_match_batched cannot be captured: it copies its edge table from host memory before every "
                     "launch; M3S_BATCH_GRAPH gives a library-managed graph instead");
     char* W = reinterpret_cast<char*>(ws);
-    std::string tune_key = std::to_string(dev) + "|" + plan.signature;
+    const std::string tune_key = info.arch + "|" + std::to_string(info.cus) + "cu|" + plan.signature;
 
-    int grid = g_override.grid > 0 ? g_override.grid : info.cus * 4;
+    L.grid = g_override.grid > 0 ? g_override.grid : info.cus * 4;
     if ((flags & M3S_BATCH_AUTOTUNE) && !overridden) {
-        TuneResult tr;
+        Launch tr;
         bool have = false;
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -767,51 +904,25 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
             if (it != g_tune.end()) { tr = it->second; have = true; }
         }
         if (!have) {
-            hipEvent_t e0, e1;
-            if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
-                return fail(M3S_ERR_HIP, "hipEventCreate failed");
-            float best = INFINITY;
-            const int mults[] = {1, 2, 4, 8};
-            for (int tc = 0; tc < m3s::kNumTileConfigs; ++tc) {
-                Plan p2;
-                if ((s = plan_batched(edges, n_edges, P, tc, &p2)) != M3S_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
-                if ((s = upload_plan(p2, W, st)) != M3S_OK) { hipEventDestroy(e0); hipEventDestroy(e1); return s; }
-                for (int mult : mults) {
-                    int g = info.cus * mult;
-                    hipError_t e = run_batched(p2, W, tc, g, st);  // warm-up
-                    float ms_sum = 0.f;
-                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
-                        hipEventRecord(e0, st);
-                        e = run_batched(p2, W, tc, g, st);
-                        hipEventRecord(e1, st);
-                        hipEventSynchronize(e1);
-                        float ms = 0.f;
-                        hipEventElapsedTime(&ms, e0, e1);
-                        ms_sum += ms;
-                    }
-                    if (e != hipSuccess) { hipEventDestroy(e0); hipEventDestroy(e1); return hip_fail(e, "autotune launch"); }
-                    if (ms_sum < best) { best = ms_sum; tr.tile = tc; tr.grid = g; }
-                }
-            }
-            hipEventDestroy(e0);
-            hipEventDestroy(e1);
+            if ((s = autotune(edges, n_edges, P, W, info.cus, st, &tr)) != M3S_OK) return s;
             std::lock_guard<std::mutex> lk(g_cache_mu);
             g_tune[tune_key] = tr;
+            if (!save_tune_file()) return fail(M3S_ERR_PARAM, "cannot write the autotuning cache %s", g_tune_path.c_str());
         }
-        if (tr.tile != tile) {
-            tile = tr.tile;
-            if ((s = plan_batched(edges, n_edges, P, tile, &plan)) != M3S_OK) return s;
-        }
-        grid = tr.grid;
+        if (tr.tile != L.tile && (s = plan_batched(edges, n_edges, P, tr.tile, &plan)) != M3S_OK) return s;
+        L = tr;
     }
-    grid = std::max(1, std::min(grid, plan.total_tiles));
+    L.grid = std::max(1, std::min(L.grid, plan.total_tiles));
     if ((s = upload_plan(plan, W, st)) != M3S_OK) return s;
-    g_last_grid = grid;
-    g_last_tile = tile;
+    g_last_grid = L.grid;
+    g_last_tile = L.tile;
+    g_last_margin = L.margin;
+    g_last_unroll = L.unroll;
 
     if ((flags & M3S_BATCH_GRAPH) && st != nullptr) {
-        std::string gkey = tune_key + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) + "|" +
-                           std::to_string(tile) + "|" + std::to_string(grid);
+        char lb[64];
+        snprintf(lb, sizeof lb, "|%d,%d,%d,%d", L.tile, L.grid, L.margin, L.unroll);
+        std::string gkey = std::to_string(dev) + "|" + tune_key + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) + lb;
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -821,7 +932,7 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
         if (!exec) {
             hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = run_batched(plan, W, tile, grid, st);
+            hipError_t le = run_batched(plan, W, L, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
             if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "captured launch"); }
@@ -837,7 +948,7 @@ m3s_status m3s_match_batched(const m3s_edge* edges, int32_t n_edges, const m3s_p
         m3s::timer_end(st);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        hipError_t e = run_batched(plan, W, tile, grid, st);
+        hipError_t e = run_batched(plan, W, L, st);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
     }
     g_last_error.clear();
@@ -849,8 +960,39 @@ void m3s_debug_set_launch(const m3s_launch_config* cfg) {
         g_override = *cfg;
         if (g_override.tile_config >= m3s::kNumTileConfigs) g_override.tile_config = -1;
     } else {
-        g_override = m3s_launch_config{-1, -1, -1};
+        g_override = m3s_launch_config{-1, -1, -1, -1, -1};
     }
+}
+
+m3s_status m3s_set_tune_cache(const char* path) {
+    std::lock_guard<std::mutex> lk(g_cache_mu);
+    if (!path || !path[0]) {
+        g_tune_path.clear();
+        return M3S_OK;
+    }
+    std::map<std::string, Launch> loaded;
+    if (FILE* f = std::fopen(path, "r")) {
+        std::string text;
+        char buf[4096];
+        size_t got;
+        while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+        std::fclose(f);
+        if (!parse_tune_file(text, &loaded))
+            return fail(M3S_ERR_PARAM, "%s is not an m3s autotuning cache of version %d", path, kTuneFileVersion);
+    }
+    for (const auto& kv : loaded) g_tune[kv.first] = kv.second;
+    g_tune_path = path;
+    g_last_error.clear();
+    return M3S_OK;
+}
+
+void m3s_batched_last_launch(m3s_launch_config* cfg) {
+    if (!cfg) return;
+    cfg->tile_config = g_last_tile;
+    cfg->grid = g_last_grid;
+    cfg->xcd_remap = -1;
+    cfg->ray_margin = g_last_margin;
+    cfg->lm_unroll = g_last_unroll;
 }
 
 m3s_status m3s_path_counters(int64_t* counts, int32_t reset) {

@@ -218,7 +218,9 @@ __device__ __forceinline__ bool lm_step(const Sample& cur, float lambda, float p
 // `iters` LM iterations on Eq. 2: damped 2x2 step, bound hold, clamp,
 // acceptance on strictly lower cost.  With `final` set these are the last
 // iterations of the query, and the last trial evaluates its cost only.
-template <class Src>
+// UNROLL: unroll factor of the iteration loop (a launch-shape choice of the
+// autotuner; the arithmetic, and so every output bit, is the same).
+template <int UNROLL = 1, class Src>
 __device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 t, int iters, LMState& st,
                                            bool final = true) {
     const float xmax = (float)(W - 1), ymax = (float)(H - 1);
@@ -226,6 +228,7 @@ __device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 
     float px = st.px, py = st.py, lambda = st.lambda;
     Sample cur = st.cur, nxt;
     const int full = final ? iters - 1 : iters;
+#pragma unroll UNROLL
     for (int it = 0; it < full; ++it) {
         float qx, qy;
         if (!lm_step(cur, lambda, px, py, xmax, ymax, qx, qy)) { lambda *= 10.f; continue; }

@@ -35,9 +35,12 @@ inline int64_t prep_tiles(int H, int W) {
 }
 hipError_t launch_prep(const float* Xii, float4* rays, int H, int W, hipStream_t s);
 hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool xcd_remap, hipStream_t s);
+// Ray-window margins and LM unroll factors of the persistent fp16 kernel
+// (tile configuration 5); other configurations use the defaults.
+constexpr int kMarginMin = 1, kMarginMax = 3, kDefaultMargin = 2, kUnrollMax = 2;
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
-                          int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs,
-                          hipStream_t s);
+                          int total_tiles, int32_t* counter, int tile_config, int grid, int margin, int unroll,
+                          bool desc_regs, hipStream_t s);
 hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, uint32_t* bitmap, int32_t* counts,
                         hipStream_t s);
 // Backward of one edge: 16 x 16 query tiles (tiles_x x tiles_y), tile ids of

@@ -389,7 +389,9 @@ __device__ __forceinline__ void block_box(int& lx, int& hx, int& ly, int& hy, in
 }
 
 // Margin (pixels) of the staged ray window around the bilinear cells of the
-// tile's queries.
+// tile's queries: the default; the persistent kernel also comes with 1 and 3
+// for the autotuner (samples outside the window read global memory, so the
+// margin changes where values come from, never the values).
 constexpr int kRayMargin = 2;
 
 // Copies the ray records of window [lx, lx + rw) x [ly, ly + rh) into `lds`
@@ -413,16 +415,16 @@ __device__ __forceinline__ void stage_rays(const EdgeArgs& A, float4* lds, int l
 
 // Phase 1 of a tile with the ray records staged in LDS.  Queries that start on
 // their own pixel (no p_init) sample the cells of the tile's pixels first, so
-// the window of those cells (plus kRayMargin) is staged before the query
+// the window of those cells (plus MARGIN) is staged before the query
 // setup, with no dependence on it.  After the first LM iteration the window
-// around the cells every query has reached (plus kRayMargin) is staged
+// around the cells every query has reached (plus MARGIN) is staged
 // unless the first window already holds it (at most cap_px pixels).  Samples
 // outside the staged window read global memory.  All lanes of the block call
 // this; [tx_lo, tx_hi] x [ty_lo, ty_hi] are the tile's pixels in the image.
 // EARLY enables the first window: it shortens the latency of a launch with
 // one wave of tiles and costs bandwidth in a persistent launch, whose other
 // workgroups hide that latency anyway.
-template <int NT, bool EARLY>
+template <int NT, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1>
 __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool inside, QState& q,
                                         float4* lds, int cap_px, int* box, int tx_lo, int tx_hi, int ty_lo,
                                         int ty_hi) {
@@ -434,8 +436,8 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
     const int first = min(A.K, 1);
     int wx = 0, wy = 0, ww = 0, wh = 0;  // staged window (ww == 0: none)
     if (EARLY && !A.p_init) {
-        const int lx = max(min(tx_lo, W - 2) - kRayMargin, 0), hx = min(min(tx_hi, W - 2) + 1 + kRayMargin, W - 1);
-        const int ly = max(min(ty_lo, H - 2) - kRayMargin, 0), hy = min(min(ty_hi, H - 2) + 1 + kRayMargin, H - 1);
+        const int lx = max(min(tx_lo, W - 2) - MARGIN, 0), hx = min(min(tx_hi, W - 2) + 1 + MARGIN, W - 1);
+        const int ly = max(min(ty_lo, H - 2) - MARGIN, 0), hy = min(min(ty_hi, H - 2) + 1 + MARGIN, H - 1);
         if ((hx - lx + 1) * (hy - ly + 1) <= cap_px) {
             wx = lx; wy = ly; ww = hx - lx + 1; wh = hy - ly + 1;
             stage_rays<NT>(A, lds, wx, wy, ww, wh);
@@ -450,17 +452,17 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
         if (ww) {
             const WindowRays wr{lds, wx, wy, ww, wh, g};
             lm_start(wr, H, W, A.lambda0, t, st);
-            lm_iterate(wr, H, W, t, first, st, A.K == first);
+            lm_iterate<UNROLL>(wr, H, W, t, first, st, A.K == first);
         } else {
             lm_start(g, H, W, A.lambda0, t, st);
-            lm_iterate(g, H, W, t, first, st, A.K == first);
+            lm_iterate<UNROLL>(g, H, W, t, first, st, A.K == first);
         }
     }
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
     if (act) {
         const int cx = min((int)floorf(st.px), W - 2), cy = min((int)floorf(st.py), H - 2);
-        lx = max(cx - kRayMargin, 0); hx = min(cx + 1 + kRayMargin, W - 1);
-        ly = max(cy - kRayMargin, 0); hy = min(cy + 1 + kRayMargin, H - 1);
+        lx = max(cx - MARGIN, 0); hx = min(cx + 1 + MARGIN, W - 1);
+        ly = max(cy - MARGIN, 0); hy = min(cy + 1 + MARGIN, H - 1);
     }
     block_box<NT>(lx, hx, ly, hy, box);  // ends with a barrier: no lane reads the window any more
     const int rw = hx - lx + 1, rh = hy - ly + 1;
@@ -480,9 +482,9 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
     if (act) {
         if (more && ww) {
             const WindowRays wr{lds, wx, wy, ww, wh, g};
-            lm_iterate(wr, H, W, t, A.K - first, st);
+            lm_iterate<UNROLL>(wr, H, W, t, A.K - first, st);
         } else {
-            lm_iterate(g, H, W, t, A.K - first, st);
+            lm_iterate<UNROLL>(g, H, W, t, A.K - first, st);
         }
         lm_finish(A, x, y, st, q);
     }
@@ -756,14 +758,14 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
 // One TX x TY tile with the fp16 pre-filtered refine.  Falls back to the exact
 // global scan for the whole tile when the region does not fit, r > 5, or a
 // region value is non-finite or too large for fp16.
-template <int TX, int TY, bool EARLY>
+template <int TX, int TY, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1>
 __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16& S) {
     constexpr int NT = TX * TY;
     const int tid = threadIdx.x;
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT, EARLY>(A, x, y, inside, q, S.rays, kRegionPx16, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+    tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, kRegionPx16, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
                 min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
@@ -890,8 +892,9 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
 // Persistent forward over all edges: workgroups pop tile ids from a counter
 // until none is left (every workgroup exits once the counter passes the last
 // tile).  LDS tiles need D = 24 and 16-byte aligned descriptors on every edge.
-// MODE 0: refine from global memory; 1: fp32 region in LDS; 2: fp16 pre-filter.
-template <int TX, int TY, int DT, int MODE>
+// MODE 0: refine from global memory; 1: fp32 region in LDS; 2: fp16 pre-filter
+// with ray-window margin MARGIN and LM unroll UNROLL.
+template <int TX, int TY, int DT, int MODE, int MARGIN = kRayMargin, int UNROLL = 1>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? 4 : 1)))
 batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
                                                                int32_t* __restrict__ counter) {
@@ -910,7 +913,7 @@ batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
         if constexpr (MODE == 1) {
             tile_lds<TX, TY>(A, tx, ty, S);
         } else if constexpr (MODE == 2) {
-            tile_f16<TX, TY, false>(A, tx, ty, S);
+            tile_f16<TX, TY, false, MARGIN, UNROLL>(A, tx, ty, S);
         } else {
             int x = tx * TX + (int)(threadIdx.x % TX);
             int y = ty * TY + (int)(threadIdx.x / TX);
@@ -1237,12 +1240,30 @@ hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool x
     return hipGetLastError();
 }
 
+template <int TX, int TY, int MARGIN, int UNROLL>
+static void launch_batched_f16(const EdgeArgs* table, int n_edges, int total_tiles, int32_t* counter, int grid,
+                               hipStream_t s) {
+    batched_fwd_kernel<TX, TY, 24, 2, MARGIN, UNROLL><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+}
+
 template <int TX, int TY>
 static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_tiles, int32_t* counter, int grid,
-                                bool desc_regs, int mode, hipStream_t s) {
-    if (mode == 2 && desc_regs)
-        batched_fwd_kernel<TX, TY, 24, 2><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
-    else if (mode == 1 && desc_regs)
+                                bool desc_regs, int mode, int margin, int unroll, hipStream_t s) {
+    if constexpr (TX == 16 && TY == 16) {
+        if (mode == 2 && desc_regs) {
+            const int v = 2 * (margin - 1) + (unroll - 1);
+            switch (v) {
+                case 0: launch_batched_f16<TX, TY, 1, 1>(table, n_edges, total_tiles, counter, grid, s); break;
+                case 1: launch_batched_f16<TX, TY, 1, 2>(table, n_edges, total_tiles, counter, grid, s); break;
+                case 3: launch_batched_f16<TX, TY, 2, 2>(table, n_edges, total_tiles, counter, grid, s); break;
+                case 4: launch_batched_f16<TX, TY, 3, 1>(table, n_edges, total_tiles, counter, grid, s); break;
+                case 5: launch_batched_f16<TX, TY, 3, 2>(table, n_edges, total_tiles, counter, grid, s); break;
+                default: launch_batched_f16<TX, TY, 2, 1>(table, n_edges, total_tiles, counter, grid, s); break;
+            }
+            return;
+        }
+    }
+    if (mode == 1 && desc_regs)
         batched_fwd_kernel<TX, TY, 24, 1><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
     else if (desc_regs)
         batched_fwd_kernel<TX, TY, 24, 0><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
@@ -1251,7 +1272,8 @@ static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_ti
 }
 
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
-                          int total_tiles, int32_t* counter, int tile_config, int grid, bool desc_regs, hipStream_t s) {
+                          int total_tiles, int32_t* counter, int tile_config, int grid, int margin, int unroll,
+                          bool desc_regs, hipStream_t s) {
     timer_begin("batched_counter", s);
     set_counter_kernel<<<1, 64, 0, s>>>(counter);
     timer_end(s);
@@ -1260,12 +1282,12 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
     timer_end(s);
     timer_begin("batched_fwd", s);
     switch (tile_config) {
-        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
-        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
-        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, s); break;
-        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, s); break;
-        case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, s); break;
-        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, s); break;
+        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
+        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
+        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, s); break;
+        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, s); break;
+        case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, margin, unroll, s); break;
+        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
     }
     timer_end(s);
     return hipGetLastError();

@@ -1,8 +1,8 @@
 // gfx950 kernels of the tracking pose solve and of the canonical pointmap
 // fusion that follows it (MASt3R-SLAM, Sec. 3.3).
 //
-// Gauss-Newton in an iteratively reweighted least-squares loop (Eq.
-// gauss_newton) for the Sim(3) pose T_kf that maps frame points X^f_f into the
+// Robustly weighted Gauss-Newton, the weights recomputed every iteration
+// (Eq. gauss_newton), for the Sim(3) pose T_kf that maps frame points X^f_f into the
 // keyframe, over the matches of the keyframe's pixels found by the matcher.
 // One launch per iteration:
 //

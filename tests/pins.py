@@ -10,8 +10,8 @@ and raises AssertionError when the oracle disagrees with:
 * invariants: depth independence of rays for a central camera (Sec. 3.1),
   orthogonality of the backward to the radial direction (Supp. A, Eq. norm_jac);
 * brute force: exhaustive scans of the ray error on tiny generic cameras;
-* the paper's convergence statement (Sec. 3.2: almost all valid pixels within
-  10 iterations);
+* the paper's convergence statement (Sec. 3.2: ten LM iterations suffice for
+  nearly every valid pixel);
 * finite differences of the loss through the forward, and autograd through an
   independent unrolled statement of the solver.
 
@@ -207,8 +207,9 @@ def pin_gradient_images(lib):
 
 
 def pin_convergence(lib):
-    """Sec. 3.2: LM converges for almost all valid pixels within 10 iterations.
-    The 10th step moves at most 1e-6 px for >= 99.9 % of valid pixels at 512x384."""
+    """Sec. 3.2 (LM convergence): by the tenth iteration nearly every valid pixel
+    has converged.  The 10th step moves at most 1e-6 px for >= 99.9 % of valid
+    pixels at 512x384."""
     pair = _pair(384, 512, 2000)
     a = fwd(lib, pair.Xii, pair.Xji, K=9, nthreads=0)
     b = fwd(lib, pair.Xii, pair.Xji, K=10, nthreads=0)
@@ -593,7 +594,12 @@ def pin_bwd_unrolled(lib):
     Xj = torch.tensor(pair.Xji, dtype=torch.float64, requires_grad=True)
     p, th, xh = unrolled.lm_project(Xi, Xj, K=20)
     dp = np.abs(p.detach().numpy().reshape(o["p"].shape) - o["p"]).max(-1)
+    # Converged (valid) queries agree to rounding.  Queries beyond the image
+    # border are held on it and still step along it after 20 iterations, so
+    # the two fp64 statements' different operation orders leave a few 1e-9 px
+    # there; every query is pinned, those at 1e-7 px.
     assert dp[o["valid"]].max() <= 1e-9, "unrolled p*"
+    assert dp.max() <= 1e-7, "unrolled p* (all queries)"
     m = torch.tensor(mask.reshape(-1))
     L = ((xh - Xj.reshape(-1, 3)) ** 2).sum(-1)[m].sum()
     L.backward()

@@ -65,7 +65,7 @@ def test_defaults_and_strings(lib):
     assert (p.max_iter, p.refine_radius, p.refine_levels) == (10, 3, 1)
     assert abs(p.lambda_init - 1e-8) < 1e-15 and abs(p.conf_min - 1.5) < 1e-7 and abs(p.max_theta - 1e-4) < 1e-10
     assert p.max_dist == float("inf")
-    assert lib.m3s_version() == 1
+    assert lib.m3s_version() == 2
     for s in range(7):
         assert lib.m3s_status_string(s)
     assert lib.m3s_status_string(99) == b"unknown status"
@@ -375,16 +375,16 @@ def test_launch_override_struct_and_counters_null(tmp_path, lib):
 #include <stddef.h>
 #include "m3s.h"
 int main(void) {
-  printf("%zu %zu %zu %d\n", sizeof(m3s_launch_config), offsetof(m3s_launch_config, grid),
-         offsetof(m3s_launch_config, xcd_remap), M3S_PATH_COUNTERS);
+  printf("%zu %zu %zu %zu %d\n", sizeof(m3s_launch_config), offsetof(m3s_launch_config, grid),
+         offsetof(m3s_launch_config, xcd_remap), offsetof(m3s_launch_config, lm_unroll), M3S_PATH_COUNTERS);
   return 0;
 }''')
     exe = tmp_path / "launch"
     subprocess.run(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
     vals = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert vals == [ctypes.sizeof(_lib.LaunchConfig), _lib.LaunchConfig.grid.offset,
-                    _lib.LaunchConfig.xcd_remap.offset, _lib.M3S_PATH_COUNTERS]
-    cfg = _lib.LaunchConfig(3, 64, 0)
+                    _lib.LaunchConfig.xcd_remap.offset, _lib.LaunchConfig.lm_unroll.offset, _lib.M3S_PATH_COUNTERS]
+    cfg = _lib.LaunchConfig(3, 64, 0, 1, 2)
     lib.m3s_debug_set_launch(ctypes.byref(cfg))
     lib.m3s_debug_set_launch(None)
     assert lib.m3s_path_counters(None, 0) == 1
@@ -425,3 +425,23 @@ int main(void) {
         arr = None if edges is None else (_lib.BwdEdge * len(edges))(*edges)
         st = lib.m3s_match_bwd_batched(arr, n, flags, ws, nb, None)
         assert st == expect, (edges, n, flags, st, lib.m3s_last_error())
+
+
+def test_tune_cache_file_validation(lib, tmp_path):
+    """m3s_set_tune_cache: a missing file is accepted (created on the first
+    tuning), a file of this format loads, anything else is refused."""
+    missing = tmp_path / "none.json"
+    assert lib.m3s_set_tune_cache(str(missing).encode()) == 0
+    good = tmp_path / "good.json"
+    good.write_text('{"format": "m3s-autotune", "version": 1, "entries": {"gfx950|256cu|0,384,512,24,10,3,5;RL1": '
+                    '[5, 1024, 2, 1]}}')
+    assert lib.m3s_set_tune_cache(str(good).encode()) == 0
+    for text in ['{}', '{"format": "m3s-autotune", "version": 2, "entries": {}}',
+                 '{"format": "m3s-autotune", "version": 1, "entries": {"k": [9, 1, 2, 1]}}',
+                 '{"format": "m3s-autotune", "version": 1, "entries": {"k": [5, 1, 4, 1]}}',
+                 '{"format": "m3s-autotune", "version": 1, "entries": {"k": [5, 1, 2]}}']:
+        bad = tmp_path / "bad.json"
+        bad.write_text(text)
+        assert lib.m3s_set_tune_cache(str(bad).encode()) == 3, text
+    assert lib.m3s_set_tune_cache(None) == 0
+    lib.m3s_clear_caches()

@@ -113,3 +113,66 @@ def test_batched_96_uneven_edges(m3s):
     """40 edges at 512x384, 32 at 384x512, 24 at 512x288, K in 5..15, r in 2..4."""
     pairs = synth.batched_uneven()
     _full_batch_check(m3s, pairs, [0, 17, 39, 40, 55, 71, 72, 88, 95], "uneven")
+
+
+def test_every_launch_candidate_gives_identical_bits(m3s):
+    """Every launch the autotuner can pick (tile configuration x grid, and for
+    the fp16 configuration ray-window margin x LM unroll) writes the same bits
+    as the per-pair launch."""
+    import torch
+    edges = edge_inputs(m3s, mixed_pairs())
+    ref = per_pair(m3s, edges)
+    cands = [(t, 64, -1, -1) for t in range(5)] + [(5, g, m, u) for g in (32, 1024) for m in (1, 2, 3) for u in (1, 2)]
+    s = torch.cuda.Stream()
+    for t, g, m, u in cands:
+        print("case launch tile %d grid %d margin %d unroll %d" % (t, g, m, u), flush=True)
+        m3s.set_launch(tile_config=t, grid=g, ray_margin=m, lm_unroll=u)
+        try:
+            with torch.cuda.stream(s):
+                outs = m3s.match_batched(edges, graph=False, want_xhat=True)
+            s.synchronize()
+            used = m3s.last_batched_launch()
+        finally:
+            m3s.set_launch()
+        assert used["tile_config"] == t
+        if t == 5:
+            assert (used["ray_margin"], used["lm_unroll"]) == (m, u)
+        for k, (a, b) in enumerate(zip(ref, outs)):
+            assert_same(a, parity.result_numpy(b), "tile %d margin %d unroll %d edge %d" % (t, m, u, k))
+
+
+def test_autotune_cache_file_round_trip(m3s, tmp_path):
+    """The tuner writes its result to the cache file; after the in-memory
+    caches are dropped, the file's entry (edited to a distinctive launch) is
+    used as is, with no new tuning, and the outputs keep their bits."""
+    import json
+    import torch
+    lib = m3s.load_library()
+    lib.m3s_clear_caches()          # earlier tests' results would be written to the file too
+    path = tmp_path / "tune.json"
+    m3s.set_tune_cache(str(path))
+    try:
+        edges = edge_inputs(m3s, mixed_pairs()[:3])
+        s = torch.cuda.Stream()
+        with torch.cuda.stream(s):
+            a = m3s.match_batched(edges, graph=False, autotune=True, want_xhat=True)
+        s.synchronize()
+        data = json.loads(path.read_text())
+        assert data["format"] == "m3s-autotune" and data["version"] == 1
+        keys = [k for k in data["entries"] if "cu|" in k]
+        assert len(keys) == 1
+        tuned = m3s.last_batched_launch()
+        assert data["entries"][keys[0]] == [tuned["tile_config"], tuned["grid"], tuned["ray_margin"], tuned["lm_unroll"]]
+        data["entries"][keys[0]] = [5, 7, 3, 2]
+        path.write_text(json.dumps(data))
+        lib.m3s_clear_caches()
+        m3s.set_tune_cache(str(path))
+        with torch.cuda.stream(s):
+            b = m3s.match_batched(edges, graph=True, autotune=True, want_xhat=True)
+        s.synchronize()
+        assert m3s.last_batched_launch() == dict(tile_config=5, grid=7, ray_margin=3, lm_unroll=2)
+        for k, (x, y) in enumerate(zip(a, b)):
+            assert_same(parity.result_numpy(x), parity.result_numpy(y), "reloaded edge %d" % k)
+    finally:
+        m3s.set_tune_cache(None)
+        lib.m3s_clear_caches()
