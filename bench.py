@@ -14,6 +14,8 @@ Further legs, reported in the same JSON line:
   fwd_bwd        forward (with xhat) then the implicit-adjoint backward per pair;
   fwd_bwd_batched the differentiation workload: 16 edges at 512x384, one batched
                  forward then one batched backward per step, against the per-pair loop;
+  tracking_c2f   tracking-mode matching: previous-frame initial pixels and the
+                 coarse-to-fine refine over 2 and 3 levels;
   batched        64 edges at 512x384 in one persistent hipGraph launch
                  (autotuned) vs a loop of per-pair launches on the same GPU;
   batched_uneven 96 edges of mixed resolution (512x384, 384x512, 512x288),
@@ -143,7 +145,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--pool", type=int, default=8, help="distinct 512x384 pairs cycled through")
     ap.add_argument("--only-main", action="store_true", help="time only the single-pair forward leg")
-    ap.add_argument("--legs", default="fwd_bwd,batched,track_fuse,backend",
+    ap.add_argument("--legs", default="fwd_bwd,tracking_c2f,batched,track_fuse,backend",
                     help="comma-separated further legs to run after the single-pair forward")
     ap.add_argument("--skip-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
@@ -273,6 +275,8 @@ def main():
         if "fwd_bwd" in legs:
             out["fwd_bwd"] = fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
             out["fwd_bwd_batched"] = fwd_bwd_batched_leg(m3s, lib, _lib, dev, args)
+        if "tracking_c2f" in legs:
+            out["tracking_c2f"] = tracking_c2f_leg(m3s, lib, _lib, pool_pairs, dev, sp, args)
         if "batched" in legs:
             out["batched"] = batched_leg(m3s, lib, _lib, synth.batched_uniform, dev, args,
                                          "64 edges 512x384, K=10, r=3")
@@ -351,6 +355,61 @@ def phases_leg(m3s, lib, _lib, dev, sp, pairs=None):
         del ws, pw
     return {"workload": "64 edges 512x384 (batched) and edge 0 alone (single pair); D=24, confidences",
             "queries_batched": queries, "variants": out}
+
+
+def tracking_c2f_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
+    """Tracking-mode matching (Sec. 3.2): each 512x384 pair of the pool starts
+    from the previous frame's matches, stood in for by the generator's true
+    projection plus N(0, 1.5^2) px noise, and refines coarse to fine over L = 2
+    and L = 3 levels (r = 3, K = 10).  Single-pair forward per step, kernel
+    time from hipEvents; algorithmic bytes per query 241 + 8 (p_init)."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(77))
+    pinit = [torch.from_numpy((p.proj + rng.normal(0, 1.5, size=p.proj.shape)).astype(np.float32)).to(dev)
+             for p in pool_pairs]
+    pool = [PreparedPair(m3s, lib, p, dev) for p in pool_pairs]
+    for P, pi in zip(pool, pinit):
+        P.pair_c.p_init = pi.data_ptr()
+    N = pool[0].H * pool[0].W
+    ws = torch.empty(lib.m3s_workspace_bytes(ctypes.byref(pool[0].pair_c), ctypes.byref(pool[0].prm)),
+                     dtype=torch.uint8, device=dev)
+    out = {"workload": "512x384 pairs, p_init = previous-frame matches (projection + N(0, 1.5^2) px), K=10, r=3, "
+                       "coarse-to-fine refine", "bytes_per_query": FWD_BYTES_PER_QUERY + 8}
+    for L in (2, 3):
+        prm = _lib.default_params(lib, refine_levels=L)
+
+        def step(k):
+            P = pool[k % len(pool)]
+            st = lib.m3s_match_fwd(ctypes.byref(P.pair_c), ctypes.byref(prm), ctypes.byref(P.out_c), ws.data_ptr(),
+                                   ws.numel(), sp)
+            _lib.check(lib, "m3s_match_fwd", st)
+
+        for k in range(5):
+            step(k)
+        torch.cuda.synchronize()
+        m3s.path_counters(reset=True)
+        steps = max(10, args.steps // 2)
+        t0 = time.perf_counter()
+        for k in range(steps):
+            step(k)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / steps
+        counts = m3s.path_counters(reset=True)
+        lib.m3s_timing_reset()
+        lib.m3s_timing_enable(1)
+        for k in range(steps):
+            step(k)
+        torch.cuda.synchronize()
+        lib.m3s_timing_enable(0)
+        fwd_ms, _ = _timer(lib, "fwd")
+        alg = (FWD_BYTES_PER_QUERY + 8) * N
+        out["L%d" % L] = {"matches_per_s": round(N / el, 1), "ms_per_step": round(el * 1e3, 5),
+                          "fwd_kernel_us": round(fwd_ms * 1e3, 2),
+                          "fwd_algorithmic_GBs": round(alg / (fwd_ms * 1e-3) / 1e9, 1),
+                          "fwd_frac_of_hbm_peak": round(alg / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                          "global_scan_tile_levels_per_step": round(counts["refine_global"] / steps, 1)}
+    log("tracking_c2f:", out)
+    return out
 
 
 def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):

@@ -180,6 +180,7 @@ struct Plan {
     int total_tiles = 0, total_prep = 0;
     size_t off_table = 0, off_prep = 0, off_rays = 0, total_bytes = 0;
     bool desc_regs = true;
+    int levels = 1;
     std::string signature;
 };
 
@@ -319,6 +320,7 @@ m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, i
     plan->total_tiles = (int)tiles;
     plan->total_prep = (int)prep;
     plan->total_bytes = off;
+    plan->levels = P->refine_levels;
     plan->signature = sig + (plan->desc_regs ? "R" : "G") + "L" + std::to_string(P->refine_levels);
     return M3S_OK;
 }
@@ -339,8 +341,8 @@ hipError_t run_batched(const Plan& plan, char* ws, const Launch& L, hipStream_t 
     return m3s::launch_batched(reinterpret_cast<const EdgeArgs*>(ws + plan.off_table),
                                reinterpret_cast<const int32_t*>(ws + plan.off_prep), (int)plan.table.size(),
                                plan.total_prep, plan.total_tiles, reinterpret_cast<int32_t*>(ws), L.tile,
-                               std::max(1, std::min(L.grid, plan.total_tiles)), L.margin, L.unroll, plan.desc_regs,
-                               s);
+                               std::max(1, std::min(L.grid, plan.total_tiles)), L.margin, L.unroll, plan.levels,
+                               plan.desc_regs, s);
 }
 
 // Times every candidate launch of one batch (warm-up plus three timed
@@ -381,7 +383,8 @@ m3s_status autotune(const m3s_edge* edges, int32_t n, const m3s_params* P, char*
         if ((s = upload_plan(plan, W, st)) != M3S_OK) break;
         for (int mult : mults) {
             Launch L;
-            L.tile = tc; L.grid = cus * mult;
+            L.tile = tc;
+            L.grid = std::max(1, std::min(cus * mult, plan.total_tiles));  // the grid the launch really has
             if (!time_it(plan, L)) break;
         }
     }

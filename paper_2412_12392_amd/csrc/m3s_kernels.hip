@@ -238,31 +238,42 @@ __device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState
 // Refine window centre: p* rounded half up.
 __device__ __forceinline__ int round_half_up(float v) { return (int)floorf(v + 0.5f); }
 
+// One level of the window refine through global memory: the first maximum
+// of the raw dot product over the (2r+1)^2 grid of spacing sp around
+// (mx0, my0), in row-major order, skipping candidates outside the image; -1
+// when none is inside.
+template <int DT>
+__device__ __forceinline__ long refine_global_level(const EdgeArgs& A, const QueryDesc<DT>& qd, int mx0, int my0,
+                                                    int sp) {
+    const int H = A.H, W = A.W, r = A.r;
+    float best = -INFINITY;
+    long lb = -1;
+    for (int dy = -r; dy <= r; ++dy) {
+        int my = my0 + sp * dy;
+        if (my < 0 || my >= H) continue;
+        for (int dx = -r; dx <= r; ++dx) {
+            int mx = mx0 + sp * dx;
+            if (mx < 0 || mx >= W) continue;
+            long m = (long)my * W + mx;
+            float s = qd.dot(A.Dii, m, A.D);
+            if (s > best) { best = s; lb = m; }
+        }
+    }
+    return lb;
+}
+
 // Phase 2 (global memory): first maximum of the raw dot product over the
-// window, row-major; with L > 1 levels, coarse to fine: level l scans the
-// grid of spacing 2^l around the previous level's best.
+// window; with L > 1 levels, coarse to fine: level l scans the grid of
+// spacing 2^l around the previous level's best.
 template <int DT>
 __device__ __forceinline__ long refine_global(const EdgeArgs& A, long n, const QState& q) {
-    const int H = A.H, W = A.W, r = A.r;
+    const int W = A.W;
     int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
     QueryDesc<DT> qd;
     qd.load(A.Dji, n, A.D);
     long bi = -1;
     for (int lev = A.levels - 1; lev >= 0; --lev) {
-        const int sp = 1 << lev;
-        float best = -INFINITY;
-        long lb = -1;
-        for (int dy = -r; dy <= r; ++dy) {
-            int my = my0 + sp * dy;
-            if (my < 0 || my >= H) continue;
-            for (int dx = -r; dx <= r; ++dx) {
-                int mx = mx0 + sp * dx;
-                if (mx < 0 || mx >= W) continue;
-                long m = (long)my * W + mx;
-                float s = qd.dot(A.Dii, m, A.D);
-                if (s > best) { best = s; lb = m; }
-            }
-        }
+        const long lb = refine_global_level<DT>(A, qd, mx0, my0, 1 << lev);
         if (lb < 0) break;
         bi = lb;
         mx0 = (int)(lb % W);
@@ -575,6 +586,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
 typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kRegionPx16 = 832;          // 832 px x 48 B = 39 KiB: four workgroups per CU
+constexpr int kRegionPx16Multi = 1088;    // the multi-level kernel: 51 KiB, three workgroups per CU
 constexpr float kF16Max = 60000.f;        // larger scaled magnitudes fall back to the exact scan
 constexpr float kScale16 = 256.f;         // 2^8, applied to both operands before the conversion
 constexpr float kU16 = 4.8828125e-4f;     // 2^-11
@@ -582,10 +594,11 @@ constexpr float kU32x24 = 1.4305115e-6f;  // 24 * 2^-24
 constexpr float kFlush16 = 6.1035156e-5f; // 2^-14
 constexpr float kSqrt24Up = 4.8989797f;   // sqrt(24) rounded up
 
+template <int CAP>
 struct TileLds16 {
     union {
-        uint4 desc[3 * kRegionPx16];       // refine region (three fp16 planes)
-        float4 rays[3 * kRegionPx16];      // LM ray window (records of up to kRegionPx16 pixels)
+        uint4 desc[3 * CAP];               // refine region (three fp16 planes of CAP pixels)
+        float4 rays[3 * CAP];              // LM ray window (records of up to CAP pixels)
     };
     int box[4 * 16];
     float stat[16];                       // per wave: largest |d|^2 of a region pixel
@@ -628,8 +641,8 @@ __device__ __forceinline__ float exact24(const float* __restrict__ q, const floa
     return acc;
 }
 
-// Pass 1 over a window that lies inside the image, for a radius R fixed at
-// compile time: the candidates of a row are unrolled (LDS addresses are the
+// Pass 1 over a window that lies inside the image, for a radius R and a
+// candidate spacing SP fixed at compile time: the candidates of a row are unrolled (LDS addresses are the
 // row base plus immediate offsets), the row's scores are kept in registers,
 // the running maximum takes the row's maximum, and each candidate of the row
 // survives if its score is within tau of that running maximum.  A candidate
@@ -639,17 +652,18 @@ __device__ __forceinline__ float exact24(const float* __restrict__ q, const floa
 // window on bit N - 1 - j; a bit reversal then gives the row-major masks of
 // the generic pass (candidate j on bit j).  w: LDS record of the window's
 // top-left candidate.
-template <int R>
+template <int R, int SP, int CAP>
 __device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* __restrict__ w, int rw, float tau,
                                               float& run, uint64_t& mask0, uint64_t& mask1) {
     constexpr int S = 2 * R + 1, N = S * S;
     static_assert(N <= 128 && S < 32, "mask width");
     uint64_t lo = 0, hi = 0;
 #pragma unroll 1
-    for (int dy = 0; dy < S; ++dy, w += rw) {
+    for (int dy = 0; dy < S; ++dy, w += SP * rw) {
         float sc[S];
 #pragma unroll
-        for (int dx = 0; dx < S; ++dx) sc[dx] = dot16(q16, w[dx], w[dx + kRegionPx16], w[dx + 2 * kRegionPx16]);
+        for (int dx = 0; dx < S; ++dx)
+            sc[dx] = dot16(q16, w[SP * dx], w[SP * dx + CAP], w[SP * dx + 2 * CAP]);
         float rm = sc[0];
 #pragma unroll
         for (int dx = 1; dx < S; ++dx) rm = fmaxf(rm, sc[dx]);
@@ -672,59 +686,76 @@ __device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* 
     }
 }
 
-// dnorm: bound on |d| over the region, dl1: bound on |d|_1.
-__device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QState& q, const uint4* __restrict__ sd,
-                                           int rx0, int ry0, int rw, float dnorm, float dl1) {
-    const int H = A.H, W = A.W, r = A.r, side = 2 * r + 1;
-    int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
+// A query descriptor for the fp16 pre-filter: fp32 elements (exact rescoring),
+// the scaled fp16 copy, and the bounds of the error budget (scaled units).
+struct Query16 {
     QueryDesc<24> qd;
-    qd.load(A.Dji, n, 24);
+    uint32_t q16[12];
+    float qn, ql1;   // bounds on |q| and |q|_1 (times kScale16)
+    bool ok;         // |q| within the fp16 range
+};
+
+__device__ __forceinline__ void load_query16(const EdgeArgs& A, long n, Query16& Q) {
+    Q.qd.load(A.Dji, n, 24);
     // |q_k| <= |q| bounds every element (fp16 range) and |q|_1 <= sqrt(24) |q|;
     // the 1.0001 margin covers the rounding of the fp32 norm.
     float qn2 = 0.f;
-    uint32_t q16[12];
 #pragma unroll
-    for (int k = 0; k < 24; ++k) qn2 = fmaf(qd.q[k], qd.q[k], qn2);
+    for (int k = 0; k < 24; ++k) qn2 = fmaf(Q.qd.q[k], Q.qd.q[k], qn2);
+    Q.qn = sqrtf(qn2) * 1.0001f * kScale16;
+    Q.ok = Q.qn <= kF16Max;
+    Q.ql1 = kSqrt24Up * Q.qn;
+#pragma unroll
+    for (int k = 0; k < 12; ++k) Q.q16[k] = pack_h2(Q.qd.q[2 * k] * kScale16, Q.qd.q[2 * k + 1] * kScale16);
+}
+
+// One level of the exact first-maximum refine with the fp16 pre-filter: the
+// (2r+1)^2 grid of spacing sp around (mx0, my0), over a staged region that
+// holds every candidate inside the image.  dnorm: bound on |d| over the
+// region, dl1: bound on |d|_1.
+template <int CAP>
+__device__ __forceinline__ long refine_f16_level(const EdgeArgs& A, const Query16& Q, int mx0, int my0, int sp,
+                                                 const uint4* __restrict__ sd, int rx0, int ry0, int rw, float dnorm,
+                                                 float dl1) {
+    const int H = A.H, W = A.W, r = A.r, side = 2 * r + 1;
     // Bounds and tau in scaled units (both operands times kScale16).
-    const float qn = sqrtf(qn2) * 1.0001f * kScale16;
-    if (!(qn <= kF16Max)) {
-        count_path(kPathRefineQuery);
-        return refine_global<24>(A, n, q);
-    }
-#pragma unroll
-    for (int k = 0; k < 12; ++k) q16[k] = pack_h2(qd.q[2 * k] * kScale16, qd.q[2 * k + 1] * kScale16);
-    const float ql1 = kSqrt24Up * qn;
+    const float qn = Q.qn;
     dnorm *= kScale16;
     dl1 *= kScale16;
-    const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (ql1 + dl1);
+    const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (Q.ql1 + dl1);
     const float eps32 = kU32x24 * qn * dnorm;
     const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
 
-    // Pass 1: fp16 scores in row-major window order over the part of the
-    // window inside the image; the running maximum is seeded with the window
-    // centre (v_med3 against +inf is the maximum of two non-NaN scores).
+    // Pass 1: fp16 scores in row-major window order over the candidates
+    // inside the image; the running maximum is seeded with the window centre
+    // (v_med3 against +inf is the maximum of two non-NaN scores).
     const uint4* c0 = sd + (my0 - ry0) * rw + (mx0 - rx0);
-    float run = dot16(q16, c0[0], c0[kRegionPx16], c0[2 * kRegionPx16]);
+    float run = dot16(Q.q16, c0[0], c0[CAP], c0[2 * CAP]);
     uint64_t mask0 = 0, mask1 = 0;
-    const int x_lo = max(mx0 - r, 0), x_hi = min(mx0 + r, W - 1);
-    const int y_lo = max(my0 - r, 0), y_hi = min(my0 + r, H - 1);
+    const int reach = r * sp;
     // Wave-uniform choice: the unrolled scan when every active lane's window
-    // is whole (then x_lo = mx0 - r etc.), the bounded loop otherwise.
-    const bool whole = x_lo == mx0 - r && x_hi == mx0 + r && y_lo == my0 - r && y_hi == my0 + r;
-    const uint4* w = sd + (y_lo - ry0) * rw + (x_lo - rx0);
+    // lies inside the image, the bounded loop otherwise.
+    const bool whole = mx0 - reach >= 0 && mx0 + reach <= W - 1 && my0 - reach >= 0 && my0 + reach <= H - 1;
+    const uint4* w = sd + (my0 - reach - ry0) * rw + (mx0 - reach - rx0);
     const bool all_whole = __all(whole) != 0;
-    if (all_whole && r == 3) {
-        scan16_inside<3>(q16, w, rw, tau, run, mask0, mask1);
-    } else if (all_whole && r == 2) {
-        scan16_inside<2>(q16, w, rw, tau, run, mask0, mask1);
-    } else if (all_whole && r == 4) {
-        scan16_inside<4>(q16, w, rw, tau, run, mask0, mask1);
+    if (all_whole && sp == 1 && r == 3) {
+        scan16_inside<3, 1, CAP>(Q.q16, w, rw, tau, run, mask0, mask1);
+    } else if (all_whole && sp == 1 && r == 2) {
+        scan16_inside<2, 1, CAP>(Q.q16, w, rw, tau, run, mask0, mask1);
+    } else if (all_whole && sp == 1 && r == 4) {
+        scan16_inside<4, 1, CAP>(Q.q16, w, rw, tau, run, mask0, mask1);
+    } else if (all_whole && sp == 2 && r == 3) {
+        scan16_inside<3, 2, CAP>(Q.q16, w, rw, tau, run, mask0, mask1);
     } else {
-        for (int my = y_lo; my <= y_hi; ++my) {
+        for (int dy = -r; dy <= r; ++dy) {
+            const int my = my0 + sp * dy;
+            if (my < 0 || my >= H) continue;
             const uint4* d = sd + (my - ry0) * rw - rx0;
-            int k = (my - my0 + r) * side + (x_lo - mx0 + r);
-            for (int mx = x_lo; mx <= x_hi; ++mx, ++k) {
-                const float s16 = dot16(q16, d[mx], d[mx + kRegionPx16], d[mx + 2 * kRegionPx16]);
+            for (int dx = -r; dx <= r; ++dx) {
+                const int mx = mx0 + sp * dx;
+                if (mx < 0 || mx >= W) continue;
+                const int k = (dy + r) * side + (dx + r);
+                const float s16 = dot16(Q.q16, d[mx], d[mx + CAP], d[mx + 2 * CAP]);
                 run = __builtin_amdgcn_fmed3f(s16, run, INFINITY);
                 if (s16 >= run - tau) {
                     if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
@@ -741,117 +772,151 @@ __device__ __forceinline__ long refine_f16(const EdgeArgs& A, long n, const QSta
     };
     auto pixel = [&](int kk) -> long {
         const int dy = kk / side, dx = kk - dy * side;
-        return (long)(my0 + dy - r) * W + (mx0 + dx - r);
+        return (long)(my0 + sp * (dy - r)) * W + (mx0 + sp * (dx - r));
     };
     float best = -INFINITY;
     long bi = -1;
     while (mask0 | mask1) {
         const int k1 = pop(mask0, mask1), k2 = pop(mask0, mask1);
         const long m1 = pixel(k1), m2 = k2 >= 0 ? pixel(k2) : m1;
-        const float s1 = exact24(qd.q, A.Dii, m1), s2 = exact24(qd.q, A.Dii, m2);
+        const float s1 = exact24(Q.qd.q, A.Dii, m1), s2 = exact24(Q.qd.q, A.Dii, m2);
         if (s1 > best) { best = s1; bi = m1; }
         if (k2 >= 0 && s2 > best) { best = s2; bi = m2; }
     }
     return bi;
 }
 
-// One TX x TY tile with the fp16 pre-filtered refine.  Falls back to the exact
-// global scan for the whole tile when the region does not fit, r > 5, or a
-// region value is non-finite or too large for fp16.
-template <int TX, int TY, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1>
-__device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16& S) {
+// One TX x TY tile with the fp16 pre-filtered refine, level by level for the
+// coarse-to-fine refine when MULTI is set (level l scans the grid of spacing 2^l around the
+// previous level's best).  For each level the region is the bounding box of
+// the windows of the tile's good queries; a level whose region does not fit,
+// whose radius exceeds 5, or whose region holds a value too large for fp16
+// is scanned exactly from global memory instead (the whole tile at that level).
+template <int TX, int TY, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1, bool MULTI = false>
+__device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty,
+                                         TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16>& S) {
     constexpr int NT = TX * TY;
+    constexpr int CAP = MULTI ? kRegionPx16Multi : kRegionPx16;
     const int tid = threadIdx.x;
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, kRegionPx16, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+    tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, CAP, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
                 min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
-    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
-    if (q.good) {
-        int mx0 = round_half_up(q.px), my0 = round_half_up(q.py);
-        lx = max(mx0 - r, 0); hx = min(mx0 + r, W - 1);
-        ly = max(my0 - r, 0); hy = min(my0 + r, H - 1);
-    }
-    block_box<NT>(lx, hx, ly, hy, S.box);
     const int wv = tid >> 6;
-    const int rw = hx - lx + 1, rh = hy - ly + 1;
-    const bool any = hx >= lx;
-    bool use16 = any && rw * rh <= kRegionPx16 && r <= 5 && A.levels == 1;
-    float pn2 = 0.f;  // largest |d|^2 over the region's pixels
-    if (use16) {
-        // Stage: each lane converts whole pixels (six float4 loads, the norm,
-        // three fp16 planes), kBatch pixels per step with all loads issued
-        // before the conversions and stores.
-        constexpr int kBatch = 2;
-        const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
-        const int total = rw * rh;
-        const SmallDiv div_rw(rw);
-        for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
-            float4 v[kBatch][6];
+    const long n = (long)y * W + x;
+    long bi = -1;
+    bool live = q.good;   // takes part in the level below
+    int cx = live ? round_half_up(q.px) : 0, cy = live ? round_half_up(q.py) : 0;
+    // MULTI = false: one level (the launcher takes the MULTI kernel for L > 1;
+    // a constant trip count keeps the single-level kernel free of spills).
+    for (int lev = MULTI ? A.levels - 1 : 0; lev >= 0; --lev) {
+        const int sp = 1 << lev, reach = r * sp;
+        int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+        if (live) {
+            lx = max(cx - reach, 0); hx = min(cx + reach, W - 1);
+            ly = max(cy - reach, 0); hy = min(cy + reach, H - 1);
+        }
+        block_box<NT>(lx, hx, ly, hy, S.box);  // ends with a barrier: the previous level is done with S
+        const int rw = hx - lx + 1, rh = hy - ly + 1;
+        const bool any = hx >= lx;
+        bool use16 = any && rw * rh <= CAP && r <= 5;
+        float pn2 = 0.f;  // largest |d|^2 over the region's pixels
+        if (use16) {
+            // Stage: each lane converts whole pixels (six float4 loads, the norm,
+            // three fp16 planes), kBatch pixels per step with all loads issued
+            // before the conversions and stores.
+            constexpr int kBatch = 2;
+            const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
+            const int total = rw * rh;
+            const SmallDiv div_rw(rw);
+            for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
+                float4 v[kBatch][6];
 #pragma unroll
-            for (int i = 0; i < kBatch; ++i) {
-                const int pix = p00 + tid + i * NT;
-                if (pix < total) {
-                    const int ry = div_rw(pix), rx = pix - ry * rw;
-                    const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
+                for (int i = 0; i < kBatch; ++i) {
+                    const int pix = p00 + tid + i * NT;
+                    if (pix < total) {
+                        const int ry = div_rw(pix), rx = pix - ry * rw;
+                        const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
 #pragma unroll
-                    for (int k = 0; k < 6; ++k) v[i][k] = src[k];
+                        for (int k = 0; k < 6; ++k) v[i][k] = src[k];
+                    }
                 }
-            }
 #pragma unroll
-            for (int i = 0; i < kBatch; ++i) {
-                const int pix = p00 + tid + i * NT;
-                if (pix < total) {
-                    float e2 = 0.f;
+                for (int i = 0; i < kBatch; ++i) {
+                    const int pix = p00 + tid + i * NT;
+                    if (pix < total) {
+                        float e2 = 0.f;
 #pragma unroll
-                    for (int k = 0; k < 6; ++k)
-                        e2 += v[i][k].x * v[i][k].x + v[i][k].y * v[i][k].y + v[i][k].z * v[i][k].z + v[i][k].w * v[i][k].w;
-                    // A NaN or infinite element, or squares that overflow, make e2
-                    // non-finite and fail the range test below.
-                    pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
+                        for (int k = 0; k < 6; ++k)
+                            e2 += v[i][k].x * v[i][k].x + v[i][k].y * v[i][k].y + v[i][k].z * v[i][k].z + v[i][k].w * v[i][k].w;
+                        // A NaN or infinite element, or squares that overflow, make e2
+                        // non-finite and fail the range test below.
+                        pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
 #pragma unroll
-                    for (int k = 0; k < 3; ++k) {
-                        const float4 u = v[i][2 * k], w = v[i][2 * k + 1];
-                        S.desc[k * kRegionPx16 + pix] =
-                            make_uint4(pack_h2(u.x * kScale16, u.y * kScale16), pack_h2(u.z * kScale16, u.w * kScale16),
-                                       pack_h2(w.x * kScale16, w.y * kScale16), pack_h2(w.z * kScale16, w.w * kScale16));
+                        for (int k = 0; k < 3; ++k) {
+                            const float4 u = v[i][2 * k], w = v[i][2 * k + 1];
+                            S.desc[k * CAP + pix] =
+                                make_uint4(pack_h2(u.x * kScale16, u.y * kScale16), pack_h2(u.z * kScale16, u.w * kScale16),
+                                           pack_h2(w.x * kScale16, w.y * kScale16), pack_h2(w.z * kScale16, w.w * kScale16));
+                        }
                     }
                 }
             }
         }
-    }
-    // Region bounds: |d| <= sqrt(pn2) for every pixel, so every element
-    // |d_k| <= sqrt(pn2) (kScale16^2 pn2 <= kF16Max^2 keeps the scaled
-    // conversion finite), and |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
+        // Region bounds: |d| <= sqrt(pn2) for every pixel, so every element
+        // |d_k| <= sqrt(pn2) (kScale16^2 pn2 <= kF16Max^2 keeps the scaled
+        // conversion finite), and |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
-    if ((tid & 63) == 0) S.stat[wv] = pn2;
-    __syncthreads();
-    pn2 = S.stat[0];
+        for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
+        if ((tid & 63) == 0) S.stat[wv] = pn2;
+        __syncthreads();
+        pn2 = S.stat[0];
 #pragma unroll
-    for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
-    use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
-    if (any && !use16 && tid == 0) count_path(kPathRefineGlobal);
-    if (q.good) {
-        const long n = (long)y * W + x;
-        const float dnorm = sqrtf(pn2) * 1.0001f;
-        long bi = use16 ? refine_f16(A, n, q, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
-                        : refine_global<24>(A, n, q);
-        finish(A, n, q, bi);
+        for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
+        use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
+        if (any && !use16 && tid == 0) count_path(kPathRefineGlobal);
+        Query16 Q;
+        if (live) {
+            // The query descriptor is read after each level's region is staged
+            // (its registers are not live during the staging).  A query whose
+            // own descriptor is outside the fp16 range refines every level
+            // exactly from global memory and leaves the levels below.
+            load_query16(A, n, Q);
+            if (!Q.ok) {
+                count_path(kPathRefineQuery);
+                bi = refine_global<24>(A, n, q);
+                live = false;
+            }
+        }
+        if (live) {
+            const float dnorm = sqrtf(pn2) * 1.0001f;
+            const long lb = use16 ? refine_f16_level<CAP>(A, Q, cx, cy, sp, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
+                                  : refine_global_level<24>(A, Q.qd, cx, cy, sp);
+            if (lb < 0) {
+                live = false;
+            } else {
+                bi = lb;
+                cx = (int)(lb % W);
+                cy = (int)(lb / W);
+            }
+        }
     }
+    if (q.good) finish(A, n, q, bi);
     __syncthreads();  // the next tile may overwrite S
 }
 
 // Four workgroups of 256 lanes fit a CU by LDS; keep the registers within that too.
-template <int TX, int TY>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(4))) fwd_f16_kernel(EdgeArgs A, int remap) {
-    __shared__ TileLds16 S;
+// The multi-level refine keeps more state per lane: three waves per SIMD.
+template <int TX, int TY, bool MULTI>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MULTI ? 3 : 4)))
+fwd_f16_kernel(EdgeArgs A, int remap) {
+    __shared__ TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16> S;
     const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
     const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
     if (t < 0) return;
-    tile_f16<TX, TY, true>(A, t % tiles_x, t / tiles_x, S);
+    tile_f16<TX, TY, true, kRayMargin, 1, MULTI>(A, t % tiles_x, t / tiles_x, S);
 }
 
 template <int TX, int TY>
@@ -894,12 +959,14 @@ __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __res
 // tile).  LDS tiles need D = 24 and 16-byte aligned descriptors on every edge.
 // MODE 0: refine from global memory; 1: fp32 region in LDS; 2: fp16 pre-filter
 // with ray-window margin MARGIN and LM unroll UNROLL.
-template <int TX, int TY, int DT, int MODE, int MARGIN = kRayMargin, int UNROLL = 1>
-__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? 4 : 1)))
+template <int TX, int TY, int DT, int MODE, int MARGIN = kRayMargin, int UNROLL = 1, bool MULTI = false>
+__global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MODE == 2 ? (MULTI ? 3 : 4) : 1)))
 batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
                                                                int32_t* __restrict__ counter) {
     __shared__ int s_tile;
-    __shared__ typename std::conditional<MODE == 1, TileLds, typename std::conditional<MODE == 2, TileLds16, int>::type>::type S;
+    __shared__ typename std::conditional<
+        MODE == 1, TileLds,
+        typename std::conditional<MODE == 2, TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16>, int>::type>::type S;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
@@ -913,7 +980,7 @@ batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
         if constexpr (MODE == 1) {
             tile_lds<TX, TY>(A, tx, ty, S);
         } else if constexpr (MODE == 2) {
-            tile_f16<TX, TY, false, MARGIN, UNROLL>(A, tx, ty, S);
+            tile_f16<TX, TY, false, MARGIN, UNROLL, MULTI>(A, tx, ty, S);
         } else {
             int x = tx * TX + (int)(threadIdx.x % TX);
             int y = ty * TY + (int)(threadIdx.x / TX);
@@ -1206,8 +1273,10 @@ static void launch_fwd_tile(const EdgeArgs& A, bool desc_regs, int mode, bool re
     const int tiles = ((A.W + TX - 1) / TX) * ((A.H + TY - 1) / TY);
     const int grid = remap ? ((tiles + kXcds - 1) / kXcds) * kXcds : tiles;
     const int rm = remap ? 1 : 0;
-    if (mode == 2 && desc_regs)
-        fwd_f16_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A, rm);
+    if (mode == 2 && desc_regs && A.levels > 1)
+        fwd_f16_kernel<TX, TY, true><<<grid, TX * TY, 0, s>>>(A, rm);
+    else if (mode == 2 && desc_regs)
+        fwd_f16_kernel<TX, TY, false><<<grid, TX * TY, 0, s>>>(A, rm);
     else if (mode == 1 && desc_regs)
         fwd_lds_kernel<TX, TY><<<grid, TX * TY, 0, s>>>(A, rm);
     else if (desc_regs)
@@ -1248,8 +1317,13 @@ static void launch_batched_f16(const EdgeArgs* table, int n_edges, int total_til
 
 template <int TX, int TY>
 static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_tiles, int32_t* counter, int grid,
-                                bool desc_regs, int mode, int margin, int unroll, hipStream_t s) {
+                                bool desc_regs, int mode, int margin, int unroll, int levels, hipStream_t s) {
     if constexpr (TX == 16 && TY == 16) {
+        if (mode == 2 && desc_regs && levels > 1) {
+            batched_fwd_kernel<TX, TY, 24, 2, kRayMargin, 1, true><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles,
+                                                                                        counter);
+            return;
+        }
         if (mode == 2 && desc_regs) {
             const int v = 2 * (margin - 1) + (unroll - 1);
             switch (v) {
@@ -1273,7 +1347,7 @@ static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_ti
 
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
                           int total_tiles, int32_t* counter, int tile_config, int grid, int margin, int unroll,
-                          bool desc_regs, hipStream_t s) {
+                          int levels, bool desc_regs, hipStream_t s) {
     timer_begin("batched_counter", s);
     set_counter_kernel<<<1, 64, 0, s>>>(counter);
     timer_end(s);
@@ -1282,12 +1356,12 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
     timer_end(s);
     timer_begin("batched_fwd", s);
     switch (tile_config) {
-        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
-        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
-        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, s); break;
-        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, s); break;
-        case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, margin, unroll, s); break;
-        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, s); break;
+        case 1: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, levels, s); break;
+        case 2: launch_batched_tile<64, 4>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, levels, s); break;
+        case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, levels, s); break;
+        case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, levels, s); break;
+        case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, margin, unroll, levels, s); break;
+        default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, levels, s); break;
     }
     timer_end(s);
     return hipGetLastError();

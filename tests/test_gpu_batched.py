@@ -176,3 +176,21 @@ def test_autotune_cache_file_round_trip(m3s, tmp_path):
     finally:
         m3s.set_tune_cache(None)
         lib.m3s_clear_caches()
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_batched_coarse_to_fine_equals_per_pair(m3s, levels):
+    """The persistent kernel's multi-level refine equals the per-pair launch bit for bit."""
+    import torch
+    edges = edge_inputs(m3s, mixed_pairs())
+    ref = []
+    for e in edges:
+        prm = m3s.params(max_iter=e.max_iter, refine_radius=e.refine_radius, refine_levels=levels)
+        ref.append(parity.result_numpy(m3s.match(e.Xii, e.Xji, e.Dii, e.Dji, e.Qii, e.Qji, None, prm,
+                                                 want_xhat=True)))
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        outs = m3s.match_batched(edges, prm=m3s.params(refine_levels=levels), graph=True, want_xhat=True)
+    s.synchronize()
+    for k, (a, b) in enumerate(zip(ref, outs)):
+        assert_same(a, parity.result_numpy(b), "L%d edge %d" % (levels, k))

@@ -268,6 +268,40 @@ def test_refine_levels(m3s, levels):
         assert np.array_equal(outs[0][k], outs[1][k]) and np.array_equal(outs[0][k], outs[2][k]), k
 
 
+@pytest.mark.parametrize("levels", [2, 3])
+def test_refine_levels_fast_path(m3s, levels):
+    """Coarse-to-fine in the fp16 tile configuration at 512x384, from
+    previous-frame initial pixels (the tracking setting, Sec. 3.2): the levels
+    whose regions fit LDS run on the pre-filtered path (L = 2: every level of
+    every tile; L = 3: the finer two), the rest scan global memory, and the
+    result equals the global-memory configuration bit for bit and the oracle."""
+    pair = synth.config_pair(2)
+    rng = np.random.Generator(np.random.PCG64(60 + levels))
+    p_init = (pair.proj + rng.normal(0, 1.5, size=pair.proj.shape)).astype(np.float32)
+    t = parity.pair_tensors(pair)
+    outs, cnts = [], []
+    for cfg in (5, 0):
+        m3s.path_counters(reset=True)
+        m3s.set_launch(tile_config=cfg)
+        try:
+            res = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"], parity.to_dev(p_init),
+                            m3s.params(refine_levels=levels), want_xhat=True)
+            outs.append(parity.result_numpy(res))
+        finally:
+            m3s.set_launch()
+        cnts.append(m3s.path_counters(reset=True))
+    print("levels", levels, "counters (fp16, global):", cnts)
+    tiles = (384 // 16) * (512 // 16)
+    if levels == 2:
+        assert cnts[0]["refine_global"] == 0
+    else:
+        assert 0 < cnts[0]["refine_global"] <= tiles      # the coarsest level only
+    for k in ("p", "idx", "valid", "theta", "xhat"):
+        assert np.array_equal(outs[0][k], outs[1][k], equal_nan=True), k
+    o = ora(pair, p_init.astype(np.float64), levels=levels)
+    print(parity.compare(outs[0], o, "tracking L%d" % levels))
+
+
 def sys_path_pins():
     import sys
     here = os.path.dirname(os.path.abspath(__file__))
