@@ -232,9 +232,10 @@ def main():
     log("kernel timing: fwd %.2f us, prep %.2f us" % (kt["fwd"] * 1e3, kt["prep"] * 1e3))
 
     # Forward kernel time per tile configuration (0-2: refine from global
-    # memory; 3-4: refine region staged in LDS; 5: fp16 pre-filter), same pool and steps.
+    # memory; 3-4: refine region staged in LDS; 5: fp16 pre-filter; 6: the same
+    # with 8x8 one-wave tiles), same pool and steps.
     sweep = {}
-    for tc, remap in [(t, "1") for t in range(6)] + [(3, "0"), (5, "0")]:
+    for tc, remap in [(t, "1") for t in range(7)] + [(3, "0"), (5, "0"), (6, "0")]:
         m3s.set_launch(tile_config=tc, xcd_remap=int(remap))
         lib.m3s_timing_reset()
         lib.m3s_timing_enable(1)

@@ -414,7 +414,8 @@ void m3s_batched_last_config(int32_t *grid, int32_t *tile_config);
  * library's choice; -1 or 0 in a field keeps the library's choice for it):
  *   tile_config  0: 32x8, 1: 16x16, 2: 64x4 query tiles refining from global
  *                memory; 3: 16x16, 4: 32x8 with the refine region staged in LDS
- *                (fp32); 5: 16x16 with an fp16 pre-filter (the default);
+ *                (fp32); 5: 16x16 with an fp16 pre-filter (the default); 6: 8x8
+ *                one-wave tiles with the fp16 pre-filter;
  *   grid         workgroups of the persistent batched launch (> 0);
  *   xcd_remap    0 turns off the tile-to-XCD band mapping of the single-pair launch;
  *   ray_margin   margin in pixels (1..3, default 2) of the LM ray window the

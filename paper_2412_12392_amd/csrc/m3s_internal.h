@@ -8,12 +8,13 @@
 
 namespace m3s {
 
-// Tile configurations of the forward kernels (query tile TX x TY, 256 lanes):
+// Tile configurations of the forward kernels (query tile TX x TY, one lane per query):
 // 0: 32x8, 1: 16x16, 2: 64x4 with the refine reading global memory;
 // 3: 16x16, 4: 32x8 with the refine region staged in LDS (D = 24 only);
 // 5: 16x16 with an fp16 copy of the region and an exact fp32 rescoring of the
-// candidates that can be the maximum (D = 24, r <= 5).
-constexpr int kNumTileConfigs = 6;
+// candidates that can be the maximum (D = 24, r <= 5); 6: the same with 8x8
+// one-wave tiles (64 lanes, no cross-wave barriers, 256-pixel regions).
+constexpr int kNumTileConfigs = 7;
 constexpr int kDefaultTileConfig = 5;
 void tile_shape(int tile_config, int* tx, int* ty);
 bool tile_uses_lds(int tile_config);

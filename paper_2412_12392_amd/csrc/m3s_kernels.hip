@@ -587,6 +587,13 @@ typedef _Float16 h2_t __attribute__((ext_vector_type(2)));
 
 constexpr int kRegionPx16 = 832;          // 832 px x 48 B = 39 KiB: four workgroups per CU
 constexpr int kRegionPx16Multi = 1088;    // the multi-level kernel: 51 KiB, three workgroups per CU
+constexpr int kRegionPx16Small = 256;     // 8 x 8 tiles: 12 KiB, twelve one-wave workgroups per CU
+
+// Region capacity (pixels) of a tile shape's fp16 LDS buffers.
+template <int TX, int TY, bool MULTI>
+constexpr int f16_cap() {
+    return MULTI ? kRegionPx16Multi : (TX * TY <= 64 ? kRegionPx16Small : kRegionPx16);
+}
 constexpr float kF16Max = 60000.f;        // larger scaled magnitudes fall back to the exact scan
 constexpr float kScale16 = 256.f;         // 2^8, applied to both operands before the conversion
 constexpr float kU16 = 4.8828125e-4f;     // 2^-11
@@ -793,10 +800,9 @@ __device__ __forceinline__ long refine_f16_level(const EdgeArgs& A, const Query1
 // whose radius exceeds 5, or whose region holds a value too large for fp16
 // is scanned exactly from global memory instead (the whole tile at that level).
 template <int TX, int TY, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1, bool MULTI = false>
-__device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty,
-                                         TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16>& S) {
+__device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16<f16_cap<TX, TY, MULTI>()>& S) {
     constexpr int NT = TX * TY;
-    constexpr int CAP = MULTI ? kRegionPx16Multi : kRegionPx16;
+    constexpr int CAP = f16_cap<TX, TY, MULTI>();
     const int tid = threadIdx.x;
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
@@ -912,7 +918,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty,
 template <int TX, int TY, bool MULTI>
 __global__ void __launch_bounds__(TX * TY) __attribute__((amdgpu_waves_per_eu(MULTI ? 3 : 4)))
 fwd_f16_kernel(EdgeArgs A, int remap) {
-    __shared__ TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16> S;
+    __shared__ TileLds16<f16_cap<TX, TY, MULTI>()> S;
     const int tiles_x = (A.W + TX - 1) / TX, tiles = tiles_x * ((A.H + TY - 1) / TY);
     const int t = tile_of_block(blockIdx.x, tiles, remap != 0);
     if (t < 0) return;
@@ -966,7 +972,7 @@ batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
     __shared__ int s_tile;
     __shared__ typename std::conditional<
         MODE == 1, TileLds,
-        typename std::conditional<MODE == 2, TileLds16<MULTI ? kRegionPx16Multi : kRegionPx16>, int>::type>::type S;
+        typename std::conditional<MODE == 2, TileLds16<f16_cap<TX, TY, MULTI>()>, int>::type>::type S;
     for (;;) {
         if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
         __syncthreads();
@@ -1289,6 +1295,7 @@ void tile_shape(int tile_config, int* tx, int* ty) {
     switch (tile_config) {
         case 1: case 3: case 5: *tx = 16; *ty = 16; return;
         case 2: *tx = 64; *ty = 4; return;
+        case 6: *tx = 8; *ty = 8; return;
         default: *tx = 32; *ty = 8; return;
     }
 }
@@ -1303,6 +1310,7 @@ hipError_t launch_fwd(const EdgeArgs& A, int tile_config, bool desc_regs, bool x
         case 3: launch_fwd_tile<16, 16>(A, desc_regs, 1, xcd_remap, s); break;
         case 4: launch_fwd_tile<32, 8>(A, desc_regs, 1, xcd_remap, s); break;
         case 5: launch_fwd_tile<16, 16>(A, desc_regs, 2, xcd_remap, s); break;
+        case 6: launch_fwd_tile<8, 8>(A, desc_regs, 2, xcd_remap, s); break;
         default: launch_fwd_tile<32, 8>(A, desc_regs, 0, xcd_remap, s); break;
     }
     timer_end(s);
@@ -1336,6 +1344,15 @@ static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_ti
             }
             return;
         }
+    } else {
+        if (mode == 2 && desc_regs) {
+            if (levels > 1)
+                batched_fwd_kernel<TX, TY, 24, 2, kRayMargin, 1, true><<<grid, TX * TY, 0, s>>>(table, n_edges,
+                                                                                            total_tiles, counter);
+            else
+                batched_fwd_kernel<TX, TY, 24, 2><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
+            return;
+        }
     }
     if (mode == 1 && desc_regs)
         batched_fwd_kernel<TX, TY, 24, 1><<<grid, TX * TY, 0, s>>>(table, n_edges, total_tiles, counter);
@@ -1361,6 +1378,7 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
         case 3: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, levels, s); break;
         case 4: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 1, margin, unroll, levels, s); break;
         case 5: launch_batched_tile<16, 16>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, margin, unroll, levels, s); break;
+        case 6: launch_batched_tile<8, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 2, margin, unroll, levels, s); break;
         default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, levels, s); break;
     }
     timer_end(s);

@@ -122,7 +122,8 @@ def test_every_launch_candidate_gives_identical_bits(m3s):
     import torch
     edges = edge_inputs(m3s, mixed_pairs())
     ref = per_pair(m3s, edges)
-    cands = [(t, 64, -1, -1) for t in range(5)] + [(5, g, m, u) for g in (32, 1024) for m in (1, 2, 3) for u in (1, 2)]
+    cands = [(t, 64, -1, -1) for t in (0, 1, 2, 3, 4, 6)] + [(5, g, m, u) for g in (32, 1024) for m in (1, 2, 3)
+                                                             for u in (1, 2)]
     s = torch.cuda.Stream()
     for t, g, m, u in cands:
         print("case launch tile %d grid %d margin %d unroll %d" % (t, g, m, u), flush=True)

@@ -55,7 +55,7 @@ def permuted_queries(pair, seed):
                       K=pair.K, r=pair.r, proj=f(pair.proj))
 
 
-@pytest.mark.parametrize("tile_config", [3, 5])
+@pytest.mark.parametrize("tile_config", [3, 5, 6])
 def test_lm_window_overflow(m3s, tile_config):
     """Shuffled queries: after the first iteration a tile's queries sit on cells
     all over the image, so every tile's LM window exceeds the LDS cap and
@@ -64,12 +64,13 @@ def test_lm_window_overflow(m3s, tile_config):
     print("case lm_window_overflow tile %d" % tile_config, flush=True)
     g, cnt = run_counted(m3s, pair, tile_config, None, max_iter=10)
     print(cnt)
-    assert cnt["lm_global"] >= 44          # 48 tiles of 16 x 16
+    tiles = 48 if tile_config != 6 else 192   # 16 x 16 or 8 x 8 tiles
+    assert cnt["lm_global"] >= 0.9 * tiles
     o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji, K=10, r=pair.r)
     print(parity.compare(g, o, "lm window overflow (tile %d)" % tile_config, pair=pair, r=pair.r))
 
 
-@pytest.mark.parametrize("tile_config", [3, 5])
+@pytest.mark.parametrize("tile_config", [3, 5, 6])
 def test_refine_region_overflow(m3s, tile_config):
     """K = 0 from scattered pixels: p* is the initial pixel, the tile's refine
     windows lie all over the image and the region exceeds LDS, so every tile
@@ -80,7 +81,7 @@ def test_refine_region_overflow(m3s, tile_config):
     print("case refine_region_overflow tile %d" % tile_config, flush=True)
     g, cnt = run_counted(m3s, pair, tile_config, pi, max_iter=0, max_theta=float("inf"))
     print(cnt)
-    assert cnt["refine_global"] == 48
+    assert cnt["refine_global"] == (48 if tile_config != 6 else 192)
     o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji, pi.astype(np.float64),
                          K=0, r=pair.r, max_theta=np.inf)
     st = parity.compare(g, o, "refine region overflow (tile %d)" % tile_config, p_theta_max=np.inf, pair=pair,
@@ -147,7 +148,7 @@ def _edges(m3s, pairs):
     return out
 
 
-@pytest.mark.parametrize("tile_config", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("tile_config", [0, 1, 2, 3, 4, 5, 6])
 def test_batched_every_tile_config(m3s, tile_config):
     """The persistent kernel in each tile configuration equals the per-pair
     launch bit for bit, and two edges agree with the oracle."""

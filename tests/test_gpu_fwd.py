@@ -170,7 +170,7 @@ def test_tile_configs_bitwise_and_deterministic(m3s):
     pair = _pair(200, 264, 16)
     outs = []
     try:
-        for tc in (0, 1, 2, 3, 4, 5, 3):
+        for tc in (0, 1, 2, 3, 4, 5, 6, 3):
             m3s.set_launch(tile_config=tc)
             outs.append(run(m3s, pair))
         m3s.set_launch(tile_config=5, xcd_remap=0)
@@ -240,9 +240,11 @@ def test_fp16_prefilter_is_exact(m3s, case):
     a = _run_cfg(m3s, pair, "0", **prm)
     b = _run_cfg(m3s, pair, "5", **prm)
     c = _run_cfg(m3s, pair, "3", **prm)
+    d = _run_cfg(m3s, pair, "6", **prm)
     for k in ("p", "idx", "valid", "theta"):
         assert np.array_equal(a[k], b[k], equal_nan=True), "%s: %s (fp16 pre-filter)" % (case, k)
         assert np.array_equal(a[k], c[k], equal_nan=True), "%s: %s (fp32 LDS)" % (case, k)
+        assert np.array_equal(a[k], d[k], equal_nan=True), "%s: %s (fp16 pre-filter, 8x8 tiles)" % (case, k)
 
 
 @pytest.mark.parametrize("levels", [2, 3])
@@ -263,9 +265,9 @@ def test_refine_levels(m3s, levels):
     off = rng.integers(-reach, reach + 1, size=(base.H, base.W, 2))
     code = _with_desc(base, pins._position_code(xs, ys), pins._position_code(m0[..., 0] + off[..., 0], m0[..., 1] + off[..., 1]))
     g, o, st = check(m3s, code, "position code L%d" % levels, levels=levels)
-    outs = [_run_cfg(m3s, code, c, refine_levels=levels) for c in ("0", "3", "5")]
+    outs = [_run_cfg(m3s, code, c, refine_levels=levels) for c in ("0", "3", "5", "6")]
     for k in ("p", "idx", "valid", "theta"):
-        assert np.array_equal(outs[0][k], outs[1][k]) and np.array_equal(outs[0][k], outs[2][k]), k
+        assert all(np.array_equal(outs[0][k], o[k]) for o in outs[1:]), k
 
 
 @pytest.mark.parametrize("levels", [2, 3])
