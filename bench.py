@@ -221,7 +221,7 @@ def main():
         kt[name] = tot.value / max(cnt.value, 1)
     alg_bytes = FWD_BYTES_PER_QUERY * N
     achieved = alg_bytes / (kt["fwd"] * 1e-3) / 1e9
-    traffic_bytes = measured_traffic("fwd_f16_kernel<16, 16>")
+    traffic_bytes = measured_traffic("fwd_f16_kernel<16, 16, false>")
     traffic = None if traffic_bytes is None else round(traffic_bytes / (kt["fwd"] * 1e-3) / 1e9, 1)
     roofline = {"bound": "hbm", "kernel": "fwd_f16_kernel<16,16>", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -262,7 +262,7 @@ def main():
            "paper_context": {"hardware": "NVIDIA RTX 4090", "match_ms_projection": 0.5,
                              "match_ms_projection_refine": 2.0, "system_fps": 15,
                              "this_ms_per_step": round(ms_per_step, 5)}}
-    vpw = measured_valu_per_wave("fwd_f16_kernel<16, 16>")
+    vpw = measured_valu_per_wave("fwd_f16_kernel<16, 16, false>")
     if vpw is not None:
         waves = ((pool[0].W + 15) // 16) * ((pool[0].H + 15) // 16) * 4
         ach = vpw * waves / (kt["fwd"] * 1e-3) / 1e9

@@ -678,7 +678,9 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
     auto* dtable = reinterpret_cast<m3s::BwdEdgeArgs*>(W + align_up(sizeof(int32_t)));
     hipError_t e = hipMemcpyAsync(dtable, table.data(), sizeof(m3s::BwdEdgeArgs) * table.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(backward edge table)");
-    const int grid = std::max(1, std::min((int)tiles, g_override.grid > 0 ? g_override.grid : info.cus * 4));
+    // Eight workgroups per CU (measured on the 16-edge workload: 230 us against
+    // 241 us with four and 293 us with two).
+    const int grid = std::max(1, std::min((int)tiles, g_override.grid > 0 ? g_override.grid : info.cus * 8));
     if ((flags & M3S_BATCH_GRAPH) && st != nullptr) {
         std::string gkey = std::to_string(dev) + "|" + sig + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) +
                            "|" + std::to_string(grid);
