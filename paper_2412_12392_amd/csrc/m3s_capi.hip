@@ -636,7 +636,7 @@ m3s_status m3s_match_bwd(const m3s_pair* pair, const m3s_outputs* fwd, const flo
 
 size_t m3s_bwd_batched_workspace_bytes(int32_t n_edges) {
     if (n_edges < 1 || n_edges > (1 << 20)) return 0;
-    return align_up(sizeof(int32_t)) + align_up(sizeof(m3s::BwdEdgeArgs) * (size_t)n_edges);
+    return align_up(sizeof(m3s::BwdEdgeArgs) * (size_t)n_edges);
 }
 
 m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uint32_t flags, void* ws,
@@ -674,8 +674,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
                     "m3s_match_bwd_batched cannot be captured: it copies its edge table from host memory before every "
                     "launch; M3S_BATCH_GRAPH gives a library-managed graph instead");
     char* W = reinterpret_cast<char*>(ws);
-    int32_t* counter = reinterpret_cast<int32_t*>(W);
-    auto* dtable = reinterpret_cast<m3s::BwdEdgeArgs*>(W + align_up(sizeof(int32_t)));
+    auto* dtable = reinterpret_cast<m3s::BwdEdgeArgs*>(W);
     hipError_t e = hipMemcpyAsync(dtable, table.data(), sizeof(m3s::BwdEdgeArgs) * table.size(), hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(backward edge table)");
     // Eight workgroups per CU (measured on the 16-edge workload: 230 us against
@@ -693,7 +692,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
         if (!exec) {
             e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, counter, grid, st);
+            hipError_t le = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
             if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "captured launch"); }
@@ -709,7 +708,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
         m3s::timer_end(st);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        e = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, counter, grid, st);
+        e = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, st);
         if (e != hipSuccess) return hip_fail(e, "batched backward launch");
     }
     g_last_error.clear();

@@ -58,11 +58,11 @@ struct BwdEdgeArgs {
     float* dXji;
 };
 hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s);
-// Zero every edge's dXii and reset the counter (one launch), then the
-// persistent backward over all edges' tiles (one launch).  max_pixels: the
-// largest H * W of the table.
-hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles,
-                              int32_t* counter, int grid, hipStream_t s);
+// Zero every edge's dXii (one launch), then the backward over all edges'
+// tiles with `grid` workgroups (one launch).  max_pixels: the largest H * W of
+// the table.
+hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles, int grid,
+                              hipStream_t s);
 
 // Tracking pose solve (m3s_track.hip): workgroups of one iteration launch,
 // workspace bytes, and the launch sequence (init + iters + 1 launches).

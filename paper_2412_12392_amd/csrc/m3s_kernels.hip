@@ -1023,13 +1023,32 @@ __device__ __forceinline__ float3 norm_jac_apply(float3 X, float3 v) {
     return f3((v.x - u.x * uv) * inv, (v.y - u.y * uv) * inv, (v.z - u.z * uv) * inv);
 }
 
-// Adjoint of one valid query n: writes dXji[n] and returns the four corner
-// pixels of p* with the gradient each receives in dXii (zero weight: none).
-__device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict__ Xii, const float* __restrict__ Xji,
-                                          const float* __restrict__ p, const float* __restrict__ grad_p,
-                                          const float* __restrict__ grad_xhat, float* __restrict__ dXji, long n,
-                                          long cm[4], float3 gc[4], int& cx0, int& cy0) {
-    float px = p[2 * n], py = p[2 * n + 1];
+// Per-query inputs of the backward, read before the query's validity is
+// known so that every load of a tile is in flight at once.
+struct BwdQueryIn {
+    float px, py, gp0, gp1;
+    float3 gx, xq;  // grad_xhat[n] (zero without it), X^j_i[n]
+};
+
+// Loads and atomics through global (not flat) instructions: the pointers of
+// an edge table read from memory are generic, which makes the compiler emit
+// flat accesses that also count against the LDS wait counter.
+template <class T>
+__device__ __forceinline__ T ld_global(const T* ptr, long i) {
+    return ((const __attribute__((address_space(1))) T*)ptr)[i];
+}
+__device__ __forceinline__ float3 ld_global_point(const float* X, long m) {
+    return f3(ld_global(X, 3 * m), ld_global(X, 3 * m + 1), ld_global(X, 3 * m + 2));
+}
+__device__ __forceinline__ void add_global(float* ptr, float v) {
+    __builtin_amdgcn_global_atomic_fadd_f32((__attribute__((address_space(1))) float*)ptr, v);
+}
+
+// Adjoint of one valid query: returns dXji[n] and the four corner pixels of p*
+// with the gradient each receives in dXii (zero weight: none).
+__device__ __forceinline__ float3 bwd_query(int H, int W, const float* __restrict__ Xii, bool has_gx,
+                                            const BwdQueryIn& in, long cm[4], float3 gc[4], int& cx0, int& cy0) {
+    const float px = in.px, py = in.py;
     int x0 = min(max((int)floorf(px), 0), W - 2), y0 = min(max((int)floorf(py), 0), H - 2);
     float a = px - (float)x0, b = py - (float)y0;
     const long cm_[4] = {(long)y0 * W + x0, (long)y0 * W + x0 + 1, (long)(y0 + 1) * W + x0, (long)(y0 + 1) * W + x0 + 1};
@@ -1037,7 +1056,7 @@ __device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict_
     float3 X[4], R[4];
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
-        X[c] = load_point(Xii, cm_[c]);
+        X[c] = ld_global_point(Xii, cm_[c]);
         R[c] = unit_ray(X[c]);
     }
     float3 r = f3(w[0] * R[0].x + w[1] * R[1].x + w[2] * R[2].x + w[3] * R[3].x,
@@ -1052,10 +1071,9 @@ __device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict_
                     (1.f - a) * (R[2].z - R[0].z) + a * (R[3].z - R[1].z));
     float3 j0 = norm_jac_apply(r, drx), j1 = norm_jac_apply(r, dry);
 
-    float gp0 = grad_p[2 * n], gp1 = grad_p[2 * n + 1];
-    float3 gx = f3(0.f, 0.f, 0.f);
-    if (grad_xhat) {
-        gx = load_point(grad_xhat, n);
+    float gp0 = in.gp0, gp1 = in.gp1;
+    const float3 gx = in.gx;
+    if (has_gx) {
         float3 dxx = f3((1.f - b) * (X[1].x - X[0].x) + b * (X[3].x - X[2].x),
                         (1.f - b) * (X[1].y - X[0].y) + b * (X[3].y - X[2].y),
                         (1.f - b) * (X[1].z - X[0].z) + b * (X[3].z - X[2].z));
@@ -1093,8 +1111,7 @@ __device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict_
         mu1 = (a00 * gp1 - a01 * gp0) * idet;
     }
     float3 v = f3(j0.x * mu0 + j1.x * mu1, j0.y * mu0 + j1.y * mu1, j0.z * mu0 + j1.z * mu1);
-    float3 dq = solve ? norm_jac_apply(load_point(Xji, n), v) : f3(0.f, 0.f, 0.f);
-    dXji[3 * n] = dq.x; dXji[3 * n + 1] = dq.y; dXji[3 * n + 2] = dq.z;
+    const float3 dq = solve ? norm_jac_apply(in.xq, v) : f3(0.f, 0.f, 0.f);
     float irn = rsq(r.x * r.x + r.y * r.y + r.z * r.z);
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
@@ -1110,84 +1127,154 @@ __device__ __forceinline__ void bwd_query(int H, int W, const float* __restrict_
     }
     cx0 = x0;
     cy0 = y0;
+    return dq;
 }
 
-// Largest box of corner pixels a tile accumulates in LDS (12 B per pixel).
-constexpr int kBwdLdsPx = 1536;
+// Largest box of corner pixels a tile accumulates in LDS (24 B per pixel).
+constexpr int kBwdLdsPx = 768;
+// Plane stride (in 64-bit words) of the planar accumulator: five words past
+// the window, so the three components of a pixel sit in different LDS banks.
+constexpr int kBwdPlane = kBwdLdsPx + 5;
+// Accumulator words, rounded up to whole 16-byte stores for the clear.
+constexpr int kBwdAccWords = (3 * kBwdPlane + 1) & ~1;
+
+// The tile's window in LDS sums signed 64-bit fixed-point numbers with integer
+// atomics: LDS float atomics run at a fraction of the integer rate on this
+// chip, and integer sums do not depend on the order of the additions.  The
+// scale 2^S is set per tile from the largest |g| of its corner gradients,
+// g_max < 2^(E+1) with E its unbiased exponent: S = 53 - E, so one term is at
+// most 2^54 and a pixel's sum of at most 256 terms (one per query of the
+// tile) stays below 2^62.  A term keeps every bit of its fp32 value down to
+// 2^-S = 2^(E-53), about 2^-53 of g_max (smaller bits are truncated),
+// subnormal terms included.
+__device__ __forceinline__ long long bwd_to_fixed(float v, int S) {
+    const uint32_t b = __float_as_uint(v);
+    const int e = (int)((b >> 23) & 0xffu);
+    // Significand and exponent; a subnormal (e = 0) has no implicit bit and
+    // the exponent of e = 1.
+    const uint32_t m = (b & 0x7fffffu) | (e ? 0x800000u : 0u);
+    const int sh = max(e, 1) - 150 + S;  // |v| * 2^S = m * 2^sh, sh <= 30
+    const unsigned long long r =
+        sh >= 0 ? (unsigned long long)m << sh : (unsigned long long)(sh > -32 ? m >> -sh : 0u);
+    return (b >> 31) ? -(long long)r : (long long)r;
+}
+__device__ __forceinline__ float bwd_from_fixed(long long t, int S) {
+    return (float)ldexp((double)t, -S);
+}
+
+// Block reduction for a backward tile: the box (lx, hx, ly, hy) of the
+// corner pixels and the largest |g| as float bits (non-negative floats order
+// like their bit patterns).  Ends with a barrier.
+__device__ __forceinline__ void bwd_block_reduce(int& lx, int& hx, int& ly, int& hy, int& mb, int* box) {
+    const int tid = threadIdx.x;
+    lx = wave_min(lx); hx = wave_max(hx); ly = wave_min(ly); hy = wave_max(hy); mb = wave_max(mb);
+    const int wv = tid >> 6;
+    __syncthreads();  // earlier readers of box are done
+    if ((tid & 63) == 0) {
+        box[5 * wv] = lx; box[5 * wv + 1] = hx; box[5 * wv + 2] = ly; box[5 * wv + 3] = hy; box[5 * wv + 4] = mb;
+    }
+    __syncthreads();
+    lx = box[0]; hx = box[1]; ly = box[2]; hy = box[3]; mb = box[4];
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+        lx = min(lx, box[5 * w]); hx = max(hx, box[5 * w + 1]);
+        ly = min(ly, box[5 * w + 2]); hy = max(hy, box[5 * w + 3]); mb = max(mb, box[5 * w + 4]);
+    }
+}
 
 // One 16 x 16 tile of queries.  The tile's scatter into dXii is summed in an
-// LDS window covering every corner its queries touch (LDS float atomics) and
+// LDS window covering every corner its queries touch (fixed point, above) and
 // then added to global memory once per window entry, in row order; a tile
-// whose window exceeds kBwdLdsPx adds each corner to global memory directly.
-// All 256 lanes of the block call this; it ends without a barrier, so a
-// caller that reuses acc for another tile synchronises first.
-__device__ __forceinline__ void bwd_tile(const BwdEdgeArgs& B, int tile, float* acc, int* box) {
+// whose window exceeds kBwdLdsPx, or whose largest |g| is zero, subnormal or
+// not finite, adds each corner to global memory directly.  All 256 lanes of
+// the block call this; it ends without a barrier, so a caller that reuses acc
+// for another tile synchronises first.
+__device__ __forceinline__ void bwd_tile(const BwdEdgeArgs& B, int tile, unsigned long long* acc, int* box) {
     const int H = B.H, W = B.W;
     const int tid = threadIdx.x;
     // The whole accumulator is cleared up front, overlapped with the query
-    // reads; the barriers of block_box order it before the atomics.
-    for (int i = tid; i < 3 * kBwdLdsPx; i += 256) acc[i] = 0.f;
+    // reads; the barriers of the block reduction order it before the atomics.
+    for (int i = tid; i < kBwdAccWords / 2; i += 256)
+        reinterpret_cast<float4*>(acc)[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     const int x = (tile % B.tiles_x) * 16 + (tid & 15), y = (tile / B.tiles_x) * 16 + (tid >> 4);
     const bool inside = x < W && y < H;
     const long n = (long)y * W + x;
+    const bool has_gx = B.grad_xhat != nullptr;
     long cm[4] = {-1, -1, -1, -1};
     float3 gc[4];
-    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
+    int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN, mb = 0;
     int cx0 = 0, cy0 = 0;  // cell of p*: corner c is (cx0 + (c & 1), cy0 + (c >> 1))
     if (inside) {
-        if (!B.valid[n]) {
-            B.dXji[3 * n] = 0.f; B.dXji[3 * n + 1] = 0.f; B.dXji[3 * n + 2] = 0.f;
-        } else {
-            bwd_query(H, W, B.Xii, B.Xji, B.p, B.grad_p, B.grad_xhat, B.dXji, n, cm, gc, cx0, cy0);
+        BwdQueryIn in;
+        const bool valid = ld_global(B.valid, n) != 0;
+        in.px = ld_global(B.p, 2 * n); in.py = ld_global(B.p, 2 * n + 1);
+        in.gp0 = ld_global(B.grad_p, 2 * n); in.gp1 = ld_global(B.grad_p, 2 * n + 1);
+        in.gx = has_gx ? ld_global_point(B.grad_xhat, n) : f3(0.f, 0.f, 0.f);
+        in.xq = ld_global_point(B.Xji, n);
+        float3 dq = f3(0.f, 0.f, 0.f);
+        if (valid) {
+            dq = bwd_query(H, W, B.Xii, has_gx, in, cm, gc, cx0, cy0);
             lx = cx0; hx = cx0 + 1; ly = cy0; hy = cy0 + 1;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                if (cm[c] < 0) continue;
+                const uint32_t m3 = max(max(__float_as_uint(fabsf(gc[c].x)), __float_as_uint(fabsf(gc[c].y))),
+                                        __float_as_uint(fabsf(gc[c].z)));
+                mb = max(mb, (int)m3);
+            }
         }
+        __attribute__((address_space(1))) float* dXji = (__attribute__((address_space(1))) float*)B.dXji;
+        dXji[3 * n] = dq.x; dXji[3 * n + 1] = dq.y; dXji[3 * n + 2] = dq.z;
     }
-    block_box<256>(lx, hx, ly, hy, box);
+    bwd_block_reduce(lx, hx, ly, hy, mb, box);
     const int bw = hx - lx + 1, bh = hy - ly + 1;
     const bool any = hx >= lx;
+    const int ge = mb >> 23;  // biased exponent of the largest |g| (255: inf or NaN)
     float* __restrict__ dXii = B.dXii;
-    if (any && bw * bh <= kBwdLdsPx) {
-        const int cnt = 3 * bw * bh;
+    if (any && ge > 0 && ge < 255 && bw * bh <= kBwdLdsPx) {
+        const int S = 53 - (ge - 127);
+        // Planar accumulator: component k of window pixel j at acc[k * kBwdPlane + j].
+        const int np = bw * bh;
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (cm[c] < 0) continue;
             const int cy = cy0 + (c >> 1), cx = cx0 + (c & 1);
-            float* a = acc + 3 * ((cy - ly) * bw + (cx - lx));
-            atomicAdd(a, gc[c].x);
-            atomicAdd(a + 1, gc[c].y);
-            atomicAdd(a + 2, gc[c].z);
+            unsigned long long* a = acc + (cy - ly) * bw + (cx - lx);
+            atomicAdd(a, (unsigned long long)bwd_to_fixed(gc[c].x, S));
+            atomicAdd(a + kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].y, S));
+            atomicAdd(a + 2 * kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].z, S));
         }
         __syncthreads();
+        // Window entry i (row-major over pixels, then components) to dXii.
         const SmallDiv div_row(3 * bw);
-        for (int i = tid; i < cnt; i += 256) {
-            const float v = acc[i];
-            if (v == 0.f) continue;
+        for (int i = tid; i < 3 * np; i += 256) {
             const int row = div_row(i), col = i - row * 3 * bw;
-            unsafeAtomicAdd(dXii + 3 * ((long)(ly + row) * W + lx) + col, v);
+            const int px = col / 3, k = col - 3 * px;
+            const long long t = (long long)acc[k * kBwdPlane + row * bw + px];
+            if (t == 0) continue;
+            add_global(dXii + 3 * ((long)(ly + row) * W + lx) + col, bwd_from_fixed(t, S));
         }
     } else {
         if (any && tid == 0) count_path(kPathBwdDirect);
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             if (cm[c] < 0) continue;
-            unsafeAtomicAdd(dXii + 3 * cm[c] + 0, gc[c].x);
-            unsafeAtomicAdd(dXii + 3 * cm[c] + 1, gc[c].y);
-            unsafeAtomicAdd(dXii + 3 * cm[c] + 2, gc[c].z);
+            add_global(dXii + 3 * cm[c] + 0, gc[c].x);
+            add_global(dXii + 3 * cm[c] + 1, gc[c].y);
+            add_global(dXii + 3 * cm[c] + 2, gc[c].z);
         }
     }
 }
 
 __global__ void __launch_bounds__(256) bwd_kernel(BwdEdgeArgs B) {
-    __shared__ float acc[3 * kBwdLdsPx];
-    __shared__ int box[4 * 4];
+    __shared__ __align__(16) unsigned long long acc[kBwdAccWords];
+    __shared__ int box[5 * 4];
     bwd_tile(B, blockIdx.x, acc, box);
 }
 
 // Zeroes dXii of every edge of a batched backward (blockIdx.y = edge, grid-
-// stride over blockIdx.x) and resets the work-queue counter.
-__global__ void __launch_bounds__(256) batched_bwd_zero_kernel(const BwdEdgeArgs* __restrict__ E,
-                                                               int32_t* __restrict__ counter) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) counter[0] = 0;
+// stride over blockIdx.x).
+__global__ void __launch_bounds__(256) batched_bwd_zero_kernel(const BwdEdgeArgs* __restrict__ E) {
     const BwdEdgeArgs& B = E[blockIdx.y];
     float* __restrict__ a = B.dXii;
     const long count = 3L * B.H * B.W;
@@ -1212,23 +1299,28 @@ __device__ __forceinline__ int find_bwd_edge(const BwdEdgeArgs* __restrict__ E, 
     return lo;
 }
 
-// Persistent backward over every edge: workgroups pop 16 x 16 tiles from the
-// counter until none is left (every workgroup exits once the counter passes
-// the last tile).  dXii of every edge was zeroed by the previous launch.
+// Backward over every edge with a fixed assignment of tiles to workgroups (the
+// tiles cost about the same, so no queue: a single global counter serialises
+// its atomics at one address, which took most of the launch).  The dispatcher
+// hands workgroups to the XCDs round robin, so workgroup b runs on XCD b mod
+// bands; each XCD takes one contiguous band of tiles, and neighbouring tiles,
+// whose corner windows overlap, share that XCD's L2.  dXii of every edge was
+// zeroed by the previous launch.
 __global__ void __launch_bounds__(256) batched_bwd_kernel(const BwdEdgeArgs* __restrict__ E, int n_edges,
-                                                          int total_tiles, int32_t* __restrict__ counter) {
-    __shared__ float acc[3 * kBwdLdsPx];
-    __shared__ int box[4 * 4];
-    __shared__ int s_tile;
-    for (;;) {
-        if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
-        __syncthreads();  // also: the previous tile's reads of acc are done
-        const int tile = s_tile;
-        __syncthreads();
-        if (tile >= total_tiles) return;
+                                                          int total_tiles) {
+    __shared__ __align__(16) unsigned long long acc[kBwdAccWords];
+    __shared__ int box[5 * 4];
+    const int g = (int)gridDim.x, b = (int)blockIdx.x;
+    const int bands = min(kXcds, g);
+    const int x = b % bands, l = b / bands;
+    const int per = (g - x + bands - 1) / bands;  // workgroups of this band
+    const int band = (total_tiles + bands - 1) / bands;
+    const int lo = x * band, hi = min(lo + band, total_tiles);
+    for (int tile = lo + l; tile < hi; tile += per) {
         const int e = find_bwd_edge(E, n_edges, tile);
         const BwdEdgeArgs B = E[e];
         bwd_tile(B, tile - B.tile_begin, acc, box);
+        __syncthreads();  // the tile's reads of acc are done before the next clears it
     }
 }
 
@@ -1424,14 +1516,14 @@ hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles,
-                              int32_t* counter, int grid, hipStream_t s) {
+hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles, int grid,
+                              hipStream_t s) {
     timer_begin("batched_bwd_zero", s);
     const unsigned zx = min(blocks_for(3 * max_pixels / 4 + 1, 256), 1024u);
-    batched_bwd_zero_kernel<<<dim3(zx, (unsigned)n_edges), 256, 0, s>>>(table, counter);
+    batched_bwd_zero_kernel<<<dim3(zx, (unsigned)n_edges), 256, 0, s>>>(table);
     timer_end(s);
     timer_begin("batched_bwd", s);
-    batched_bwd_kernel<<<grid, 256, 0, s>>>(table, n_edges, total_tiles, counter);
+    batched_bwd_kernel<<<grid, 256, 0, s>>>(table, n_edges, total_tiles);
     timer_end(s);
     return hipGetLastError();
 }

@@ -52,6 +52,36 @@ def test_bwd_matches_oracle_adjoint(m3s, H, W, seed):
     assert (gj[~o["valid"]] == 0).all()
 
 
+@pytest.mark.parametrize("scale", [1e-30, 1e-12, 1.0, 1e12, 1e30])
+def test_bwd_gradient_scales(m3s, scale):
+    """The LDS window sums fixed-point numbers scaled per tile from the tile's
+    largest |g|: incoming gradients from 1e-30 to 1e30 (with a 1e-6 .. 1
+    spread inside the image, so the smallest reach fp32 subnormals at 1e-30)
+    give dL/dX^i_i within 1e-4 of its largest entry, element by element,
+    against the oracle's adjoint on the same p* and mask."""
+    import torch
+    pair = synth.make_pair(48, 64, 506)
+    o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji, K=20, r=pair.r)
+    p32 = o["p"].astype(np.float32)
+    rng = np.random.Generator(np.random.PCG64(507))
+    spread = 10.0 ** rng.uniform(-6, 0, size=(pair.H, pair.W, 1))
+    gp = (rng.normal(size=p32.shape) * spread * scale).astype(np.float32)
+    gx = (rng.normal(size=pair.Xii.shape) * spread * scale).astype(np.float32)
+    print("case bwd scale %g" % scale, flush=True)
+    gi, gj = m3s.match_backward(parity.to_dev(pair.Xii), parity.to_dev(pair.Xji), parity.to_dev(p32),
+                                torch.from_numpy(o["valid"].astype(np.uint8)).cuda(), parity.to_dev(gp),
+                                parity.to_dev(gx))
+    torch.cuda.synchronize()
+    oi, oj = oracle.match_bwd(pair.Xii, pair.Xji, p32.astype(np.float64), o["valid"], gp.astype(np.float64),
+                              gx.astype(np.float64))
+    gi, gj = gi.cpu().numpy(), gj.cpu().numpy()
+    assert np.isfinite(gi).all() and np.isfinite(gj).all()
+    mi = float(np.abs(gi - oi).max() / np.abs(oi).max())
+    mj = float(np.abs(gj - oj).max() / np.abs(oj).max())
+    print(dict(scale=scale, max_rel_dXii=mi, max_rel_dXji=mj))
+    assert mi <= 1e-4 and mj <= 1e-4
+
+
 def test_bwd_deterministic_query_side(m3s):
     pair = synth.make_pair(96, 128, 504)
     a = _fed(m3s, pair, 1)
