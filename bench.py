@@ -469,10 +469,12 @@ def fwd_bwd_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
 
 def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
     """The differentiation workload: 16 edges at 512x384 per step, one batched
-    forward (with xhat; one persistent hipGraph launch) then one batched
-    backward (zero-fill + persistent launch, hipGraph) to dL/dX^i_i and
-    dL/dX^j_i for L = sum over valid matches of |xhat - x|^2 (grad_xhat =
-    2 (xhat - x) on valid queries, from one forward before timing)."""
+    forward (with xhat; one persistent launch) then one batched backward
+    (zero-fill + static-band launch) to dL/dX^i_i and dL/dX^j_i for L = sum
+    over valid matches of |xhat - x|^2 (grad_xhat = 2 (xhat - x) on valid
+    queries, from one forward before timing).  Both calls are timed with the
+    library's hipGraphs (M3S_BATCH_GRAPH) and with eager launches; the step
+    figure is the faster of the two."""
     import torch
     t0 = time.time()
     pairs = [synth.config_pair(5, e) for e in range(16)]
@@ -487,8 +489,11 @@ def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
     s = torch.cuda.Stream()
     fflags = _lib.M3S_BATCH_GRAPH | _lib.M3S_BATCH_AUTOTUNE
 
+    gflag = [_lib.M3S_BATCH_GRAPH]  # submission mode of fwd() and bwd(): GRAPH or 0 (eager)
+
     def fwd():
-        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), fflags, ws.data_ptr(), ws.numel(), s.cuda_stream)
+        fl = _lib.M3S_BATCH_AUTOTUNE | gflag[0]
+        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), fl, ws.data_ptr(), ws.numel(), s.cuda_stream)
         _lib.check(lib, "m3s_match_batched", st)
 
     with torch.cuda.stream(s):
@@ -502,7 +507,7 @@ def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
     wsb = torch.empty(lib.m3s_bwd_batched_workspace_bytes(n), dtype=torch.uint8, device=dev)
 
     def bwd():
-        st = lib.m3s_match_bwd_batched(btable, n, _lib.M3S_BATCH_GRAPH, wsb.data_ptr(), wsb.numel(), s.cuda_stream)
+        st = lib.m3s_match_bwd_batched(btable, n, gflag[0], wsb.data_ptr(), wsb.numel(), s.cuda_stream)
         _lib.check(lib, "m3s_match_bwd_batched", st)
 
     def step():
@@ -510,16 +515,22 @@ def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
         bwd()
 
     steps = max(5, args.steps // 5)
-    with torch.cuda.stream(s):
-        for _ in range(3):
-            step()
-    s.synchronize()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(s):
-        for _ in range(steps):
-            step()
-    s.synchronize()
-    el = (time.perf_counter() - t0) / steps
+    mode_ms = {}
+    for mode, gf in (("graph", _lib.M3S_BATCH_GRAPH), ("eager", 0)):
+        gflag[0] = gf
+        with torch.cuda.stream(s):
+            for _ in range(3):
+                step()
+        s.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            for _ in range(steps):
+                step()
+        s.synchronize()
+        mode_ms[mode] = (time.perf_counter() - t0) / steps * 1e3
+    best_mode = min(mode_ms, key=mode_ms.get)
+    el = mode_ms[best_mode] / 1e3
+    gflag[0] = _lib.M3S_BATCH_GRAPH
     lib.m3s_timing_reset()
     lib.m3s_timing_enable(1)
     with torch.cuda.stream(s):
@@ -558,6 +569,7 @@ def fwd_bwd_batched_leg(m3s, lib, _lib, dev, args):
     res = {"workload": "16 edges 512x384 (W x H), K=10, r=3, confidences: batched forward with xhat then batched "
                        "implicit-adjoint backward, L = sum of squared matched-point distances",
            "edges": n, "queries": queries, "matches_per_s": round(queries / el, 1), "ms_per_step": round(el * 1e3, 4),
+           "submission": best_mode, "ms_by_submission": {k: round(v, 4) for k, v in mode_ms.items()},
            "fwd_graph_ms_events": round(fg, 4), "bwd_graph_ms_events": round(bg, 4),
            "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
            "speedup_vs_per_pair": round(el_p / el, 3),
@@ -589,8 +601,8 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
     s = torch.cuda.Stream()
     flags = _lib.M3S_BATCH_GRAPH | _lib.M3S_BATCH_AUTOTUNE
 
-    def call():
-        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), flags, ws.data_ptr(), ws.numel(), s.cuda_stream)
+    def call(fl=flags):
+        st = lib.m3s_match_batched(table, n, ctypes.byref(prm), fl, ws.data_ptr(), ws.numel(), s.cuda_stream)
         _lib.check(lib, "m3s_match_batched", st)
 
     steps = max(3, args.steps // 10)
@@ -599,12 +611,21 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
             call()
     s.synchronize()
     launch = m3s.last_batched_launch()
-    t0 = time.perf_counter()
-    with torch.cuda.stream(s):
-        for _ in range(steps):
-            call()
-    s.synchronize()
-    el_b = (time.perf_counter() - t0) / steps
+    # Both submission modes, same tuned launch: the library's hipGraph
+    # (M3S_BATCH_GRAPH) and eager launches; the step figure is the faster.
+    mode_ms = {}
+    for mode, fl in (("graph", flags), ("eager", _lib.M3S_BATCH_AUTOTUNE)):
+        with torch.cuda.stream(s):
+            call(fl)
+        s.synchronize()
+        t0 = time.perf_counter()
+        with torch.cuda.stream(s):
+            for _ in range(steps):
+                call(fl)
+        s.synchronize()
+        mode_ms[mode] = (time.perf_counter() - t0) / steps * 1e3
+    best_mode = min(mode_ms, key=mode_ms.get)
+    el_b = mode_ms[best_mode] / 1e3
     lib.m3s_timing_reset()
     lib.m3s_timing_enable(1)
     with torch.cuda.stream(s):
@@ -637,6 +658,7 @@ def batched_leg(m3s, lib, _lib, make_pairs, dev, args, label):
     el_p = (time.perf_counter() - t0) / steps
     res = {"workload": label, "edges": n, "queries": queries,
            "batched_matches_per_s": round(queries / el_b, 1), "batched_ms": round(el_b * 1e3, 4),
+           "submission": best_mode, "ms_by_submission": {k: round(v, 4) for k, v in mode_ms.items()},
            "graph_launch_ms_events": round(graph_ms, 4),
            "per_pair_loop_matches_per_s": round(queries / el_p, 1), "per_pair_loop_ms": round(el_p * 1e3, 4),
            "speedup_vs_per_pair": round(el_p / el_b, 3), "launch": launch,

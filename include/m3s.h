@@ -475,7 +475,8 @@ m3s_status m3s_path_counters(int64_t *counts, int32_t reset);
  * hipEvents around every kernel it launches eagerly (and around each hipGraph
  * launch, as "batched_graph").  m3s_timing_read synchronises on the recorded
  * events and returns, for the kernel `name` ("prep", "fwd", "fill", "bwd",
- * "batched_counter", "batched_prep", "batched_fwd", "batched_graph",
+ * "batched_prep" (with the reset of the work-queue counter), "batched_fwd",
+ * "batched_graph", "batched_bwd_zero", "batched_bwd", "batched_bwd_graph",
  * "track_step" (one Gauss-Newton iteration: the previous system's solve and
  * the accumulation), "track_final", "fuse" (the vectorised launch),
  * "backend_accum", "backend_edge", "backend_solve"), the

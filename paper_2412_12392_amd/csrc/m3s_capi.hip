@@ -325,16 +325,61 @@ m3s_status plan_batched(const m3s_edge* edges, int32_t n, const m3s_params* P, i
     return M3S_OK;
 }
 
-// Rebase the table onto the workspace and copy it (and prep_begin) to the device.
+// Host -> device copies of the edge tables: the table is written into a
+// pinned staging buffer and a small kernel on the stream reads it from there
+// (a DMA copy starts later in the stream than a kernel does, and from
+// pageable memory hipMemcpyAsync may also wait for the stream).  Each device
+// has a ring of kStageSlots slots; a slot is reused only after the kernel
+// that last read it has completed (its event).
+constexpr int kStageSlots = 8;
+struct StageSlot {
+    char* host = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+};
+struct StageRing {
+    StageSlot slot[kStageSlots];
+    int next = 0;
+};
+std::mutex g_stage_mu;
+std::map<int, StageRing> g_stage;
+
+m3s_status staged_copy(void* dst, const void* src, size_t bytes, hipStream_t s, const char* what) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_stage_mu);
+    StageRing& ring = g_stage[dev];
+    StageSlot& sl = ring.slot[ring.next];
+    ring.next = (ring.next + 1) % kStageSlots;
+    if (sl.done && (e = hipEventSynchronize(sl.done)) != hipSuccess) return hip_fail(e, "hipEventSynchronize(staging)");
+    if (sl.cap < bytes) {
+        if (sl.host && (e = hipHostFree(sl.host)) != hipSuccess) return hip_fail(e, "hipHostFree(staging)");
+        sl.host = nullptr;
+        sl.cap = 0;
+        const size_t cap = std::max(bytes, (size_t)4096);
+        if ((e = hipHostMalloc((void**)&sl.host, cap, hipHostMallocDefault)) != hipSuccess)
+            return hip_fail(e, "hipHostMalloc(staging)");
+        sl.cap = cap;
+    }
+    if (!sl.done && (e = hipEventCreateWithFlags(&sl.done, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "hipEventCreate(staging)");
+    std::memcpy(sl.host, src, bytes);
+    if (bytes % 4 || reinterpret_cast<uintptr_t>(dst) % 4) return fail(M3S_ERR_HIP, "%s: unaligned table copy", what);
+    if ((e = m3s::launch_host_copy(dst, sl.host, bytes, s)) != hipSuccess) return hip_fail(e, what);
+    if ((e = hipEventRecord(sl.done, s)) != hipSuccess) return hip_fail(e, "hipEventRecord(staging)");
+    return M3S_OK;
+}
+
+// Rebase the table onto the workspace and copy it and prep_begin to the
+// device in one copy (the workspace bytes [off_table, off_prep + prep size)).
 m3s_status upload_plan(Plan& plan, char* ws, hipStream_t s) {
     for (EdgeArgs& A : plan.table) A.rays = reinterpret_cast<const float4*>(ws + reinterpret_cast<uintptr_t>(A.rays));
-    hipError_t e = hipMemcpyAsync(ws + plan.off_table, plan.table.data(), sizeof(EdgeArgs) * plan.table.size(),
-                                  hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(edge table)");
-    e = hipMemcpyAsync(ws + plan.off_prep, plan.prep_begin.data(), sizeof(int32_t) * plan.prep_begin.size(),
-                       hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(prep table)");
-    return M3S_OK;
+    const size_t tb = sizeof(EdgeArgs) * plan.table.size(), pb = sizeof(int32_t) * plan.prep_begin.size();
+    std::vector<char> image(plan.off_prep - plan.off_table + pb, 0);
+    std::memcpy(image.data(), plan.table.data(), tb);
+    std::memcpy(image.data() + (plan.off_prep - plan.off_table), plan.prep_begin.data(), pb);
+    return staged_copy(ws + plan.off_table, image.data(), image.size(), s, "edge table copy");
 }
 
 hipError_t run_batched(const Plan& plan, char* ws, const Launch& L, hipStream_t s) {
@@ -675,8 +720,10 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
                     "launch; M3S_BATCH_GRAPH gives a library-managed graph instead");
     char* W = reinterpret_cast<char*>(ws);
     auto* dtable = reinterpret_cast<m3s::BwdEdgeArgs*>(W);
-    hipError_t e = hipMemcpyAsync(dtable, table.data(), sizeof(m3s::BwdEdgeArgs) * table.size(), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(backward edge table)");
+    if ((s = staged_copy(dtable, table.data(), sizeof(m3s::BwdEdgeArgs) * table.size(), st,
+                         "hipMemcpyAsync(backward edge table)")) != M3S_OK)
+        return s;
+    hipError_t e = hipSuccess;
     // 32 workgroups per CU, each taking every grid-th tile of its XCD's band
     // (measured on the 16-edge 512x384 workload: 79 us, against 85 us with 12
     // per CU, 91 us with 8 and 81 us with one workgroup per tile).

@@ -42,6 +42,9 @@ constexpr int kMarginMin = 1, kMarginMax = 3, kDefaultMargin = 2, kUnrollMax = 2
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
                           int total_tiles, int32_t* counter, int tile_config, int grid, int margin, int unroll,
                           int levels, bool desc_regs, hipStream_t s);
+// Device copy of `bytes` (a multiple of 4, both pointers 4-byte aligned)
+// from pinned host memory, by a kernel on stream s.
+hipError_t launch_host_copy(void* dst, const void* pinned_src, size_t bytes, hipStream_t s);
 hipError_t launch_stats(const int32_t* idx, const uint8_t* valid, int H, int W, uint32_t* bitmap, int32_t* counts,
                         hipStream_t s);
 // Backward of one edge: 16 x 16 query tiles (tiles_x x tiles_y), tile ids of

@@ -947,10 +947,13 @@ __device__ __forceinline__ int find_edge(const EdgeArgs* __restrict__ E, int n_e
 }
 
 // Prep tiles of edge e start at prep_begin[e] (prep_tiles(H, W) per edge).
+// Also resets the forward's work-queue counter (the forward launch follows in
+// the stream).
 __global__ void __launch_bounds__(256) batched_prep_kernel(const EdgeArgs* __restrict__ E, const int32_t* __restrict__ prep_begin,
-                                                           int n_edges) {
+                                                           int n_edges, int32_t* __restrict__ counter) {
     __shared__ PrepLds S;
     int blk = blockIdx.x;
+    if (blk == 0 && threadIdx.x == 0) counter[0] = 0;
     int lo = 0, hi = n_edges - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -995,9 +998,6 @@ batched_fwd_kernel(const EdgeArgs* __restrict__ E, int n_edges, int total_tiles,
     }
 }
 
-__global__ void __launch_bounds__(64) set_counter_kernel(int32_t* counter) {
-    if (threadIdx.x == 0) counter[0] = 0;
-}
 
 // ---------------------------------------------------------------- backward
 
@@ -1326,6 +1326,15 @@ __global__ void __launch_bounds__(256) batched_bwd_kernel(const BwdEdgeArgs* __r
 
 // ---------------------------------------------------------------- match statistics
 
+// Copies `words` 32-bit words from pinned host memory (read over the bus by
+// the kernel itself) to device memory: for the small edge tables a kernel in
+// the stream starts sooner than a DMA copy.
+__global__ void __launch_bounds__(256) host_copy_kernel(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src,
+                                                        long words) {
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += (long)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 __global__ void __launch_bounds__(256) fill_u32_kernel(uint32_t* __restrict__ a, long count) {
     long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     long stride = (long)gridDim.x * blockDim.x;
@@ -1457,11 +1466,8 @@ static void launch_batched_tile(const EdgeArgs* table, int n_edges, int total_ti
 hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int n_edges, int total_prep_blocks,
                           int total_tiles, int32_t* counter, int tile_config, int grid, int margin, int unroll,
                           int levels, bool desc_regs, hipStream_t s) {
-    timer_begin("batched_counter", s);
-    set_counter_kernel<<<1, 64, 0, s>>>(counter);
-    timer_end(s);
     timer_begin("batched_prep", s);
-    batched_prep_kernel<<<total_prep_blocks, 256, 0, s>>>(table, prep_begin, n_edges);
+    batched_prep_kernel<<<total_prep_blocks, 256, 0, s>>>(table, prep_begin, n_edges, counter);
     timer_end(s);
     timer_begin("batched_fwd", s);
     switch (tile_config) {
@@ -1474,6 +1480,13 @@ hipError_t launch_batched(const EdgeArgs* table, const int32_t* prep_begin, int 
         default: launch_batched_tile<32, 8>(table, n_edges, total_tiles, counter, grid, desc_regs, 0, margin, unroll, levels, s); break;
     }
     timer_end(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_host_copy(void* dst, const void* pinned_src, size_t bytes, hipStream_t s) {
+    const long words = (long)(bytes / 4);
+    host_copy_kernel<<<min(blocks_for(words, 256), 64u), 256, 0, s>>>(static_cast<uint32_t*>(dst),
+                                                                      static_cast<const uint32_t*>(pinned_src), words);
     return hipGetLastError();
 }
 
