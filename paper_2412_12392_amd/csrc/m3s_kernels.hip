@@ -1142,21 +1142,17 @@ constexpr int kBwdAccWords = (3 * kBwdPlane + 1) & ~1;
 // atomics: LDS float atomics run at a fraction of the integer rate on this
 // chip, and integer sums do not depend on the order of the additions.  The
 // scale 2^S is set per tile from the largest |g| of its corner gradients,
-// g_max < 2^(E+1) with E its unbiased exponent: S = 53 - E, so one term is at
-// most 2^54 and a pixel's sum of at most 256 terms (one per query of the
-// tile) stays below 2^62.  A term keeps every bit of its fp32 value down to
-// 2^-S = 2^(E-53), about 2^-53 of g_max (smaller bits are truncated),
-// subnormal terms included.
-__device__ __forceinline__ long long bwd_to_fixed(float v, int S) {
-    const uint32_t b = __float_as_uint(v);
-    const int e = (int)((b >> 23) & 0xffu);
-    // Significand and exponent; a subnormal (e = 0) has no implicit bit and
-    // the exponent of e = 1.
-    const uint32_t m = (b & 0x7fffffu) | (e ? 0x800000u : 0u);
-    const int sh = max(e, 1) - 150 + S;  // |v| * 2^S = m * 2^sh, sh <= 30
-    const unsigned long long r =
-        sh >= 0 ? (unsigned long long)m << sh : (unsigned long long)(sh > -32 ? m >> -sh : 0u);
-    return (b >> 31) ? -(long long)r : (long long)r;
+// g_max < 2^(E+1) with E its unbiased exponent: S = 49 - E, so one term is
+// below 2^50 and a pixel's sum of at most 256 terms (one per query of the
+// tile) stays below 2^58.  A term is |v| 2^S rounded to the nearest integer,
+// an error of at most 2^-(S+1) = 2^(E-50), about 2^-50 of g_max (subnormal
+// terms included: fp32 -> fp64 and the power-of-two scale are exact).  The
+// rounding adds 1.5 * 2^52: a double in [2^52, 2^53) has unit spacing, so the
+// sum rounds to an integer that its low bits hold; subtracting the bit
+// pattern of 1.5 * 2^52 leaves that integer (|v| 2^S < 2^51 is needed).
+__device__ __forceinline__ long long bwd_to_fixed(float v, double scale) {
+    const double t = (double)v * scale + 6755399441055744.0;  // 1.5 * 2^52
+    return __double_as_longlong(t) - 0x4338000000000000ll;
 }
 __device__ __forceinline__ float bwd_from_fixed(long long t, int S) {
     return (float)ldexp((double)t, -S);
@@ -1232,7 +1228,8 @@ __device__ __forceinline__ void bwd_tile(const BwdEdgeArgs& B, int tile, unsigne
     const int ge = mb >> 23;  // biased exponent of the largest |g| (255: inf or NaN)
     float* __restrict__ dXii = B.dXii;
     if (any && ge > 0 && ge < 255 && bw * bh <= kBwdLdsPx) {
-        const int S = 53 - (ge - 127);
+        const int S = 49 - (ge - 127);
+        const double scale = ldexp(1.0, S);
         // Planar accumulator: component k of window pixel j at acc[k * kBwdPlane + j].
         const int np = bw * bh;
 #pragma unroll
@@ -1240,9 +1237,9 @@ __device__ __forceinline__ void bwd_tile(const BwdEdgeArgs& B, int tile, unsigne
             if (cm[c] < 0) continue;
             const int cy = cy0 + (c >> 1), cx = cx0 + (c & 1);
             unsigned long long* a = acc + (cy - ly) * bw + (cx - lx);
-            atomicAdd(a, (unsigned long long)bwd_to_fixed(gc[c].x, S));
-            atomicAdd(a + kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].y, S));
-            atomicAdd(a + 2 * kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].z, S));
+            atomicAdd(a, (unsigned long long)bwd_to_fixed(gc[c].x, scale));
+            atomicAdd(a + kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].y, scale));
+            atomicAdd(a + 2 * kBwdPlane, (unsigned long long)bwd_to_fixed(gc[c].z, scale));
         }
         __syncthreads();
         // Window entry i (row-major over pixels, then components) to dXii.
