@@ -664,6 +664,31 @@ __device__ __forceinline__ void scan16_inside(const uint32_t* q16, const uint4* 
                                               float& run, uint64_t& mask0, uint64_t& mask1) {
     constexpr int S = 2 * R + 1, N = S * S;
     static_assert(N <= 128 && S < 32, "mask width");
+    if constexpr (N <= 64) {
+        // The whole mask in one word: candidate (dy, dx) at bit dy * S + dx,
+        // the row-major order the survivor pass pops in (bit values 1 .. 2^(S-1)
+        // are inline constants).
+        uint64_t m = 0;
+#pragma unroll 1
+        for (int dy = 0; dy < S; ++dy, w += SP * rw) {
+            float sc[S];
+#pragma unroll
+            for (int dx = 0; dx < S; ++dx)
+                sc[dx] = dot16(q16, w[SP * dx], w[SP * dx + CAP], w[SP * dx + 2 * CAP]);
+            float rm = sc[0];
+#pragma unroll
+            for (int dx = 1; dx < S; ++dx) rm = fmaxf(rm, sc[dx]);
+            run = fmaxf(run, rm);
+            const float thr = run - tau;
+            uint32_t rb = 0;
+#pragma unroll
+            for (int dx = 0; dx < S; ++dx) rb |= sc[dx] >= thr ? (1u << dx) : 0u;
+            m |= (uint64_t)rb << (dy * S);
+        }
+        mask0 = m;
+        mask1 = 0;
+        return;
+    }
     uint64_t lo = 0, hi = 0;
 #pragma unroll 1
     for (int dy = 0; dy < S; ++dy, w += SP * rw) {
