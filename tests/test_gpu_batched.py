@@ -60,6 +60,61 @@ def test_batched_equals_per_pair(m3s, graph, autotune):
         assert_same(a, parity.result_numpy(b), "edge %d" % k)
 
 
+def test_back_to_back_calls_without_synchronisation(m3s):
+    """Twelve batched forwards, then twelve batched backwards, issued on one
+    stream without a host synchronisation and alternating three edge sets
+    (eager and graph submission): every call's edge table goes through a ring
+    of eight pinned staging slots, so slots are reused while earlier calls may
+    still be queued. Every call's outputs equal the per-pair launches (the
+    forward bit for bit; the backward's dL/dX^j_i bit for bit and dL/dX^i_i
+    up to the order of the fp32 atomics)."""
+    import torch
+    pairs = mixed_pairs()
+    sets = [pairs[:3], pairs[3:], pairs[1:5]]
+    edges = [edge_inputs(m3s, ps) for ps in sets]
+    refs = [per_pair(m3s, e) for e in edges]
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    outs = []
+    print("case back-to-back batched forwards", flush=True)
+    with torch.cuda.stream(s):
+        for k in range(12):
+            j = k % 3
+            outs.append((j, m3s.match_batched(edges[j], graph=(k % 4 < 2), want_xhat=True, stream=s)))
+    s.synchronize()
+    for k, (j, o) in enumerate(outs):
+        for e, (a, b) in enumerate(zip(refs[j], o)):
+            assert_same(a, parity.result_numpy(b), "call %d edge %d" % (k, e))
+    # Backward over the same edges from the per-pair matches.
+    bins, brefs = [], []
+    for j, es in enumerate(edges):
+        bj, rj = [], []
+        for e, r in zip(es, refs[j]):
+            H, W = e.Xii.shape[:2]
+            rng = np.random.Generator(np.random.PCG64(40 + H + W))
+            p = parity.to_dev(r["p"])
+            v = torch.from_numpy(r["valid"].astype(np.uint8)).cuda()
+            gp = parity.to_dev(rng.normal(size=(H, W, 2)))
+            gx = parity.to_dev(rng.normal(size=(H, W, 3)))
+            bj.append(m3s.BwdEdgeInput(e.Xii, e.Xji, p, v, gp, gx))
+            rj.append(m3s.match_backward(e.Xii, e.Xji, p, v, gp, gx))
+        bins.append(bj)
+        brefs.append(rj)
+    torch.cuda.synchronize()
+    bouts = []
+    print("case back-to-back batched backwards", flush=True)
+    with torch.cuda.stream(s):
+        for k in range(12):
+            j = k % 3
+            bouts.append((j, m3s.match_backward_batched(bins[j], graph=(k % 4 < 2), stream=s)))
+    s.synchronize()
+    for k, (j, o) in enumerate(bouts):
+        for e, ((ri, rj), (gi, gj)) in enumerate(zip(brefs[j], o)):
+            assert torch.equal(rj, gj), (k, e)
+            scale = max(float(ri.abs().max()), 1e-30)
+            assert float((gi - ri).abs().max()) <= 1e-6 * scale, (k, e)
+
+
 def test_graph_replays_with_new_contents(m3s):
     """The same shapes with new inputs replay the cached graph; every replay,
     with eager work and synchronisation between them, equals the eager result."""
