@@ -21,10 +21,13 @@
 //   assemble one workgroup per block row of the reduced 7(N-1) system
 //           (keyframe 0 holds the gauge): the edges' blocks summed in LDS in
 //           edge order, one writer per entry, rows written out whole.
-//   solve   one workgroup: blocked right-looking Cholesky in fp64 with
-//           32 x 32 tiles, the diagonal tile factored one column per
-//           barrier and the panel kept in LDS; the forward substitution
-//           folded into the factorization, the backward one blocked;
+//   solve   one workgroup: the block-sparse Cholesky of the system in
+//           keyframe order over its fill pattern (found once per call), in
+//           LDS, the forward substitution folded into the factorization;
+//           when the fill exceeds LDS, the dense blocked right-looking
+//           Cholesky in fp64 with 32 x 32 tiles instead (the diagonal tile
+//           factored one column group per barrier, the panel kept in LDS, the
+//           backward substitution blocked);
 //           T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  A system that is not positive definite, or a step norm
 //           below step_tol, ends the loop: later launches of the call return
 //           at once.
@@ -49,6 +52,7 @@ constexpr int kSolveThreads = 512;
 constexpr int kVals = kPoseVals;
 constexpr int kStride = 40;         // floats per block partial, doubles per edge system
 constexpr int kMaxDim = 7 * (M3S_MAX_KEYFRAMES - 1);  // largest reduced system
+constexpr int kPatWords = (M3S_MAX_KEYFRAMES + 31) / 32;  // bit words per block row of the pattern
 
 struct BackendArgs {
     int N, HW, E, blocks_per_edge;
@@ -67,11 +71,13 @@ struct BackendArgs {
     double* edge_sys;         // [E*kStride] fp64 relative normal equations per edge
     double* edge_blk;         // [E*kBlk] A^T H_e A (49) and A^T g_e (7) per edge
     float* partials;          // [E*blocks_per_edge*kStride]
-    int32_t* state;           // [0] done flag, [1] applied steps
+    int32_t* state;           // [0] done flag, [1] applied steps, [2] the factor's fill exceeds the sparse solve
     double* stat;             // [0] last step norm
     double* M;                // [np*np] reduced Hessian, factored in place (lower triangle)
     double* rhs;              // [np]
     double* dinv;             // [nt*kTile*kTile] inverses of the diagonal tiles
+    uint32_t* pat;            // [(N-1)*kPatWords] block pattern of the factor L (lower, after fill), bit j of row i
+    int32_t* row_start;       // [N] first slot of each block row of L in row-major block order; [N-1] = blocks
     float* T_out;             // [N*12]
     float* info;              // [4] or null
 };
@@ -88,7 +94,8 @@ __global__ void __launch_bounds__(256) backend_init_kernel(const float* __restri
                                                            double* __restrict__ stat) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < 12 * N) T64[t] = (double)T_in[t];
-    if (t < 2) { state[t] = 0; stat[t] = 0.0; }
+    if (t < 3) state[t] = 0;
+    if (t < 2) stat[t] = 0.0;
 }
 
 __device__ __forceinline__ bool edge_in_range(int ei, int ej, int N) {
@@ -321,8 +328,39 @@ __device__ __forceinline__ void trailing_tile(const BackendArgs& A, PanelPtr P, 
             }
 }
 
-// One workgroup: assemble the reduced system, factor it (blocked Cholesky),
-// solve and update the poses.
+// The end of a solve: pose updates T_WC[k] <- Exp(tau_k) o T_WC[k] for
+// keyframes 1..N-1 from the solution x (LDS), the relative pose of every edge
+// at the new poses (for the next accumulation), and the step norm, which ends
+// the loop below step_tol.  All NT lanes of the workgroup call this.
+template <int NT>
+__device__ __forceinline__ void apply_step(const BackendArgs& A, const double* x, double* red) {
+    const int tid = threadIdx.x;
+    for (int k = 1 + tid; k < A.N; k += NT) {
+        double E[12], Tn[12];
+        sim3_exp(x + 7 * (k - 1), E);
+        sim3_mul(E, A.T64 + 12 * k, Tn);
+        for (int j = 0; j < 12; ++j) A.T64[12 * k + j] = Tn[j];
+    }
+    __syncthreads();
+    for (int e = tid; e < A.E; e += NT) write_relative_pose(A, e);
+    double sq = 0.0;
+    for (int k = tid; k < A.n; k += NT) sq += x[k] * x[k];
+    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
+    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    __syncthreads();
+    if (tid == 0) {
+        double t = 0.0;
+        for (int w = 0; w < NT / 64; ++w) t += red[w];
+        const double step = sqrt(t);
+        A.stat[0] = step;
+        A.state[1] += 1;
+        if (step < A.step_tol) A.state[0] = 1;
+    }
+}
+
+// One workgroup: factor the assembled reduced system (blocked Cholesky),
+// solve and update the poses.  Runs when the block-sparse factor does not fit
+// (state[2]); otherwise backend_sparse_solve_kernel has solved the system.
 __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArgs A) {
     __shared__ double D[kTile][kTile + 1];        // diagonal tile being factored
     __shared__ double Dinv[kTile][kTile + 1];     // its inverse
@@ -332,7 +370,7 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
     __shared__ double red[kSolveThreads / 64];
     __shared__ double part[kTile];
     __shared__ double stage[kStageRows * kPanelStride];  // raw panel rows
-    if (A.state[0]) return;
+    if (A.state[0] || !A.state[2]) return;
     const int tid = threadIdx.x;
     const int n = A.n, np = A.np, nt = np / kTile;
 
@@ -592,29 +630,304 @@ __global__ void __launch_bounds__(kSolveThreads) backend_solve_kernel(BackendArg
         __syncthreads();
     }
 
-    // Pose updates, keyframes 1..N-1, and the step norm.
-    for (int k = 1 + tid; k < A.N; k += kSolveThreads) {
-        double E[12], Tn[12];
-        sim3_exp(x + 7 * (k - 1), E);
-        sim3_mul(E, A.T64 + 12 * k, Tn);
-        for (int j = 0; j < 12; ++j) A.T64[12 * k + j] = Tn[j];
-    }
-    // Relative poses of every edge at the new poses, for the next accumulation.
+    apply_step<kSolveThreads>(A, x, red);
+}
+
+// ---------------------------------------------------------------- block-sparse solve
+//
+// The reduced system has one 7 x 7 block row per keyframe 1..N-1, and block
+// (i, j) is non-zero only where an edge joins keyframes i and j.  In the
+// natural (keyframe) order, Cholesky fills exactly the pairs of later
+// neighbours of every eliminated block (a chain with a few loop closures fills
+// little: the 32-keyframe benchmark graph's factor has 115 blocks of the 496
+// in a dense lower triangle).  backend_pattern_kernel finds that pattern once
+// per call; backend_sparse_solve_kernel factors only those blocks, in LDS,
+// every iteration.  A pattern with more than kSpBlocks blocks takes the dense
+// blocked solve instead (state[2]).
+
+constexpr int kSpThreads = 256;
+constexpr int kSpBlocks = 320;   // blocks of L in LDS: 320 x 392 B = 122.5 KB
+
+// Bits j of word w (of a row's kPatWords words) with lo < j < hi.
+__device__ __forceinline__ uint32_t bits_between(int w, int lo, int hi) {
+    const long b0 = 32L * w;
+    const uint64_t below_hi = hi <= b0 ? 0ull : (hi >= b0 + 32 ? 0xffffffffull : ((1ull << (hi - b0)) - 1ull));
+    const uint64_t above_lo = lo < b0 ? 0xffffffffull : (lo >= b0 + 31 ? 0ull : (0xffffffffull << (lo - b0 + 1)));
+    return (uint32_t)(below_hi & above_lo & 0xffffffffull);
+}
+
+// One workgroup, once per call: the lower block pattern of L after symbolic
+// elimination in keyframe order (diagonal, every in-range edge between
+// keyframes 1..N-1, then for each block column k every pair of its later
+// non-zero rows), the slot of each block row's first block, and whether the
+// factor fits the sparse solve.
+__global__ void __launch_bounds__(kSpThreads) backend_pattern_kernel(BackendArgs A) {
+    __shared__ uint32_t rows[M3S_MAX_KEYFRAMES * kPatWords];
+    __shared__ uint32_t colm[kPatWords];
+    __shared__ int32_t cnt[M3S_MAX_KEYFRAMES];
+    const int nb = A.N - 1, tid = threadIdx.x;
+    for (int i = tid; i < nb * kPatWords; i += kSpThreads) rows[i] = 0u;
     __syncthreads();
-    for (int e = tid; e < A.E; e += kSolveThreads) write_relative_pose(A, e);
-    double sq = 0.0;
-    for (int k = tid; k < n; k += kSolveThreads) sq += x[k] * x[k];
-    for (int o = 32; o > 0; o >>= 1) sq += __shfl_xor(sq, o, 64);
-    if ((tid & 63) == 0) red[tid >> 6] = sq;
+    for (int i = tid; i < nb; i += kSpThreads) atomicOr(&rows[i * kPatWords + (i >> 5)], 1u << (i & 31));
+    for (int e = tid; e < A.E; e += kSpThreads) {
+        const int ei = A.edges[2 * e], ej = A.edges[2 * e + 1];
+        if (!edge_in_range(ei, ej, A.N) || ei == ej || ei == 0 || ej == 0) continue;
+        const int a = max(ei, ej) - 1, b = min(ei, ej) - 1;
+        atomicOr(&rows[a * kPatWords + (b >> 5)], 1u << (b & 31));
+    }
+    __syncthreads();
+    for (int k = 0; k < nb; ++k) {
+        if (tid < kPatWords) colm[tid] = 0u;
+        __syncthreads();
+        for (int i = k + 1 + tid; i < nb; i += kSpThreads)
+            if ((rows[i * kPatWords + (k >> 5)] >> (k & 31)) & 1u) atomicOr(&colm[i >> 5], 1u << (i & 31));
+        __syncthreads();
+        // Row x of the column takes every other row z of the column, k < z < x
+        // (one writer per row).
+        for (int x = k + 1 + tid; x < nb; x += kSpThreads) {
+            if (!((colm[x >> 5] >> (x & 31)) & 1u)) continue;
+            for (int w = 0; w < kPatWords; ++w) rows[x * kPatWords + w] |= colm[w] & bits_between(w, k, x);
+        }
+        __syncthreads();
+    }
+    for (int i = tid; i < nb; i += kSpThreads) {
+        int c = 0;
+        for (int w = 0; w < kPatWords; ++w) {
+            A.pat[i * kPatWords + w] = rows[i * kPatWords + w];
+            c += __popc(rows[i * kPatWords + w]);
+        }
+        cnt[i] = c;
+    }
     __syncthreads();
     if (tid == 0) {
-        double t = 0.0;
-        for (int w = 0; w < kSolveThreads / 64; ++w) t += red[w];
-        const double step = sqrt(t);
-        A.stat[0] = step;
-        A.state[1] += 1;
-        if (step < A.step_tol) A.state[0] = 1;
+        int t = 0;
+        for (int i = 0; i < nb; ++i) {
+            A.row_start[i] = t;
+            t += cnt[i];
+        }
+        A.row_start[nb] = t;
+        A.state[2] = t > kSpBlocks ? 1 : 0;
     }
+}
+
+// One workgroup per iteration: the block-sparse Cholesky of the assembled
+// system over the pattern, the forward substitution folded in, the backward
+// substitution, and the pose updates.  Per block column k, three barriers:
+//   1. every lane factors L_kk = chol(A_kk) and forms L_kk^-1 in registers
+//      (the same operations in every lane, so a block that is not positive
+//      definite stops every lane alike), and y_k <- L_kk^-1 y_k; the later
+//      rows of the column are listed in ascending order;
+//   2. one lane per row a of each listed block: L_xk[a] <- A_xk[a] L_kk^-T,
+//      then y_x[a] -= L_xk[a] . y_k;
+//   3. one lane per entry of each listed pair x >= z: L_xz -= L_xk L_zk^T.
+// L_kk^-1 replaces L_kk for the backward substitution L^T x = y, which one
+// wave runs from the last block row up (x_k = L_kk^-T (y_k - sum_i L_ik^T x_i)).
+__global__ void __launch_bounds__(kSpThreads) backend_sparse_solve_kernel(BackendArgs A) {
+    __shared__ double Lb[kSpBlocks * 49];
+    __shared__ double xs[kMaxDim];
+    __shared__ uint32_t rows[M3S_MAX_KEYFRAMES * kPatWords];
+    __shared__ int32_t rstart[M3S_MAX_KEYFRAMES];
+    __shared__ uint8_t si[kSpBlocks], sj[kSpBlocks];
+    __shared__ int32_t col[M3S_MAX_KEYFRAMES];
+    __shared__ int32_t cslot[M3S_MAX_KEYFRAMES];  // slot of block (col[p], k)
+    __shared__ uint64_t wb[kSpThreads / 64];
+    __shared__ double red[kSpThreads / 64];
+    if (A.state[0] || A.state[2]) return;
+    const int nb = A.N - 1, np = A.np, tid = threadIdx.x;
+    for (int i = tid; i < nb * kPatWords; i += kSpThreads) rows[i] = A.pat[i];
+    for (int i = tid; i <= nb; i += kSpThreads) rstart[i] = A.row_start[i];
+    for (int i = tid; i < A.n; i += kSpThreads) xs[i] = A.rhs[i];
+    __syncthreads();
+    const int nblk = rstart[nb];
+    // Block (si[s], sj[s]) of every slot s, row-major.
+    for (int i = tid; i < nb; i += kSpThreads) {
+        int sl = rstart[i];
+        for (int w = 0; w < kPatWords; ++w) {
+            uint32_t m = rows[i * kPatWords + w];
+            while (m) {
+                const int j = 32 * w + __builtin_ctz(m);
+                m &= m - 1u;
+                si[sl] = (uint8_t)i;
+                sj[sl] = (uint8_t)j;
+                ++sl;
+            }
+        }
+    }
+    __syncthreads();
+    for (int q = tid; q < nblk * 49; q += kSpThreads) {
+        const int sl = q / 49, e = q - 49 * (q / 49), a = e / 7, b = e - 7 * (e / 7);
+        Lb[q] = A.M[(long)(7 * si[sl] + a) * np + 7 * sj[sl] + b];
+    }
+    __syncthreads();
+    // Slot of block (i, j), j <= i, present in the pattern.
+    auto slot = [&](int i, int j) -> int {
+        int sl = rstart[i];
+        for (int w = 0; w < (j >> 5); ++w) sl += __popc(rows[i * kPatWords + w]);
+        return sl + __popc(rows[i * kPatWords + (j >> 5)] & ((1u << (j & 31)) - 1u));
+    };
+    const int wave = tid >> 6, lane = tid & 63;
+    bool failed = false;
+    for (int k = 0; k < nb; ++k) {
+        // 1. L_kk and its inverse in registers (lower triangles), y_k.
+        const double* Dk = Lb + 49 * (rstart[k + 1] - 1);  // the diagonal is row k's last block
+        double L[7][7], Li[7][7], yk[7], isd[7];
+        bool bad = false;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            double d = Dk[7 * j + j];
+#pragma unroll
+            for (int m = 0; m < j; ++m) d -= L[j][m] * L[j][m];
+            bad = bad || !(d > 0.0) || !isfinite(d);
+            // 1/sqrt(d): hardware estimate and two Newton steps (no fp64
+            // division or square root in the chain).
+            double is = __builtin_amdgcn_rsq(d);
+            is = is * fma(-0.5 * d * is, is, 1.5);
+            is = is * fma(-0.5 * d * is, is, 1.5);
+            L[j][j] = d * is;
+            isd[j] = is;
+#pragma unroll
+            for (int i = j + 1; i < 7; ++i) {
+                double v = Dk[7 * i + j];
+#pragma unroll
+                for (int m = 0; m < j; ++m) v -= L[i][m] * L[j][m];
+                L[i][j] = v * is;
+            }
+        }
+        if (bad) {
+            failed = true;
+            break;
+        }
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            Li[i][i] = isd[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) {
+                double v = 0.0;
+#pragma unroll
+                for (int m = j; m < i; ++m) v += L[i][m] * Li[m][j];
+                Li[i][j] = -v * Li[i][i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 7; ++i) {
+            double v = 0.0;
+#pragma unroll
+            for (int m = 0; m <= i; ++m) v += Li[i][m] * xs[7 * k + m];
+            yk[i] = v;
+        }
+        // Later rows x of column k, ascending: one ballot per wave.
+        const int xr = tid;
+        const bool in_col = xr > k && xr < nb && ((rows[xr * kPatWords + (k >> 5)] >> (k & 31)) & 1u);
+        const uint64_t bal = __ballot(in_col);
+        if (lane == 0) wb[wave] = bal;
+        __syncthreads();
+        int ncol = 0, before = 0;
+#pragma unroll
+        for (int w = 0; w < kSpThreads / 64; ++w) {
+            const int c = __popcll(wb[w]);
+            if (w < wave) before += c;
+            ncol += c;
+        }
+        if (in_col) {
+            const int pos = before + __popcll(bal & ((1ull << lane) - 1ull));
+            col[pos] = xr;
+            cslot[pos] = slot(xr, k);
+        }
+        // The diagonal slot keeps L_kk^-1 (its lower triangle, the only part
+        // the backward substitution reads) and y_k is final: one lane writes
+        // both from registers with fixed offsets.
+        if (tid == 0) {
+            double* dk = Lb + 49 * (rstart[k + 1] - 1);
+#pragma unroll
+            for (int i = 0; i < 7; ++i) {
+#pragma unroll
+                for (int j = 0; j <= i; ++j) dk[7 * i + j] = Li[i][j];
+                xs[7 * k + i] = yk[i];
+            }
+        }
+        __syncthreads();
+        // 2. Panel rows and the forward substitution.
+        for (int q = tid; q < 7 * ncol; q += kSpThreads) {
+            const int x = col[q / 7], a = q - 7 * (q / 7);
+            double* row = Lb + 49 * cslot[q / 7] + 7 * a;
+            double r[7], out[7];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) r[c] = row[c];
+            double acc = 0.0;
+#pragma unroll
+            for (int b = 0; b < 7; ++b) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = 0; c <= b; ++c) v += r[c] * Li[b][c];
+                out[b] = v;
+                acc += v * yk[b];
+            }
+#pragma unroll
+            for (int b = 0; b < 7; ++b) row[b] = out[b];
+            xs[7 * x + a] -= acc;
+        }
+        __syncthreads();
+        // 3. Trailing update of every listed pair x >= z.
+        const int npair = ncol * (ncol + 1) / 2;
+        for (int q = tid; q < 49 * npair; q += kSpThreads) {
+            const int p = q / 49, e = q - 49 * (q / 49), a = e / 7, b = e - 7 * (e / 7);
+            int xi = 0;
+            while ((xi + 1) * (xi + 2) / 2 <= p) ++xi;
+            const int zi = p - xi * (xi + 1) / 2;
+            const int x = col[xi], z = col[zi];
+            const double* lx = Lb + 49 * cslot[xi] + 7 * a;
+            const double* lz = Lb + 49 * cslot[zi] + 7 * b;
+            double v = 0.0;
+#pragma unroll
+            for (int c = 0; c < 7; ++c) v += lx[c] * lz[c];
+            Lb[49 * slot(x, z) + e] -= v;
+        }
+        __syncthreads();
+    }
+    if (failed) {
+        if (tid == 0) A.state[0] = 1;
+        return;
+    }
+    // Backward substitution in wave 0, from the last block row up: every lane
+    // forms x_k = L_kk^-T y_k (y_k has taken every later row's share), then
+    // one lane per off-diagonal block (k, j) of row k (its slots are
+    // consecutive) takes y_j -= L_kj^T x_k.  Row k is the only writer of those
+    // y_j in its step, and the wave's LDS accesses complete in order.
+    if (wave == 0) {
+        for (int k = nb - 1; k >= 0; --k) {
+            const int s0 = rstart[k], sd = rstart[k + 1] - 1;  // first and diagonal slot of row k
+            const double* inv = Lb + 49 * sd;
+            double yv[7], xk[7];
+#pragma unroll
+            for (int c = 0; c < 7; ++c) yv[c] = xs[7 * k + c];
+#pragma unroll
+            for (int b = 0; b < 7; ++b) {
+                double v = 0.0;
+#pragma unroll
+                for (int c = b; c < 7; ++c) v += inv[7 * c + b] * yv[c];
+                xk[b] = v;
+            }
+            if (lane < 7) {
+                double v = 0.0;
+#pragma unroll
+                for (int b = 0; b < 7; ++b) if (b == lane) v = xk[b];
+                xs[7 * k + lane] = v;
+            }
+            for (int sl = s0 + lane; sl < sd; sl += 64) {
+                const int j = sj[sl];
+                const double* blk = Lb + 49 * sl;
+#pragma unroll
+                for (int c = 0; c < 7; ++c) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int a = 0; a < 7; ++a) v += blk[7 * a + c] * xk[a];
+                    xs[7 * j + c] -= v;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    apply_step<kSpThreads>(A, xs, red);
 }
 
 __global__ void __launch_bounds__(256) backend_finish_kernel(BackendArgs A) {
@@ -636,7 +949,7 @@ __global__ void __launch_bounds__(256) backend_finish_kernel(BackendArgs A) {
 
 // Workspace layout.
 struct BackendLayout {
-    size_t T64, Trel, edge_sys, edge_blk, partials, state, stat, M, rhs, dinv, total;
+    size_t T64, Trel, edge_sys, edge_blk, partials, state, stat, M, rhs, dinv, pat, row_start, total;
 };
 
 int padded_dim(int N) { return (7 * (N - 1) + kTile - 1) / kTile * kTile; }
@@ -652,11 +965,13 @@ BackendLayout backend_layout(int N, int HW, int E) {
     L.edge_sys = o; o = al(o + sizeof(double) * kStride * E);
     L.edge_blk = o; o = al(o + sizeof(double) * kBlk * E);
     L.partials = o; o = al(o + sizeof(float) * kStride * (size_t)bpe * E);
-    L.state = o;    o = al(o + sizeof(int32_t) * 2);
+    L.state = o;    o = al(o + sizeof(int32_t) * 3);
     L.stat = o;     o = al(o + sizeof(double) * 2);
     L.M = o;        o = al(o + sizeof(double) * np * np);
     L.rhs = o;      o = al(o + sizeof(double) * np);
     L.dinv = o;     o = al(o + sizeof(double) * np * kTile);
+    L.pat = o;      o = al(o + sizeof(uint32_t) * kPatWords * (size_t)N);
+    L.row_start = o; o = al(o + sizeof(int32_t) * (size_t)N);
     L.total = o;
     return L;
 }
@@ -695,11 +1010,14 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
     A.M = reinterpret_cast<double*>(w + L.M);
     A.rhs = reinterpret_cast<double*>(w + L.rhs);
     A.dinv = reinterpret_cast<double*>(w + L.dinv);
+    A.pat = reinterpret_cast<uint32_t*>(w + L.pat);
+    A.row_start = reinterpret_cast<int32_t*>(w + L.row_start);
     A.T_out = T;
     A.info = info;
     const dim3 grid(A.blocks_per_edge, E);
     backend_init_kernel<<<(12 * N + 255) / 256, 256, 0, s>>>(T, A.T64, N, A.state, A.stat);
     backend_relpose_kernel<<<(E + 255) / 256, 256, 0, s>>>(A);
+    backend_pattern_kernel<<<1, kSpThreads, 0, s>>>(A);
     for (int it = 0; it <= iters; ++it) {
         const int final_pass = it == iters ? 1 : 0;
         timer_begin("backend_accum", s);
@@ -711,6 +1029,7 @@ hipError_t launch_backend(int N, int HW, int E, const float* Xc, const float* Q,
         if (final_pass) break;
         timer_begin("backend_solve", s);
         backend_assemble_kernel<<<N, kAsmThreads, 0, s>>>(A);
+        backend_sparse_solve_kernel<<<1, kSpThreads, 0, s>>>(A);
         backend_solve_kernel<<<1, kSolveThreads, 0, s>>>(A);
         timer_end(s);
     }

@@ -77,11 +77,38 @@ CASES = [
     ("least_squares", (4, 24, 32, 6), dict(noise=1e-3, loops=1), dict(huber=float("inf"))),
     ("full_512x384", (4, 384, 512, 7), dict(noise=1e-3, outlier_frac=0.05, scramble=False, loops=1),
      dict(iters=3)),
-    # Reduced systems larger than the LDS panel (the factorisation reads the panel from memory),
-    # up to the largest keyframe count.
+    # A 40-keyframe graph with 8 loop closures: 287 factor blocks, the block-sparse solve near
+    # its LDS capacity (320).
+    ("loops_40", (40, 8, 12, 13), dict(noise=1e-3, loops=8), dict(iters=4)),
+    # Fill above the sparse capacity (379 and 377 blocks): the dense blocked solve, with reduced
+    # systems larger than its LDS panel (the factorisation reads the panel from memory), up to
+    # the largest keyframe count.
     ("long_chain_80", (80, 8, 12, 11), dict(loops=4), dict(iters=5)),
     ("max_keyframes_128", (128, 6, 8, 12), dict(loops=2), dict(iters=4)),
 ]
+
+# Which solve each case takes: the factor's block count in keyframe order (the
+# symbolic elimination the pattern kernel runs) against the sparse capacity.
+SPARSE_CAPACITY = 320
+EXPECTED_SOLVE = {"loops_40": "sparse", "long_chain_80": "dense", "max_keyframes_128": "dense"}
+
+
+def factor_blocks(N, edges):
+    """Blocks of the lower Cholesky factor of the reduced system (keyframe 0
+    held) in keyframe order: the diagonal, every edge between keyframes 1..N-1,
+    and for each eliminated block column every pair of its later rows."""
+    nb = N - 1
+    rows = [1 << i for i in range(nb)]
+    for i, j in np.asarray(edges).tolist():
+        if 0 < i < N and 0 < j < N and i != j:
+            a, b = max(i, j) - 1, min(i, j) - 1
+            rows[a] |= 1 << b
+    for k in range(nb):
+        col = [x for x in range(k + 1, nb) if rows[x] >> k & 1]
+        for u in range(len(col)):
+            for v in range(u):
+                rows[col[u]] |= 1 << col[v]
+    return sum(bin(r).count("1") for r in rows)
 
 
 @pytest.mark.parametrize("name,shape,gen,solve", CASES, ids=[c[0] for c in CASES])
@@ -89,6 +116,11 @@ def test_backend_matches_oracle(name, shape, gen, solve):
     N, H, W, seed = shape
     print("backend case", name, N, H, W, seed, flush=True)
     bp = synth.make_backend(N, H, W, seed, **gen)
+    blocks = factor_blocks(N, bp.edges)
+    path = "sparse" if blocks <= SPARSE_CAPACITY else "dense"
+    print("factor blocks", blocks, "->", path, "solve", flush=True)
+    if name in EXPECTED_SOLVE:
+        assert path == EXPECTED_SOLVE[name], (name, blocks)
     T, info, T_ref, ref = _run(bp, **solve)
     assert np.array_equal(T[0], np.asarray(bp.T_init[0], np.float32)), "keyframe 0 moved"
     _check_poses(T, T_ref)
