@@ -318,9 +318,10 @@ m3s_status m3s_fuse_pointmap(const m3s_fuse_problem *prob, const float *T, void 
  *   distance residual |T_ij Xc[j][n]| - |Xc[i][m]|         weight q / sigma_dist^2
  * with T_ij = T_WC[i]^-1 T_WC[j], Huber weights as in m3s_track_pose, and the
  * world-pose Jacobians -J Ad(T_WC[i]^-1), J Ad(T_WC[i]^-1) (Supp. A).  Keyframe 0
- * holds the gauge.  The reduced 7(N-1) system is solved by a dense Cholesky
- * factorisation in fp64 (the same solution as the paper's sparse one) and every
- * other pose takes T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  The loop ends after
+ * holds the gauge.  The reduced 7(N-1) system is solved by a block-sparse
+ * Cholesky factorisation in fp64 over 7 x 7 blocks in keyframe order (a dense
+ * one when the factor's fill exceeds 320 blocks; the same solution either way)
+ * and every other pose takes T_WC[k] <- Exp(tau_k) o T_WC[k] (Eq. 1).  The loop ends after
  * `iters` steps, once a step norm |tau| falls below step_tol (that step is
  * applied), or when the system is not positive definite (no step applied).
  * Residuals are evaluated in fp32 and summed per workgroup in fp32, per edge
@@ -361,10 +362,12 @@ size_t m3s_backend_workspace_bytes(int32_t N, int32_t H, int32_t W, int32_t E);
  *         used there, steps applied, norm of the last applied step}.
  *   ws    256-byte aligned DEVICE memory of >= m3s_backend_workspace_bytes();
  *         calls that share a workspace must not overlap.
- * 4 + 3 * iters launches on `stream`, no host synchronisation (a graph can
+ * 6 + 5 * iters launches on `stream`, no host synchronisation (a graph can
  * capture the call); after the loop has ended, the remaining launches return
- * at once.  The solve runs in one workgroup: a blocked Cholesky factorisation
- * of the dense reduced system (32 x 32 tiles).
+ * at once.  The solve runs in one workgroup: the block pattern of the factor
+ * is found once per call, and each iteration factors the pattern's blocks in
+ * LDS, or, when they do not fit, factors the dense reduced system blocked in
+ * 32 x 32 tiles.
  */
 m3s_status m3s_backend_gn(const m3s_backend_problem *prob, const m3s_backend_params *params, float *T_WC,
                           float *info, void *ws, size_t ws_bytes, void *stream);
