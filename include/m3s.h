@@ -151,7 +151,7 @@ m3s_status m3s_match_fwd(const m3s_pair *pair, const m3s_params *params, const m
  * callers that cannot allocate device memory (code under hipGraph stream
  * capture, tight serving loops, harnesses that forbid hipMalloc).  The ray
  * records live in a static device array of the library, one copy per GPU,
- * sized for M3S_NOALLOC_MAX_PIXELS pixels (48 B each: 12 MiB) and held until
+ * sized for M3S_NOALLOC_MAX_PIXELS pixels (36 B each: 9 MiB) and held until
  * the process ends; the call itself allocates nothing (no hipMalloc, no
  * hipFree, no events even with timing enabled).  H * W above the limit
  * returns M3S_ERR_SHAPE.  Every call on one GPU shares that array: calls

@@ -142,7 +142,7 @@ m3s::BwdEdgeArgs make_bwd_edge(int32_t H, int32_t W, const float* Xii, const flo
     return B;
 }
 
-size_t ray_bytes(int32_t H, int32_t W) { return align_up((size_t)H * W * m3s::kRecF4 * sizeof(float4)); }
+size_t ray_bytes(int32_t H, int32_t W) { return align_up((size_t)H * W * m3s::kRecBytes); }
 
 // Descriptors go to registers with 16-byte loads when D == 24 and both arrays are 16-byte aligned.
 bool desc_in_regs(const m3s_pair* A) {
@@ -540,7 +540,7 @@ m3s_status drain_timings() {
 // symbol.  The device address of each GPU's copy is looked up once per
 // device with hipGetSymbolAddress, with that device current, and kept here.
 namespace m3s {
-__device__ __align__(256) float4 scratch[(size_t)M3S_NOALLOC_MAX_PIXELS * kRecF4];
+__device__ __align__(256) float4 scratch[(size_t)M3S_NOALLOC_MAX_PIXELS * kRecBytes / sizeof(float4)];
 }  // namespace m3s
 
 namespace {

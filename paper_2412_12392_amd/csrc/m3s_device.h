@@ -32,10 +32,18 @@ struct EdgeArgs {
     float* xhat;                   // may be nullptr
 };
 
-// Ray record of reference pixel m: {R.x, R.y, R.z, Gx.x}, {Gx.y, Gx.z, Gy.x, Gy.y},
-// {Gy.z, 0, 0, 0}: the unit ray R = X/|X| (zero for a non-finite or zero point)
-// and its central-difference gradients along x and y (one-sided at the border).
-constexpr int kRecF4 = 3;
+// Ray record of reference pixel m: the unit ray R = X/|X| (zero for a
+// non-finite or zero point) and its central-difference gradients Gx, Gy along
+// x and y (one-sided at the border), nine floats held in three planes of the
+// ray image, one after the other: P0 = {R.x, R.y, R.z, Gx.x} and
+// P1 = {Gx.y, Gx.z, Gy.x, Gy.y} (a float4 per pixel each), then Z = Gy.z (a
+// float per pixel).  36 bytes per pixel, no padding; each plane is written and
+// read in contiguous rows.
+constexpr int kRecP4 = 2;            // float4 planes
+constexpr uint32_t kRecBytes = 36;   // bytes per pixel over the three planes
+
+// Byte offset of plane Z in a ray image of H x W pixels (plane P1 is at half of it).
+__device__ __forceinline__ uint32_t ray_zoff(int H, int W) { return (uint32_t)H * (uint32_t)W * 32u; }
 
 __device__ __forceinline__ float3 f3(float x, float y, float z) { return make_float3(x, y, z); }
 
@@ -70,21 +78,26 @@ struct Sample {
 
 // Ray records are read with buffer loads: one resource descriptor (base,
 // byte size) in scalar registers, a 32-bit byte offset per lane, immediate
-// offsets for the three float4s of a record.  Reads past the size return 0.
-// The host keeps 48 * H * W below 2^32.
+// offsets within a record.  Reads past the size return 0.  The host keeps
+// 36 * H * W below 2^32.
 using RayBuf = __amdgpu_buffer_rsrc_t;
 
 __device__ __forceinline__ RayBuf ray_buffer(const float4* rec, int H, int W) {
     return __builtin_amdgcn_make_buffer_rsrc(const_cast<float4*>(rec), (short)0,
-                                             (int)((uint32_t)H * (uint32_t)W * (uint32_t)(kRecF4 * 16)), 0x00020000);
+                                             (int)((uint32_t)H * (uint32_t)W * kRecBytes), 0x00020000);
 }
 
 __device__ __forceinline__ float4 rec_load(RayBuf rb, uint32_t byte_off) {
     return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(rb, byte_off, 0, 0));
 }
 
+__device__ __forceinline__ float rec_load1(RayBuf rb, uint32_t byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rb, byte_off, 0, 0));
+}
+
 // Ray error of Eq. 2 from the four ray records around p (A = (x0, y0),
-// B = (x0+1, y0), C = (x0, y0+1), D = (x0+1, y0+1)) with bilinear weights a, b.
+// B = (x0+1, y0), C = (x0, y0+1), D = (x0+1, y0+1): plane P in A..D, plane Z
+// in z[0..3] in the same order) with bilinear weights a, b.
 // FULL = false evaluates the cost only (the last trial of the LM needs nothing
 // else).  A degenerate sample (interpolated ray zero or not finite) costs +inf;
 // its Jacobian blocks are then not meaningful, and they are never used: a
@@ -92,7 +105,7 @@ __device__ __forceinline__ float4 rec_load(RayBuf rb, uint32_t byte_off) {
 // gives a non-finite step, which the LM rejects without moving.
 template <bool FULL>
 __device__ __forceinline__ void ray_error_from(const float4* A, const float4* B, const float4* C, const float4* D,
-                                               float a, float b, float3 t, Sample& s) {
+                                               const float* z, float a, float b, float3 t, Sample& s) {
     float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
 #define M3S_BL(i, c) (w00 * A[i].c + w10 * B[i].c + w01 * C[i].c + w11 * D[i].c)
     float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
@@ -104,7 +117,7 @@ __device__ __forceinline__ void ray_error_from(const float4* A, const float4* B,
     s.c = ok ? e0 * e0 + e1 * e1 + e2 * e2 : INFINITY;
     if constexpr (FULL) {
         float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
-        float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = M3S_BL(2, x);
+        float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = w00 * z[0] + w10 * z[1] + w01 * z[2] + w11 * z[3];
         float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
         float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
         // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
@@ -123,42 +136,61 @@ __device__ __forceinline__ void ray_error_from(const float4* A, const float4* B,
 struct GlobalRays {
     RayBuf rb;
     int W;
-    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D) const {
-        const uint32_t rs = (uint32_t)kRecF4 * 16u;
-        const uint32_t o00 = ((uint32_t)y0 * (uint32_t)W + (uint32_t)x0) * rs;
-        const uint32_t o10 = o00 + rs, o01 = o00 + (uint32_t)W * rs, o11 = o01 + rs;
-#pragma unroll
-        for (int j = 0; j < kRecF4; ++j) {
-            A[j] = rec_load(rb, o00 + 16 * j);
-            B[j] = rec_load(rb, o10 + 16 * j);
-            C[j] = rec_load(rb, o01 + 16 * j);
-            D[j] = rec_load(rb, o11 + 16 * j);
-        }
+    uint32_t zoff;  // byte offset of plane Z (twice that of plane P1)
+    __device__ __forceinline__ GlobalRays(const float4* rays, int H, int W_)
+        : rb(ray_buffer(rays, H, W_)), W(W_), zoff(ray_zoff(H, W_)) {}
+    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D,
+                                          float* z) const {
+        const uint32_t m00 = (uint32_t)y0 * (uint32_t)W + (uint32_t)x0, m01 = m00 + (uint32_t)W;
+        const uint32_t o00 = m00 * 16u, o01 = m01 * 16u, p1 = zoff >> 1;
+        A[0] = rec_load(rb, o00);
+        B[0] = rec_load(rb, o00 + 16);
+        C[0] = rec_load(rb, o01);
+        D[0] = rec_load(rb, o01 + 16);
+        A[1] = rec_load(rb, p1 + o00);
+        B[1] = rec_load(rb, p1 + o00 + 16);
+        C[1] = rec_load(rb, p1 + o01);
+        D[1] = rec_load(rb, p1 + o01 + 16);
+        z[0] = rec_load1(rb, zoff + 4 * m00);
+        z[1] = rec_load1(rb, zoff + 4 * m00 + 4);
+        z[2] = rec_load1(rb, zoff + 4 * m01);
+        z[3] = rec_load1(rb, zoff + 4 * m01 + 4);
     }
 };
 
-// Ray records of a window [rx0, rx0 + rw) x [ry0, ry0 + rh) staged in LDS
-// (record of window pixel k at lds[3k .. 3k+2]); cells outside the window
-// are read from global memory.  Same values either way.
+// Ray records of a window [rx0, rx0 + rw) x [ry0, ry0 + rh) staged in LDS:
+// planes P0 and P1 of window pixel k at lds[2k] and lds[2k + 1], plane Z at
+// ldz[k] (ldz = lds + 2 rw rh); cells outside the window are read from global
+// memory.  Same values either way.
 struct WindowRays {
     const float4* lds;
+    const float* ldz;
     int rx0, ry0, rw, rh;
     GlobalRays g;
-    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D) const {
+    __device__ __forceinline__ WindowRays(const float4* l, int x, int y, int w, int h, const GlobalRays& g_)
+        : lds(l), ldz(reinterpret_cast<const float*>(l + kRecP4 * w * h)), rx0(x), ry0(y), rw(w), rh(h), g(g_) {}
+    __device__ __forceinline__ void fetch(int x0, int y0, float4* A, float4* B, float4* C, float4* D,
+                                          float* z) const {
         const int lx = x0 - rx0, ly = y0 - ry0;
         // 0 <= lx <= rw - 2 and 0 <= ly <= rh - 2 (the whole cell in the window).
         if ((uint32_t)lx < (uint32_t)(rw - 1) && (uint32_t)ly < (uint32_t)(rh - 1)) {
-            const float4* a = lds + (uint32_t)(kRecF4 * (ly * rw + lx));
-            const float4* c = a + kRecF4 * rw;
+            const uint32_t k = (uint32_t)(ly * rw + lx);
+            const float4* a = lds + kRecP4 * k;
+            const float4* c = a + kRecP4 * rw;
 #pragma unroll
-            for (int j = 0; j < kRecF4; ++j) {
+            for (int j = 0; j < kRecP4; ++j) {
                 A[j] = a[j];
-                B[j] = a[kRecF4 + j];
+                B[j] = a[kRecP4 + j];
                 C[j] = c[j];
-                D[j] = c[kRecF4 + j];
+                D[j] = c[kRecP4 + j];
             }
+            const float* zz = ldz + k;
+            z[0] = zz[0];
+            z[1] = zz[1];
+            z[2] = zz[rw];
+            z[3] = zz[rw + 1];
         } else {
-            g.fetch(x0, y0, A, B, C, D);
+            g.fetch(x0, y0, A, B, C, D, z);
         }
     }
 };
@@ -171,9 +203,10 @@ __device__ __forceinline__ void sample_ray_error(const Src& src, float xcell, fl
                                                  float3 t, Sample& s) {
     const float fx0 = fminf(floorf(px), xcell), fy0 = fminf(floorf(py), ycell);
     const float a = px - fx0, b = py - fy0;
-    float4 A[kRecF4], B[kRecF4], C[kRecF4], D[kRecF4];
-    src.fetch((int)fx0, (int)fy0, A, B, C, D);
-    ray_error_from<FULL>(A, B, C, D, a, b, t, s);
+    float4 A[kRecP4], B[kRecP4], C[kRecP4], D[kRecP4];
+    float z[4];
+    src.fetch((int)fx0, (int)fy0, A, B, C, D, z);
+    ray_error_from<FULL>(A, B, C, D, z, a, b, t, s);
 }
 
 __device__ __forceinline__ float clampf(float v, float lo, float hi) { return __builtin_amdgcn_fmed3f(v, lo, hi); }
@@ -261,7 +294,7 @@ __device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 
 // K Levenberg-Marquardt iterations from (px, py) reading global memory; returns the final cost.
 __device__ __forceinline__ float lm_project(const float4* __restrict__ rays, int H, int W, int K, float lambda0,
                                             float3 t, float& px, float& py) {
-    const GlobalRays g{ray_buffer(rays, H, W), W};
+    const GlobalRays g(rays, H, W);
     LMState st;
     st.px = px; st.py = py;
     lm_start(g, H, W, lambda0, t, st);

@@ -30,7 +30,7 @@ void timer_begin(const char* name, hipStream_t s);
 void timer_end(hipStream_t s);
 
 // Ray-record prep: one workgroup of 256 lanes per kPrepTX x kPrepTY pixels.
-constexpr int kPrepTX = 64, kPrepTY = 4;
+constexpr int kPrepTX = 32, kPrepTY = 8;
 inline int64_t prep_tiles(int H, int W) {
     return (int64_t)((W + kPrepTX - 1) / kPrepTX) * (int64_t)((H + kPrepTY - 1) / kPrepTY);
 }

@@ -32,16 +32,17 @@ typedef float f4v_t __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ void store_nt(float4* p, float4 v) {
     __builtin_nontemporal_store(__builtin_bit_cast(f4v_t, v), reinterpret_cast<f4v_t*>(p));
 }
+__device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 
 // One prep tile of kPrepTX x kPrepTY pixels per workgroup of 256 lanes.  The
 // tile and a one-pixel halo of X (edge-replicated, which gives the one-sided
 // differences at the image border) are read with coalesced loads, each
-// pixel's unit ray is computed once in LDS, and the records are written back
-// as contiguous float4s.  Same arithmetic per pixel as reading the five points
-// directly: r, rx-, rx+, ry-, ry+ and (r+ - r-) / (x+ - x-).
+// pixel's unit ray is computed once in LDS, and each lane writes its pixels'
+// records to the three planes (a wave writes contiguous rows of each).  Same
+// arithmetic per pixel as reading the five points directly: r, rx-, rx+, ry-,
+// ry+ and (r+ - r-) / (x+ - x-).
 struct PrepLds {
     float ray[(kPrepTY + 2) * (kPrepTX + 2) * 3];
-    float4 rec[kPrepTY * kPrepTX * kRecF4];
 };
 
 __device__ __forceinline__ void prep_tile(const float* __restrict__ X, float4* __restrict__ rec, int H, int W,
@@ -61,8 +62,8 @@ __device__ __forceinline__ void prep_tile(const float* __restrict__ X, float4* _
         S.ray[3 * i] = r.x; S.ray[3 * i + 1] = r.y; S.ray[3 * i + 2] = r.z;
     }
     __syncthreads();
-    {
-        const int lx = tid % kPrepTX, ly = tid / kPrepTX;
+    for (int pix = tid; pix < kPrepTX * kPrepTY; pix += 256) {
+        const int lx = pix % kPrepTX, ly = pix / kPrepTX;
         const int x = x0 + lx, y = y0 + ly;
         const int xm = max(x - 1, 0), xp = min(x + 1, W - 1);
         const int ym = max(y - 1, 0), yp = min(y + 1, H - 1);
@@ -76,17 +77,11 @@ __device__ __forceinline__ void prep_tile(const float* __restrict__ X, float4* _
             float sx = 1.0f / (float)(xp - xm), sy = 1.0f / (float)(yp - ym);
             float3 gx = f3((rxp.x - rxm.x) * sx, (rxp.y - rxm.y) * sx, (rxp.z - rxm.z) * sx);
             float3 gy = f3((ryp.x - rym.x) * sy, (ryp.y - rym.y) * sy, (ryp.z - rym.z) * sy);
-            float4* o = S.rec + kRecF4 * tid;
-            o[0] = make_float4(r.x, r.y, r.z, gx.x);
-            o[1] = make_float4(gx.y, gx.z, gy.x, gy.y);
-            o[2] = make_float4(gy.z, 0.f, 0.f, 0.f);
+            const long m = (long)y * W + x, hw = (long)H * W;
+            store_nt(rec + m, make_float4(r.x, r.y, r.z, gx.x));
+            store_nt(rec + hw + m, make_float4(gx.y, gx.z, gy.x, gy.y));
+            store_nt(reinterpret_cast<float*>(rec + 2 * hw) + m, gy.z);
         }
-    }
-    __syncthreads();
-    const int nx = min(kPrepTX, W - x0);
-    for (int i = tid; i < kPrepTY * kPrepTX * kRecF4; i += 256) {
-        const int row = i / (kPrepTX * kRecF4), j = i - row * (kPrepTX * kRecF4);
-        if (j < nx * kRecF4 && y0 + row < H) store_nt(rec + ((long)(y0 + row) * W + x0) * kRecF4 + j, S.rec[i]);
     }
 }
 
@@ -229,7 +224,7 @@ __device__ __forceinline__ void lm_phase(const EdgeArgs& A, int x, int y, QState
     float3 t;
     LMState st;
     if (!lm_setup(A, x, y, q, t, st)) return;
-    const GlobalRays g{ray_buffer(A.rays, A.H, A.W), A.W};
+    const GlobalRays g(A.rays, A.H, A.W);
     lm_start(g, A.H, A.W, A.lambda0, t, st);
     lm_iterate(g, A.H, A.W, t, A.K, st);
     lm_finish(A, x, y, st, q);
@@ -406,20 +401,31 @@ __device__ __forceinline__ void block_box(int& lx, int& hx, int& ly, int& hy, in
 constexpr int kRayMargin = 2;
 
 // Copies the ray records of window [lx, lx + rw) x [ly, ly + rh) into `lds`
-// (direct global -> LDS loads, record of window pixel k at lds[3k .. 3k+2]);
-// the caller waits for them and synchronises.
+// in the layout WindowRays reads (direct global -> LDS loads: planes P0 and P1
+// of window pixel k at lds[2k] and lds[2k + 1], then plane Z, one float per
+// pixel); the caller waits for them and synchronises.  Needs 36 rw rh bytes.
 template <int NT>
 __device__ __forceinline__ void stage_rays(const EdgeArgs& A, float4* lds, int lx, int ly, int rw, int rh) {
     const int tid = threadIdx.x;
-    const int slots = kRecF4 * rw * rh;
+    const int npx = rw * rh, slots = kRecP4 * npx;
     const SmallDiv div_rw(rw);
     for (int c0 = tid & ~63; c0 < slots; c0 += NT) {
         const int c = c0 + (tid & 63);
         if (c < slots) {
-            const int pix = c / kRecF4, j = c - kRecF4 * (c / kRecF4);
+            const int pix = c >> 1, j = c & 1;
             const int ry = div_rw(pix), rx = pix - ry * rw;
-            __builtin_amdgcn_global_load_lds(A.rays + ((long)(ly + ry) * A.W + lx + rx) * kRecF4 + j,
+            __builtin_amdgcn_global_load_lds(A.rays + (long)j * A.H * A.W + (long)(ly + ry) * A.W + lx + rx,
                                              (__attribute__((address_space(3))) void*)(lds + c0), 16, 0, 0);
+        }
+    }
+    const float* z = reinterpret_cast<const float*>(A.rays + (long)kRecP4 * A.H * A.W);
+    float* ldz = reinterpret_cast<float*>(lds + slots);
+    for (int c0 = tid & ~63; c0 < npx; c0 += NT) {
+        const int c = c0 + (tid & 63);
+        if (c < npx) {
+            const int ry = div_rw(c), rx = c - ry * rw;
+            __builtin_amdgcn_global_load_lds(z + (long)(ly + ry) * A.W + lx + rx,
+                                             (__attribute__((address_space(3))) void*)(ldz + c0), 4, 0, 0);
         }
     }
 }
@@ -443,7 +449,7 @@ __device__ __forceinline__ void tile_lm(const EdgeArgs& A, int x, int y, bool in
     float3 t;
     LMState st;
     q.good = false;
-    const GlobalRays g{ray_buffer(A.rays, H, W), W};
+    const GlobalRays g(A.rays, H, W);
     const int first = min(A.K, 1);
     int wx = 0, wy = 0, ww = 0, wh = 0;  // staged window (ww == 0: none)
     if (EARLY && !A.p_init) {
@@ -508,7 +514,7 @@ constexpr int kRegionPx = 832;
 struct TileLds {
     union {
         float4 desc[6 * kRegionPx];        // refine region (six planes)
-        float4 rays[6 * kRegionPx];        // LM ray window (records of up to 2 * kRegionPx pixels)
+        float4 rays[6 * kRegionPx];        // LM ray window (36-byte records of up to 2218 pixels)
     };
     int box[4 * 16];
 };
@@ -525,7 +531,7 @@ __device__ __forceinline__ void tile_lds(const EdgeArgs& A, int tx, int ty, Tile
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT, false>(A, x, y, inside, q, S.rays, 2 * kRegionPx, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+    tile_lm<NT, false>(A, x, y, inside, q, S.rays, (int)(sizeof(S.rays) / kRecBytes), S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
                 min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
     int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
@@ -605,7 +611,7 @@ template <int CAP>
 struct TileLds16 {
     union {
         uint4 desc[3 * CAP];               // refine region (three fp16 planes of CAP pixels)
-        float4 rays[3 * CAP];              // LM ray window (records of up to CAP pixels)
+        float4 rays[3 * CAP];              // LM ray window (36-byte records of up to 4 CAP / 3 pixels)
     };
     int box[4 * 16];
     float stat[16];                       // per wave: largest |d|^2 of a region pixel
@@ -832,7 +838,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     const int x = tx * TX + tid % TX, y = ty * TY + tid / TX;
     const bool inside = x < A.W && y < A.H;
     QState q;
-    tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, CAP, S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
+    tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, (int)(sizeof(S.rays) / kRecBytes), S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
                 min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
     const int wv = tid >> 6;

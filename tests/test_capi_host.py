@@ -142,7 +142,7 @@ def test_fwd_validation(lib, case, expect):
 
 def test_workspace_bytes(lib):
     prm = _lib.default_params(lib)
-    assert lib.m3s_workspace_bytes(ctypes.byref(_pair(384, 512)), ctypes.byref(prm)) >= 384 * 512 * 48
+    assert lib.m3s_workspace_bytes(ctypes.byref(_pair(384, 512)), ctypes.byref(prm)) >= 384 * 512 * 36
     assert lib.m3s_workspace_bytes(ctypes.byref(_pair(1, 512)), ctypes.byref(prm)) == 0
     assert lib.m3s_workspace_bytes(None, ctypes.byref(prm)) == 0
 
