@@ -408,7 +408,8 @@ def tracking_c2f_leg(m3s, lib, _lib, pool_pairs, dev, sp, args):
                           "fwd_kernel_us": round(fwd_ms * 1e3, 2),
                           "fwd_algorithmic_GBs": round(alg / (fwd_ms * 1e-3) / 1e9, 1),
                           "fwd_frac_of_hbm_peak": round(alg / (fwd_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                          "global_scan_tile_levels_per_step": round(counts["refine_global"] / steps, 1)}
+                          "global_scan_tile_levels_per_step": round(counts["refine_global"] / steps, 1),
+                          "banded_tile_levels_per_step": round(counts["refine_bands"] / steps, 1)}
     log("tracking_c2f:", out)
     return out
 

@@ -462,7 +462,11 @@ m3s_status m3s_set_tune_cache(const char *path);
  *   M3S_PATH_REFINE_QUERY   a query's own descriptor norm was outside the fp16
  *                           range (fp16 configuration): exact global scan;
  *   M3S_PATH_BWD_DIRECT     a backward tile's corner window exceeded LDS, so its
- *                           gradients went to dL/dX^i_i by direct global atomics.
+ *                           gradients went to dL/dX^i_i by direct global atomics;
+ *   M3S_PATH_REFINE_BANDS   a coarse-to-fine level's region exceeded LDS and was
+ *                           staged and pre-filtered in fp16 in up to six bands of
+ *                           whole rows (not a fallback: counted so that tests can
+ *                           show the banded path ran).
  * Writes counts[M3S_PATH_COUNTERS] and, if reset != 0, zeroes the counters.
  * Synchronises the device.
  */
@@ -470,6 +474,7 @@ m3s_status m3s_set_tune_cache(const char *path);
 #define M3S_PATH_REFINE_GLOBAL 1
 #define M3S_PATH_REFINE_QUERY  2
 #define M3S_PATH_BWD_DIRECT    3
+#define M3S_PATH_REFINE_BANDS  4
 #define M3S_PATH_COUNTERS      8
 m3s_status m3s_path_counters(int64_t *counts, int32_t reset);
 

@@ -79,7 +79,7 @@ class LaunchConfig(ctypes.Structure):
 
 M3S_PATH_COUNTERS = 8
 M3S_NOALLOC_MAX_PIXELS = 1 << 18
-PATH_NAMES = ["lm_global", "refine_global", "refine_query", "bwd_direct"]
+PATH_NAMES = ["lm_global", "refine_global", "refine_query", "bwd_direct", "refine_bands"]
 
 
 class M3SError(RuntimeError):

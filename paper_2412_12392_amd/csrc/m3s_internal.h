@@ -20,7 +20,8 @@ void tile_shape(int tile_config, int* tx, int* ty);
 bool tile_uses_lds(int tile_config);
 
 // Fallback-path counters kept on the device (indices match M3S_PATH_* of m3s.h).
-enum { kPathLmGlobal = 0, kPathRefineGlobal = 1, kPathRefineQuery = 2, kPathBwdDirect = 3, kNumPathCounters = 8 };
+enum { kPathLmGlobal = 0, kPathRefineGlobal = 1, kPathRefineQuery = 2, kPathBwdDirect = 3, kPathRefineBands = 4,
+       kNumPathCounters = 8 };
 // Synchronises the device, copies the counters to out[kNumPathCounters], optionally zeroes them.
 hipError_t read_path_counters(int64_t* out, bool reset);
 

@@ -747,6 +747,75 @@ __device__ __forceinline__ void load_query16(const EdgeArgs& A, long n, Query16&
     for (int k = 0; k < 12; ++k) Q.q16[k] = pack_h2(Q.qd.q[2 * k] * kScale16, Q.qd.q[2 * k + 1] * kScale16);
 }
 
+// Survivor threshold tau of the fp16 pre-filter in scaled units (both
+// operands times kScale16): twice the bound on the fp16 score's error plus
+// that of the exact fp32 rescoring.  dnorm: bound on |d| over the staged
+// region, dl1: bound on |d|_1.
+__device__ __forceinline__ float f16_tau(const Query16& Q, float dnorm, float dl1) {
+    const float qn = Q.qn;
+    dnorm *= kScale16;
+    dl1 *= kScale16;
+    const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (Q.ql1 + dl1);
+    const float eps32 = kU32x24 * qn * dnorm;
+    return 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
+}
+
+// Pass 2 of the fp16 refine: exact scores of the survivors (candidate k of the
+// (2r+1)^2 window on bit k of mask1:mask0) in row-major order, two per step
+// so that both descriptor reads are in flight together; the first maximum.
+__device__ __forceinline__ long f16_rescore(const EdgeArgs& A, const Query16& Q, int mx0, int my0, int sp,
+                                            uint64_t mask0, uint64_t mask1) {
+    const int W = A.W, r = A.r, side = 2 * r + 1;
+    auto pop = [&](uint64_t& m0, uint64_t& m1) -> int {
+        if (m0) { const int k = __builtin_ctzll(m0); m0 &= m0 - 1; return k; }
+        if (m1) { const int k = 64 + __builtin_ctzll(m1); m1 &= m1 - 1; return k; }
+        return -1;
+    };
+    auto pixel = [&](int kk) -> long {
+        const int dy = kk / side, dx = kk - dy * side;
+        return (long)(my0 + sp * (dy - r)) * W + (mx0 + sp * (dx - r));
+    };
+    float best = -INFINITY;
+    long bi = -1;
+    while (mask0 | mask1) {
+        const int k1 = pop(mask0, mask1), k2 = pop(mask0, mask1);
+        const long m1 = pixel(k1), m2 = k2 >= 0 ? pixel(k2) : m1;
+        const float s1 = exact24(Q.qd.q, A.Dii, m1), s2 = exact24(Q.qd.q, A.Dii, m2);
+        if (s1 > best) { best = s1; bi = m1; }
+        if (k2 >= 0 && s2 > best) { best = s2; bi = m2; }
+    }
+    return bi;
+}
+
+// Pass 1 of the fp16 refine over the window rows that lie in one band of a
+// region staged band by band: region rows [ry0, bhi] (inside the image) are in
+// LDS, ry0 first.  The running maximum `run` and the survivor masks carry over
+// from the bands above, so the candidates are still thresholded in row-major
+// order, each against the largest score before it; tau only grows from band
+// to band (it follows the largest |d| staged so far), so every survivor test
+// keeps the margin that the candidates scanned until then need.
+template <int CAP>
+__device__ __forceinline__ void f16_scan_band(const EdgeArgs& A, const Query16& Q, int mx0, int my0, int sp,
+                                              const uint4* __restrict__ sd, int rx0, int ry0, int rw, int bhi,
+                                              float tau, float& run, uint64_t& mask0, uint64_t& mask1) {
+    const int W = A.W, r = A.r, side = 2 * r + 1;
+    for (int dy = -r; dy <= r; ++dy) {
+        const int my = my0 + sp * dy;
+        if (my < ry0 || my > bhi) continue;
+        const uint4* d = sd + (my - ry0) * rw - rx0;
+        for (int dx = -r; dx <= r; ++dx) {
+            const int mx = mx0 + sp * dx;
+            if (mx < 0 || mx >= W) continue;
+            const int k = (dy + r) * side + (dx + r);
+            const float s16 = dot16(Q.q16, d[mx], d[mx + CAP], d[mx + 2 * CAP]);
+            run = __builtin_amdgcn_fmed3f(s16, run, INFINITY);
+            if (s16 >= run - tau) {
+                if (k < 64) mask0 |= 1ull << k; else mask1 |= 1ull << (k - 64);
+            }
+        }
+    }
+}
+
 // One level of the exact first-maximum refine with the fp16 pre-filter: the
 // (2r+1)^2 grid of spacing sp around (mx0, my0), over a staged region that
 // holds every candidate inside the image.  dnorm: bound on |d| over the
@@ -756,13 +825,7 @@ __device__ __forceinline__ long refine_f16_level(const EdgeArgs& A, const Query1
                                                  const uint4* __restrict__ sd, int rx0, int ry0, int rw, float dnorm,
                                                  float dl1) {
     const int H = A.H, W = A.W, r = A.r, side = 2 * r + 1;
-    // Bounds and tau in scaled units (both operands times kScale16).
-    const float qn = Q.qn;
-    dnorm *= kScale16;
-    dl1 *= kScale16;
-    const float eps16 = (2.f * kU16 + kU16 * kU16 + kU32x24) * qn * dnorm + kFlush16 * (Q.ql1 + dl1);
-    const float eps32 = kU32x24 * qn * dnorm;
-    const float tau = 2.f * (eps16 + eps32) * 1.0001f + 1e-30f;
+    const float tau = f16_tau(Q, dnorm, dl1);
 
     // Pass 1: fp16 scores in row-major window order over the candidates
     // inside the image; the running maximum is seeded with the window centre
@@ -801,28 +864,79 @@ __device__ __forceinline__ long refine_f16_level(const EdgeArgs& A, const Query1
             }
         }
     }
-    // Pass 2: exact scores of the survivors in row-major order, two per step
-    // so that both descriptor reads are in flight together.
-    auto pop = [&](uint64_t& m0, uint64_t& m1) -> int {
-        if (m0) { const int k = __builtin_ctzll(m0); m0 &= m0 - 1; return k; }
-        if (m1) { const int k = 64 + __builtin_ctzll(m1); m1 &= m1 - 1; return k; }
-        return -1;
-    };
-    auto pixel = [&](int kk) -> long {
-        const int dy = kk / side, dx = kk - dy * side;
-        return (long)(my0 + sp * (dy - r)) * W + (mx0 + sp * (dx - r));
-    };
-    float best = -INFINITY;
-    long bi = -1;
-    while (mask0 | mask1) {
-        const int k1 = pop(mask0, mask1), k2 = pop(mask0, mask1);
-        const long m1 = pixel(k1), m2 = k2 >= 0 ? pixel(k2) : m1;
-        const float s1 = exact24(Q.qd.q, A.Dii, m1), s2 = exact24(Q.qd.q, A.Dii, m2);
-        if (s1 > best) { best = s1; bi = m1; }
-        if (k2 >= 0 && s2 > best) { best = s2; bi = m2; }
-    }
-    return bi;
+    // Pass 2: exact scores of the survivors.
+    return f16_rescore(A, Q, mx0, my0, sp, mask0, mask1);
 }
+
+// Stages region rows [ly, ly + rh) x columns [lx, lx + rw) of D^i_i into the
+// three fp16 planes of `desc` (region pixel pix of plane k at desc[k * CAP +
+// pix], scaled by kScale16): each lane converts whole pixels (six float4
+// loads, the norm, three fp16 planes), kBatch pixels per step with all loads
+// issued before the conversions and stores.  Returns the lane's largest |d|^2
+// (+inf for a pixel with a non-finite element or squares that overflow, which
+// fails the caller's range test).
+template <int NT, int CAP, int kBatch>
+__device__ __forceinline__ float stage_region16(const EdgeArgs& A, uint4* desc, int lx, int ly, int rw, int rh) {
+    const int tid = threadIdx.x, W = A.W;
+    const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
+    const int total = rw * rh;
+    const SmallDiv div_rw(rw);
+    float pn2 = 0.f;
+    for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
+        float4 v[kBatch][6];
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int pix = p00 + tid + i * NT;
+            if (pix < total) {
+                const int ry = div_rw(pix), rx = pix - ry * rw;
+                const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) v[i][k] = src[k];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < kBatch; ++i) {
+            const int pix = p00 + tid + i * NT;
+            if (pix < total) {
+                float e2 = 0.f;
+#pragma unroll
+                for (int k = 0; k < 6; ++k)
+                    e2 += v[i][k].x * v[i][k].x + v[i][k].y * v[i][k].y + v[i][k].z * v[i][k].z + v[i][k].w * v[i][k].w;
+                pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
+#pragma unroll
+                for (int k = 0; k < 3; ++k) {
+                    const float4 u = v[i][2 * k], w = v[i][2 * k + 1];
+                    desc[k * CAP + pix] =
+                        make_uint4(pack_h2(u.x * kScale16, u.y * kScale16), pack_h2(u.z * kScale16, u.w * kScale16),
+                                   pack_h2(w.x * kScale16, w.y * kScale16), pack_h2(w.z * kScale16, w.w * kScale16));
+                }
+            }
+        }
+    }
+    return pn2;
+}
+
+// Largest pn2 over the block (ends with a barrier, so the staged region is
+// complete).  Region bounds: |d| <= sqrt(pn2) for every pixel, so every
+// element |d_k| <= sqrt(pn2) (kScale16^2 pn2 <= kF16Max^2 keeps the scaled
+// conversion finite), and |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
+template <int NT>
+__device__ __forceinline__ float block_max16(float pn2, float* stat) {
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
+    if ((tid & 63) == 0) stat[tid >> 6] = pn2;
+    __syncthreads();
+    pn2 = stat[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, stat[w]);
+    return pn2;
+}
+
+// Bands of whole region rows that the multi-level kernel stages and scans one
+// after another when a level's region exceeds LDS (more fall back to the exact
+// global scan).
+constexpr int kMaxBands = 6;
 
 // One TX x TY tile with the fp16 pre-filtered refine, level by level for the
 // coarse-to-fine refine when MULTI is set (level l scans the grid of spacing 2^l around the
@@ -841,7 +955,6 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     tile_lm<NT, EARLY, MARGIN, UNROLL>(A, x, y, inside, q, S.rays, (int)(sizeof(S.rays) / kRecBytes), S.box, tx * TX, min(tx * TX + TX, A.W) - 1, ty * TY,
                 min(ty * TY + TY, A.H) - 1);
     const int r = A.r, W = A.W, H = A.H;
-    const int wv = tid >> 6;
     const long n = (long)y * W + x;
     long bi = -1;
     bool live = q.good;   // takes part in the level below
@@ -858,79 +971,68 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
         block_box<NT>(lx, hx, ly, hy, S.box);  // ends with a barrier: the previous level is done with S
         const int rw = hx - lx + 1, rh = hy - ly + 1;
         const bool any = hx >= lx;
-        bool use16 = any && rw * rh <= CAP && r <= 5;
-        float pn2 = 0.f;  // largest |d|^2 over the region's pixels
-        if (use16) {
-            // Stage: each lane converts whole pixels (six float4 loads, the norm,
-            // three fp16 planes), kBatch pixels per step with all loads issued
-            // before the conversions and stores.
-            constexpr int kBatch = 2;
-            const float4* src4 = reinterpret_cast<const float4*>(A.Dii);
-            const int total = rw * rh;
-            const SmallDiv div_rw(rw);
-            for (int p00 = 0; p00 < total; p00 += kBatch * NT) {
-                float4 v[kBatch][6];
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    const int pix = p00 + tid + i * NT;
-                    if (pix < total) {
-                        const int ry = div_rw(pix), rx = pix - ry * rw;
-                        const float4* src = src4 + ((long)(ly + ry) * W + lx + rx) * 6;
-#pragma unroll
-                        for (int k = 0; k < 6; ++k) v[i][k] = src[k];
-                    }
-                }
-#pragma unroll
-                for (int i = 0; i < kBatch; ++i) {
-                    const int pix = p00 + tid + i * NT;
-                    if (pix < total) {
-                        float e2 = 0.f;
-#pragma unroll
-                        for (int k = 0; k < 6; ++k)
-                            e2 += v[i][k].x * v[i][k].x + v[i][k].y * v[i][k].y + v[i][k].z * v[i][k].z + v[i][k].w * v[i][k].w;
-                        // A NaN or infinite element, or squares that overflow, make e2
-                        // non-finite and fail the range test below.
-                        pn2 = fmaxf(pn2, isfinite(e2) ? e2 : INFINITY);
-#pragma unroll
-                        for (int k = 0; k < 3; ++k) {
-                            const float4 u = v[i][2 * k], w = v[i][2 * k + 1];
-                            S.desc[k * CAP + pix] =
-                                make_uint4(pack_h2(u.x * kScale16, u.y * kScale16), pack_h2(u.z * kScale16, u.w * kScale16),
-                                           pack_h2(w.x * kScale16, w.y * kScale16), pack_h2(w.z * kScale16, w.w * kScale16));
-                        }
-                    }
-                }
-            }
-        }
-        // Region bounds: |d| <= sqrt(pn2) for every pixel, so every element
-        // |d_k| <= sqrt(pn2) (kScale16^2 pn2 <= kF16Max^2 keeps the scaled
-        // conversion finite), and |d|_1 <= sqrt(24) |d| (Cauchy-Schwarz).
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) pn2 = fmaxf(pn2, __shfl_xor(pn2, o, 64));
-        if ((tid & 63) == 0) S.stat[wv] = pn2;
-        __syncthreads();
-        pn2 = S.stat[0];
-#pragma unroll
-        for (int w = 1; w < NT / 64; ++w) pn2 = fmaxf(pn2, S.stat[w]);
-        use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
-        if (any && !use16 && tid == 0) count_path(kPathRefineGlobal);
+        // The query descriptor is read after the level's region (or its first
+        // band) is staged: its registers are not live during the staging.  A
+        // query whose own descriptor is outside the fp16 range refines every
+        // level exactly from global memory and leaves the levels below.
         Query16 Q;
-        if (live) {
-            // The query descriptor is read after each level's region is staged
-            // (its registers are not live during the staging).  A query whose
-            // own descriptor is outside the fp16 range refines every level
-            // exactly from global memory and leaves the levels below.
+        auto query = [&]() {
             load_query16(A, n, Q);
             if (!Q.ok) {
                 count_path(kPathRefineQuery);
                 bi = refine_global<24>(A, n, q);
                 live = false;
             }
+        };
+        long lb = -1;
+        // Rows per band when the multi-level kernel stages a region that
+        // exceeds LDS band by band (0: not banded).
+        int band = 0;
+        if constexpr (MULTI) {
+            if (any && r <= 5 && rw * rh > CAP && rw <= CAP && rh <= kMaxBands * (CAP / rw)) band = CAP / rw;
+        }
+        if (band > 0) {
+            if (tid == 0) count_path(kPathRefineBands);
+            float pn2 = 0.f, run = -INFINITY;
+            uint64_t mask0 = 0, mask1 = 0;
+            bool ok16 = true, have_q = false;
+            for (int b0 = 0; b0 < rh; b0 += band) {
+                const int nr = min(band, rh - b0);
+                if (b0 > 0) __syncthreads();  // every lane is done with the previous band
+                pn2 = fmaxf(pn2, block_max16<NT>(stage_region16<NT, CAP, 1>(A, S.desc, lx, ly + b0, rw, nr), S.stat));
+                if (!(pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16))) {
+                    ok16 = false;  // the same for every lane
+                    break;
+                }
+                if (live && !have_q) {
+                    have_q = true;
+                    query();
+                }
+                if (live) {
+                    const float dnorm = sqrtf(pn2) * 1.0001f;
+                    f16_scan_band<CAP>(A, Q, cx, cy, sp, S.desc, lx, ly + b0, rw, ly + b0 + nr - 1,
+                                       f16_tau(Q, dnorm, kSqrt24Up * dnorm), run, mask0, mask1);
+                }
+            }
+            if (!ok16 && tid == 0) count_path(kPathRefineGlobal);
+            if (live && !have_q) query();
+            if (live)
+                lb = ok16 ? f16_rescore(A, Q, cx, cy, sp, mask0, mask1) : refine_global_level<24>(A, Q.qd, cx, cy, sp);
+        } else {
+            bool use16 = any && rw * rh <= CAP && r <= 5;
+            float pn2 = 0.f;  // largest |d|^2 over the region's pixels
+            if (use16) pn2 = stage_region16<NT, CAP, 2>(A, S.desc, lx, ly, rw, rh);
+            pn2 = block_max16<NT>(pn2, S.stat);
+            use16 = use16 && pn2 <= (kF16Max / kScale16) * (kF16Max / kScale16);
+            if (any && !use16 && tid == 0) count_path(kPathRefineGlobal);
+            if (live) query();
+            if (live) {
+                const float dnorm = sqrtf(pn2) * 1.0001f;
+                lb = use16 ? refine_f16_level<CAP>(A, Q, cx, cy, sp, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
+                           : refine_global_level<24>(A, Q.qd, cx, cy, sp);
+            }
         }
         if (live) {
-            const float dnorm = sqrtf(pn2) * 1.0001f;
-            const long lb = use16 ? refine_f16_level<CAP>(A, Q, cx, cy, sp, S.desc, lx, ly, rw, dnorm, kSqrt24Up * dnorm)
-                                  : refine_global_level<24>(A, Q.qd, cx, cy, sp);
             if (lb < 0) {
                 live = false;
             } else {
