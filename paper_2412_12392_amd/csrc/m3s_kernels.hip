@@ -961,6 +961,8 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
     int cx = live ? round_half_up(q.px) : 0, cy = live ? round_half_up(q.py) : 0;
     // MULTI = false: one level (the launcher takes the MULTI kernel for L > 1;
     // a constant trip count keeps the single-level kernel free of spills).
+    Query16 Q;            // read once, at the first level that needs it
+    bool have_q = false;
     for (int lev = MULTI ? A.levels - 1 : 0; lev >= 0; --lev) {
         const int sp = 1 << lev, reach = r * sp;
         int lx = INT_MAX, hx = INT_MIN, ly = INT_MAX, hy = INT_MIN;
@@ -971,12 +973,14 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
         block_box<NT>(lx, hx, ly, hy, S.box);  // ends with a barrier: the previous level is done with S
         const int rw = hx - lx + 1, rh = hy - ly + 1;
         const bool any = hx >= lx;
-        // The query descriptor is read after the level's region (or its first
-        // band) is staged: its registers are not live during the staging.  A
+        // The query descriptor is read once, after the first level's region (or
+        // its first band) is staged, so that its registers are not live during
+        // that staging; the later levels of the multi-level kernel keep it.  A
         // query whose own descriptor is outside the fp16 range refines every
         // level exactly from global memory and leaves the levels below.
-        Query16 Q;
         auto query = [&]() {
+            if (have_q) return;
+            have_q = true;
             load_query16(A, n, Q);
             if (!Q.ok) {
                 count_path(kPathRefineQuery);
@@ -995,7 +999,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
             if (tid == 0) count_path(kPathRefineBands);
             float pn2 = 0.f, run = -INFINITY;
             uint64_t mask0 = 0, mask1 = 0;
-            bool ok16 = true, have_q = false;
+            bool ok16 = true;
             for (int b0 = 0; b0 < rh; b0 += band) {
                 const int nr = min(band, rh - b0);
                 if (b0 > 0) __syncthreads();  // every lane is done with the previous band
@@ -1004,10 +1008,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
                     ok16 = false;  // the same for every lane
                     break;
                 }
-                if (live && !have_q) {
-                    have_q = true;
-                    query();
-                }
+                if (live) query();
                 if (live) {
                     const float dnorm = sqrtf(pn2) * 1.0001f;
                     f16_scan_band<CAP>(A, Q, cx, cy, sp, S.desc, lx, ly + b0, rw, ly + b0 + nr - 1,
@@ -1015,7 +1016,7 @@ __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, Tile
                 }
             }
             if (!ok16 && tid == 0) count_path(kPathRefineGlobal);
-            if (live && !have_q) query();
+            if (live) query();
             if (live)
                 lb = ok16 ? f16_rescore(A, Q, cx, cy, sp, mask0, mask1) : refine_global_level<24>(A, Q.qd, cx, cy, sp);
         } else {
