@@ -174,8 +174,10 @@ m3s_status m3s_match_fwd_noalloc(const m3s_pair *pair, const m3s_params *params,
  * grad_Xji[n] = N(x_n) v and grad_Xii[c] -= w_c N(X^i_i[c]) v / |r|, with
  * N(X) = (I - X X^T/|X|^2)/|X| (Supp. A, Eq. norm_jac), plus the bilinear
  * weights of grad_xhat into the four corners of p*.  Invalid queries
- * contribute nothing.  grad_Xii is accumulated with fp32 atomics, so its
- * rounding may differ between runs.  No workspace is needed.
+ * contribute nothing.  grad_Xii sums the terms of each 16 x 16 query tile in
+ * 64-bit fixed point (exact, independent of their order) and adds the tiles'
+ * sums with fp32 atomics, so its rounding may differ between runs.  No
+ * workspace is needed.
  */
 m3s_status m3s_match_bwd(const m3s_pair *pair, const m3s_outputs *fwd,
                          const float *grad_p, const float *grad_xhat,

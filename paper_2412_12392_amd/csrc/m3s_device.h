@@ -24,7 +24,7 @@ struct EdgeArgs {
     const float* Qii;              // nullptr: no confidence gate
     const float* Qji;
     const float* p_init;           // nullptr: identity initialisation
-    const float4* rays;            // workspace: 3 float4 per reference pixel
+    const float4* rays;            // workspace: ray image, 36 B per reference pixel (planes P0, P1, Z)
     float* p;
     int32_t* idx;
     uint8_t* valid;

@@ -1,13 +1,14 @@
 // gfx950 kernels of the projective pointmap matcher (MASt3R-SLAM, Sec. 3.2).
 //
 //   prep      ray image R = X^i_i / |X^i_i| and its central-difference
-//             gradient images, packed as 3 float4 per reference pixel
+//             gradient images, 36 B per reference pixel in three planes
 //             (Sec. 3.1: each pointmap defines its own central camera through
 //             its rays; Fig. 2: the reference pointmap is normalised first).
 //   fwd       one lane per query pixel: LM on the ray error (Eq. 2), residual
 //             angle (Eq. 3), bilinear xhat, window refine by descriptor dot
 //             product (feature refinement paragraph), gates (Sec. 3.2, 3.3).
-//   bwd       implicit adjoint at p* with fp32 atomics into dL/dX^i_i.
+//   bwd       implicit adjoint at p*, scattered into dL/dX^i_i through an LDS
+//             window of 64-bit fixed point.
 //   batched   persistent work-queue version of prep + fwd over an edge table.
 //
 // Every launch is checked on the host against the shapes its grid assumes;
