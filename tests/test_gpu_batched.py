@@ -236,7 +236,8 @@ def test_autotune_cache_file_round_trip(m3s, tmp_path):
 
 @pytest.mark.parametrize("levels", [2, 3])
 def test_batched_coarse_to_fine_equals_per_pair(m3s, levels):
-    """The persistent kernel's multi-level refine equals the per-pair launch bit for bit."""
+    """The persistent kernel's multi-level refine equals the per-pair launch bit
+    for bit; at L = 3 the coarsest levels that exceed LDS are staged in bands."""
     import torch
     edges = edge_inputs(m3s, mixed_pairs())
     ref = []
@@ -245,8 +246,13 @@ def test_batched_coarse_to_fine_equals_per_pair(m3s, levels):
         ref.append(parity.result_numpy(m3s.match(e.Xii, e.Xji, e.Dii, e.Dji, e.Qii, e.Qji, None, prm,
                                                  want_xhat=True)))
     s = torch.cuda.Stream()
+    m3s.path_counters(reset=True)
     with torch.cuda.stream(s):
         outs = m3s.match_batched(edges, prm=m3s.params(refine_levels=levels), graph=True, want_xhat=True)
     s.synchronize()
+    cnt = m3s.path_counters(reset=True)
+    print("L%d batched path counters:" % levels, cnt)
+    if levels == 3:
+        assert cnt["refine_bands"] > 0
     for k, (a, b) in enumerate(zip(ref, outs)):
         assert_same(a, parity.result_numpy(b), "L%d edge %d" % (levels, k))
