@@ -179,3 +179,39 @@ def test_batched_every_tile_config(m3s, tile_config):
         p = pairs[k]
         o = oracle.match_fwd(p.Xii, p.Xji, p.Dii, p.Dji, p.Qii, p.Qji, K=p.K, r=p.r)
         print(parity.compare(parity.result_numpy(outs[k]), o, "tile %d edge %d" % (tile_config, k), pair=p, r=p.r))
+
+
+def test_banded_level_fallbacks(m3s):
+    """Coarse to fine at L = 3 from previous-frame pixels: the coarsest level's
+    regions exceed LDS and are staged and pre-filtered in bands of rows.
+    Reference descriptors beyond the scaled fp16 range in the lower rows make
+    some of those levels fail the range test in a later band (exact global
+    scan of that level instead), and oversized query descriptors send their
+    queries to the exact scan from the first band.  The bits equal the
+    global-memory configuration's, and the plain case agrees with the oracle."""
+    base = synth.make_pair(96, 128, 41)
+    rng = np.random.Generator(np.random.PCG64(41))
+    p_init = (base.proj + rng.normal(0, 1.5, size=base.proj.shape)).astype(np.float32)
+    big_ref = base.Dii.copy()
+    big_ref[64:] *= 1000.0
+    big_query = base.Dji.copy()
+    big_query[10:12, 40:60] *= 300.0
+    cases = [("plain", base.Dii, base.Dji, ()), ("ref_rows_x1000", big_ref, base.Dji, ("refine_global",)),
+             ("query_x300", base.Dii, big_query, ("refine_query",))]
+    for name, Dii, Dji, keys in cases:
+        pair = synth.Pair(base.H, base.W, base.Xii, base.Xji, np.ascontiguousarray(Dii, np.float32),
+                          np.ascontiguousarray(Dji, np.float32), base.Qii, base.Qji, K=base.K, r=base.r,
+                          proj=base.proj)
+        print("case banded levels %s" % name, flush=True)
+        g5, c5 = run_counted(m3s, pair, 5, p_init, refine_levels=3)
+        g0, _ = run_counted(m3s, pair, 0, p_init, refine_levels=3)
+        print(name, c5)
+        assert c5["refine_bands"] > 0, (name, c5)
+        for key in keys:
+            assert c5[key] > 0, (name, key, c5)
+        for k in ("p", "idx", "valid", "theta", "xhat"):
+            assert np.array_equal(g5[k], g0[k], equal_nan=True), (name, k)
+        if name == "plain":
+            o = oracle.match_fwd(pair.Xii, pair.Xji, pair.Dii, pair.Dji, pair.Qii, pair.Qji,
+                                 p_init.astype(np.float64), K=pair.K, r=pair.r, levels=3)
+            print(parity.compare(g5, o, "banded levels", pair=pair, r=pair.r, levels=3))
