@@ -942,9 +942,11 @@ constexpr int kMaxBands = 6;
 // One TX x TY tile with the fp16 pre-filtered refine, level by level for the
 // coarse-to-fine refine when MULTI is set (level l scans the grid of spacing 2^l around the
 // previous level's best).  For each level the region is the bounding box of
-// the windows of the tile's good queries; a level whose region does not fit,
-// whose radius exceeds 5, or whose region holds a value too large for fp16
-// is scanned exactly from global memory instead (the whole tile at that level).
+// the windows of the tile's good queries.  With MULTI set, a region that does
+// not fit LDS is staged and pre-filtered in bands of whole rows (at most
+// kMaxBands).  A level whose region does not fit (in bands), whose radius
+// exceeds 5, or whose region holds a value too large for fp16 is scanned
+// exactly from global memory instead (the whole tile at that level).
 template <int TX, int TY, bool EARLY, int MARGIN = kRayMargin, int UNROLL = 1, bool MULTI = false>
 __device__ __forceinline__ void tile_f16(const EdgeArgs& A, int tx, int ty, TileLds16<f16_cap<TX, TY, MULTI>()>& S) {
     constexpr int NT = TX * TY;
