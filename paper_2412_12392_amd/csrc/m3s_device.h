@@ -103,33 +103,53 @@ __device__ __forceinline__ float rec_load1(RayBuf rb, uint32_t byte_off) {
 // its Jacobian blocks are then not meaningful, and they are never used: a
 // trial of infinite cost is never accepted, and a degenerate starting sample
 // gives a non-finite step, which the LM rejects without moving.
-template <bool FULL>
-__device__ __forceinline__ void ray_error_from(const float4* A, const float4* B, const float4* C, const float4* D,
-                                               const float* z, float a, float b, float3 t, Sample& s) {
-    float w00 = (1.f - a) * (1.f - b), w10 = a * (1.f - b), w01 = (1.f - a) * b, w11 = a * b;
-#define M3S_BL(i, c) (w00 * A[i].c + w10 * B[i].c + w01 * C[i].c + w11 * D[i].c)
+// What the Jacobian part of a sample needs from its ray part: the bilinear
+// weights, the unit interpolated ray psi, 1/|r| and the residual e.
+struct RayPart {
+    float w00, w10, w01, w11;
+    float p0, p1, p2, inv;
+    float e0, e1, e2;
+};
+
+#define M3S_BL(i, c) (r.w00 * A[i].c + r.w10 * B[i].c + r.w01 * C[i].c + r.w11 * D[i].c)
+
+// Ray part of a sample: the cost |e|^2 (+inf when degenerate).
+__device__ __forceinline__ float ray_cost_from(const float4* A, const float4* B, const float4* C, const float4* D,
+                                               float a, float b, float3 t, RayPart& r) {
+    r.w00 = (1.f - a) * (1.f - b), r.w10 = a * (1.f - b), r.w01 = (1.f - a) * b, r.w11 = a * b;
     float rx = M3S_BL(0, x), ry = M3S_BL(0, y), rz = M3S_BL(0, z);
     float n2 = rx * rx + ry * ry + rz * rz;
     const bool ok = n2 > 0.0f && n2 < INFINITY;  // false for 0, +inf and NaN
-    float inv = rsq(n2);
-    float p0 = rx * inv, p1 = ry * inv, p2 = rz * inv;
-    float e0 = p0 - t.x, e1 = p1 - t.y, e2 = p2 - t.z;
-    s.c = ok ? e0 * e0 + e1 * e1 + e2 * e2 : INFINITY;
-    if constexpr (FULL) {
-        float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
-        float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = w00 * z[0] + w10 * z[1] + w01 * z[2] + w11 * z[3];
-        float pgx = p0 * gxx + p1 * gxy + p2 * gxz;
-        float pgy = p0 * gyx + p1 * gyy + p2 * gyz;
-        // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
-        float jx0 = (gxx - p0 * pgx) * inv, jx1 = (gxy - p1 * pgx) * inv, jx2 = (gxz - p2 * pgx) * inv;
-        float jy0 = (gyx - p0 * pgy) * inv, jy1 = (gyy - p1 * pgy) * inv, jy2 = (gyz - p2 * pgy) * inv;
-        s.a00 = jx0 * jx0 + jx1 * jx1 + jx2 * jx2;
-        s.a01 = jx0 * jy0 + jx1 * jy1 + jx2 * jy2;
-        s.a11 = jy0 * jy0 + jy1 * jy1 + jy2 * jy2;
-        s.g0 = jx0 * e0 + jx1 * e1 + jx2 * e2;
-        s.g1 = jy0 * e0 + jy1 * e1 + jy2 * e2;
-    }
+    r.inv = rsq(n2);
+    r.p0 = rx * r.inv, r.p1 = ry * r.inv, r.p2 = rz * r.inv;
+    r.e0 = r.p0 - t.x, r.e1 = r.p1 - t.y, r.e2 = r.p2 - t.z;
+    return ok ? r.e0 * r.e0 + r.e1 * r.e1 + r.e2 * r.e2 : INFINITY;
+}
+
+// Jacobian part of a sample: J^T J and J^T e from the interpolated gradients.
+__device__ __forceinline__ void ray_jacobian_from(const float4* A, const float4* B, const float4* C,
+                                                  const float4* D, const float* z, const RayPart& r, Sample& s) {
+    float gxx = M3S_BL(0, w), gxy = M3S_BL(1, x), gxz = M3S_BL(1, y);
+    float gyx = M3S_BL(1, z), gyy = M3S_BL(1, w), gyz = r.w00 * z[0] + r.w10 * z[1] + r.w01 * z[2] + r.w11 * z[3];
+    float pgx = r.p0 * gxx + r.p1 * gxy + r.p2 * gxz;
+    float pgy = r.p0 * gyx + r.p1 * gyy + r.p2 * gyz;
+    // J = (I - psi psi^T) [gx gy] / |r|  (Supp. A, Eq. norm_jac)
+    float jx0 = (gxx - r.p0 * pgx) * r.inv, jx1 = (gxy - r.p1 * pgx) * r.inv, jx2 = (gxz - r.p2 * pgx) * r.inv;
+    float jy0 = (gyx - r.p0 * pgy) * r.inv, jy1 = (gyy - r.p1 * pgy) * r.inv, jy2 = (gyz - r.p2 * pgy) * r.inv;
+    s.a00 = jx0 * jx0 + jx1 * jx1 + jx2 * jx2;
+    s.a01 = jx0 * jy0 + jx1 * jy1 + jx2 * jy2;
+    s.a11 = jy0 * jy0 + jy1 * jy1 + jy2 * jy2;
+    s.g0 = jx0 * r.e0 + jx1 * r.e1 + jx2 * r.e2;
+    s.g1 = jy0 * r.e0 + jy1 * r.e1 + jy2 * r.e2;
+}
 #undef M3S_BL
+
+template <bool FULL>
+__device__ __forceinline__ void ray_error_from(const float4* A, const float4* B, const float4* C, const float4* D,
+                                               const float* z, float a, float b, float3 t, Sample& s) {
+    RayPart r;
+    s.c = ray_cost_from(A, B, C, D, a, b, t, r);
+    if constexpr (FULL) ray_jacobian_from(A, B, C, D, z, r, s);
 }
 
 // Ray records from the workspace in global memory.
@@ -265,17 +285,22 @@ __device__ __forceinline__ void lm_iterate(const Src& src, int H, int W, float3 
     for (int it = 0; it < full; ++it) {
         float qx, qy;
         if (!lm_step(cur, lambda, px, py, xmax, ymax, qx, qy)) { lambda *= 10.f; continue; }
-        sample_ray_error<true>(src, xcell, ycell, qx, qy, t, nxt);
-        // Accept on strictly lower cost: selects, no branch.
-        const bool acc = nxt.c < cur.c;
-        px = acc ? qx : px;
-        py = acc ? qy : py;
-        cur.c = acc ? nxt.c : cur.c;
-        cur.a00 = acc ? nxt.a00 : cur.a00;
-        cur.a01 = acc ? nxt.a01 : cur.a01;
-        cur.a11 = acc ? nxt.a11 : cur.a11;
-        cur.g0 = acc ? nxt.g0 : cur.g0;
-        cur.g1 = acc ? nxt.g1 : cur.g1;
+        // The trial's cost first; its Jacobian blocks only where it is accepted
+        // (on strictly lower cost).  After the first few iterations most lanes
+        // reject, and a wave whose lanes all reject skips that part.
+        const float fx0 = fminf(floorf(qx), xcell), fy0 = fminf(floorf(qy), ycell);
+        float4 A[kRecP4], B[kRecP4], C[kRecP4], D[kRecP4];
+        float z[4];
+        src.fetch((int)fx0, (int)fy0, A, B, C, D, z);
+        RayPart r;
+        const float c = ray_cost_from(A, B, C, D, qx - fx0, qy - fy0, t, r);
+        const bool acc = c < cur.c;
+        if (acc) {
+            ray_jacobian_from(A, B, C, D, z, r, cur);
+            cur.c = c;
+            px = qx;
+            py = qy;
+        }
         lambda = acc ? lambda * 0.1f : lambda * 10.f;
     }
     if (final && iters > 0) {
