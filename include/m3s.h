@@ -187,7 +187,11 @@ m3s_status m3s_match_bwd(const m3s_pair *pair, const m3s_outputs *fwd,
  * m3s_match_bwd_batched -- m3s_match_bwd over n_edges edges (for example the
  * edges just matched by m3s_match_batched) in two launches: one zeroes every
  * grad_Xii, then one persistent launch works through the 16 x 16 query tiles
- * of all edges.  `edges` is a HOST array, copied into the workspace on
+ * of all edges.  With M3S_BWD_ACCUMULATE in flags there is no zeroing launch:
+ * the gradients are added to grad_Xii's contents (gradient accumulation, for
+ * example several edges of one keyframe into one buffer, or a buffer the
+ * caller cleared on another stream while the forward ran); grad_Xji is still
+ * overwritten.  `edges` is a HOST array, copied into the workspace on
  * `stream` before the launches (the caller may reuse it when the call
  * returns).  grad_Xji equals m3s_match_bwd's bit for bit; grad_Xii equals it
  * up to the order of the fp32 atomic additions.  With M3S_BATCH_GRAPH the two
@@ -203,7 +207,7 @@ typedef struct {
     const uint8_t *valid;          /* [H*W]   the forward's valid */
     const float   *grad_p;         /* [H*W*2] required */
     const float   *grad_xhat;      /* [H*W*3] or NULL */
-    float         *grad_Xii;       /* [H*W*3] overwritten */
+    float         *grad_Xii;       /* [H*W*3] overwritten (added to with M3S_BWD_ACCUMULATE) */
     float         *grad_Xji;       /* [H*W*3] overwritten */
 } m3s_bwd_edge;
 size_t m3s_bwd_batched_workspace_bytes(int32_t n_edges);
@@ -377,6 +381,7 @@ m3s_status m3s_backend_gn(const m3s_backend_problem *prob, const m3s_backend_par
 /* Flags of m3s_match_batched. */
 #define M3S_BATCH_GRAPH    0x1u  /* capture the launch sequence in a hipGraph and replay it */
 #define M3S_BATCH_AUTOTUNE 0x2u  /* time candidate launch shapes once per shape signature */
+#define M3S_BWD_ACCUMULATE 0x4u  /* m3s_match_bwd_batched: add to grad_Xii instead of overwriting it */
 
 /*
  * Workspace bytes m3s_match_batched needs for these edges (0 on invalid input):

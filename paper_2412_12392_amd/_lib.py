@@ -12,6 +12,7 @@ STATUS_NAMES = {0: "M3S_OK", 1: "M3S_ERR_NULL", 2: "M3S_ERR_SHAPE", 3: "M3S_ERR_
                 4: "M3S_ERR_WORKSPACE", 5: "M3S_ERR_HIP", 6: "M3S_ERR_UNSUPPORTED"}
 M3S_BATCH_GRAPH = 0x1
 M3S_BATCH_AUTOTUNE = 0x2
+M3S_BWD_ACCUMULATE = 0x4
 
 c_fp = ctypes.POINTER(ctypes.c_float)
 

@@ -201,15 +201,19 @@ def make_bwd_edges(inputs: Sequence[BwdEdgeInput], outs=None):
     return table, grads
 
 
-def match_backward_batched(inputs: Sequence[BwdEdgeInput], graph: bool = True, outs=None, stream=None):
+def match_backward_batched(inputs: Sequence[BwdEdgeInput], graph: bool = True, outs=None, stream=None,
+                           accumulate: bool = False):
     """m3s_match_bwd_batched: the implicit adjoint of every edge in one persistent launch
-    (after one launch that zeroes every grad_Xii); returns [(grad_Xii, grad_Xji)] per edge."""
+    (after one launch that zeroes every grad_Xii, or, with accumulate, added to the
+    given grad_Xii's contents); returns [(grad_Xii, grad_Xji)] per edge."""
     lib = _lib.load()
+    if accumulate and outs is None:
+        raise ValueError("accumulate needs the grad_Xii buffers (outs) to add to")
     table, grads = make_bwd_edges(inputs, outs)
     n = len(inputs)
     nbytes = lib.m3s_bwd_batched_workspace_bytes(n)
     ws = _workspace(nbytes, inputs[0].Xii.device, stream)
-    flags = _lib.M3S_BATCH_GRAPH if graph else 0
+    flags = (_lib.M3S_BATCH_GRAPH if graph else 0) | (_lib.M3S_BWD_ACCUMULATE if accumulate else 0)
     st = lib.m3s_match_bwd_batched(table, n, flags, ws.data_ptr(), ws.numel(), _stream(stream))
     _lib.check(lib, "m3s_match_bwd_batched", st)
     return grads

@@ -688,7 +688,9 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
                                  size_t ws_bytes, void* stream) {
     if (!edges) return fail(M3S_ERR_NULL, "edges is NULL");
     if (n_edges < 1 || n_edges > (1 << 20)) return fail(M3S_ERR_SHAPE, "n_edges %d outside [1, 2^20]", n_edges);
-    if (flags & ~(uint32_t)M3S_BATCH_GRAPH) return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
+    if (flags & ~(uint32_t)(M3S_BATCH_GRAPH | M3S_BWD_ACCUMULATE))
+        return fail(M3S_ERR_UNSUPPORTED, "unknown flags 0x%x", flags);
+    const bool zero = !(flags & M3S_BWD_ACCUMULATE);
     std::vector<m3s::BwdEdgeArgs> table((size_t)n_edges);
     int64_t tiles = 0;
     long max_px = 0;
@@ -730,7 +732,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
     const int grid = std::max(1, std::min((int)tiles, g_override.grid > 0 ? g_override.grid : info.cus * 32));
     if ((flags & M3S_BATCH_GRAPH) && st != nullptr) {
         std::string gkey = std::to_string(dev) + "|" + sig + "|" + std::to_string(reinterpret_cast<uintptr_t>(ws)) +
-                           "|" + std::to_string(grid);
+                           "|" + std::to_string(grid) + (zero ? "|z" : "|a");
         hipGraphExec_t exec = nullptr;
         {
             std::lock_guard<std::mutex> lk(g_cache_mu);
@@ -740,7 +742,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
         if (!exec) {
             e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            hipError_t le = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, st);
+            hipError_t le = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, zero, st);
             hipGraph_t graph = nullptr;
             e = hipStreamEndCapture(st, &graph);
             if (le != hipSuccess) { if (graph) hipGraphDestroy(graph); return hip_fail(le, "captured launch"); }
@@ -756,7 +758,7 @@ m3s_status m3s_match_bwd_batched(const m3s_bwd_edge* edges, int32_t n_edges, uin
         m3s::timer_end(st);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     } else {
-        e = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, st);
+        e = m3s::launch_bwd_batched(dtable, n_edges, max_px, (int)tiles, grid, zero, st);
         if (e != hipSuccess) return hip_fail(e, "batched backward launch");
     }
     g_last_error.clear();

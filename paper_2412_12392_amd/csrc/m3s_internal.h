@@ -66,7 +66,7 @@ hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s);
 // tiles with `grid` workgroups (one launch).  max_pixels: the largest H * W of
 // the table.
 hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles, int grid,
-                              hipStream_t s);
+                              bool zero, hipStream_t s);
 
 // Tracking pose solve (m3s_track.hip): workgroups of one iteration launch,
 // workspace bytes, and the launch sequence (init + iters + 1 launches).

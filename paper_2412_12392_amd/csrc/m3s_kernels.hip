@@ -1664,11 +1664,13 @@ hipError_t launch_bwd(const BwdEdgeArgs& B, hipStream_t s) {
 }
 
 hipError_t launch_bwd_batched(const BwdEdgeArgs* table, int n_edges, long max_pixels, int total_tiles, int grid,
-                              hipStream_t s) {
-    timer_begin("batched_bwd_zero", s);
-    const unsigned zx = min(blocks_for(3 * max_pixels / 4 + 1, 256), 1024u);
-    batched_bwd_zero_kernel<<<dim3(zx, (unsigned)n_edges), 256, 0, s>>>(table);
-    timer_end(s);
+                              bool zero, hipStream_t s) {
+    if (zero) {
+        timer_begin("batched_bwd_zero", s);
+        const unsigned zx = min(blocks_for(3 * max_pixels / 4 + 1, 256), 1024u);
+        batched_bwd_zero_kernel<<<dim3(zx, (unsigned)n_edges), 256, 0, s>>>(table);
+        timer_end(s);
+    }
     timer_begin("batched_bwd", s);
     batched_bwd_kernel<<<grid, 256, 0, s>>>(table, n_edges, total_tiles);
     timer_end(s);

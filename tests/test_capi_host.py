@@ -413,7 +413,8 @@ int main(void) {
     cases = [
         (None, 1, 0, (base, 1024), 1),
         ([good], 0, 0, (base, 1024), 2),
-        ([good], 1, 0x4, (base, 1024), 6),
+        ([good], 1, 0x8, (base, 1024), 6),
+        ([good], 1, 0x2, (base, 1024), 6),
         ([_lib.BwdEdge(1, 4, _addr, _addr, _addr, _addr, _addr, 0, _addr, _addr)], 1, 0, (base, 1024), 2),
         ([_lib.BwdEdge(4, 4, 0, _addr, _addr, _addr, _addr, 0, _addr, _addr)], 1, 0, (base, 1024), 1),
         ([_lib.BwdEdge(4, 4, _addr, _addr, _addr, _addr, 0, 0, _addr, _addr)], 1, 0, (base, 1024), 1),

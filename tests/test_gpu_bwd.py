@@ -208,3 +208,54 @@ def test_bwd_batched_matches_per_edge(m3s):
         mj = float(np.abs(gj - oj).max() / np.abs(oj).max())
         print(dict(edge=k, max_rel_dXii=mi, max_rel_dXji=mj))
         assert mi <= 1e-4 and mj <= 1e-4
+
+
+def test_bwd_batched_accumulate(m3s):
+    """M3S_BWD_ACCUMULATE: the batched backward adds its dL/dX^i_i to the
+    buffers' contents (no zeroing launch) and still overwrites dL/dX^j_i.  Into
+    zeroed buffers it equals the plain call up to the order of the fp32 atomics;
+    into buffers holding G0 it gives G0 plus that; two edges sharing one
+    dL/dX^i_i buffer (the same keyframe) sum their gradients; eager and graph."""
+    import torch
+    dims = [(48, 64), (37, 53), (96, 128)]
+    pairs = [synth.make_pair(H, W, 840 + k) for k, (H, W) in enumerate(dims)]
+    inputs = []
+    for k, pr in enumerate(pairs):
+        t = parity.pair_tensors(pr)
+        res = m3s.match(t["Xii"], t["Xji"], t["Dii"], t["Dji"], t["Qii"], t["Qji"], want_xhat=True)
+        rng = np.random.Generator(np.random.PCG64(940 + k))
+        gp = parity.to_dev(rng.normal(size=(pr.H, pr.W, 2)))
+        gx = None if k == 1 else parity.to_dev(rng.normal(size=(pr.H, pr.W, 3)))
+        inputs.append(m3s.BwdEdgeInput(t["Xii"], t["Xji"], res.p, res.valid, gp, gx))
+    ref = m3s.match_backward_batched(inputs, graph=False)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    for graph in (False, True, True):
+        print("case bwd accumulate graph %s" % graph, flush=True)
+        g0 = [parity.to_dev(np.random.Generator(np.random.PCG64(950 + k)).normal(size=(H, W, 3)))
+              for k, (H, W) in enumerate(dims)]
+        outs = [(g.clone(), torch.full_like(g, float("nan"))) for g in g0]
+        with torch.cuda.stream(s):
+            m3s.match_backward_batched(inputs, graph=graph, outs=outs, accumulate=True)
+        s.synchronize()
+        for k, ((ri, rj), (gi, gj)) in enumerate(zip(ref, outs)):
+            assert torch.equal(rj, gj), k
+            want = g0[k] + ri
+            scale = max(float(want.abs().max()), 1e-30)
+            assert float((gi - want).abs().max()) <= 2e-6 * scale, (graph, k)
+        zeros = [(torch.zeros_like(ri), torch.empty_like(rj)) for ri, rj in ref]
+        with torch.cuda.stream(s):
+            m3s.match_backward_batched(inputs, graph=graph, outs=zeros, accumulate=True)
+        s.synchronize()
+        for k, ((ri, _), (gi, _)) in enumerate(zip(ref, zeros)):
+            scale = max(float(ri.abs().max()), 1e-30)
+            assert float((gi - ri).abs().max()) <= 1e-6 * scale, (graph, k)
+    # Two edges of one keyframe into one dL/dX^i_i buffer.
+    shared = torch.zeros_like(ref[0][0])
+    two = [inputs[0], inputs[0]]
+    with torch.cuda.stream(s):
+        m3s.match_backward_batched(two, graph=False, outs=[(shared, torch.empty_like(shared)),
+                                                           (shared, torch.empty_like(shared))], accumulate=True)
+    s.synchronize()
+    scale = max(float(ref[0][0].abs().max()), 1e-30)
+    assert float((shared - 2.0 * ref[0][0]).abs().max()) <= 2e-6 * scale
